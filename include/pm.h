@@ -1,0 +1,154 @@
+/*
+ * pm.h -- C ABI of libpm: products of univariate polynomial matrices over
+ * Z/pZ on one AMD Instinct MI355X (gfx950), by evaluation/interpolation.
+ *
+ * Operation (Hyun, Neiger, Schost, ISSAC 2019, Section 2, "Polynomial matrix
+ * multiplication"): given A (m x n) and B (n x k) whose entries are
+ * polynomials of degree < d over F_p (the set K[x]_d of Section 2,
+ * "Polynomial multiplication"), compute C = A B (m x k, degree < 2d-1):
+ *
+ *   C[c][i][j] = sum_{l<n} sum_{a+b=c} A[a][i][l] * B[b][l][j]  (mod p),
+ *   0 <= c <= 2d-2.
+ *
+ * Method (same section): evaluate A and B at the L-th roots of unity of a
+ * prime q (L = 2^ceil(log2(2d-1))), multiply the m x n and n x k matrices
+ * of values point by point, interpolate back (the number-theoretic
+ * transform; Section 2, "Polynomial multiplication", FFT paragraph).
+ *   * Direct mode: p itself is prime, p < 2^31 and 2^log2(L) divides p-1.
+ *   * CRT mode, for any other modulus p >= 2 (the 3-primes idea of Section 2,
+ *     "Polynomial multiplication" and "Polynomial matrix multiplication"):
+ *     lift inputs to integers in [0, p), compute the integer product modulo
+ *     r word-size NTT primes q_1..q_r with prod q_i > n*d*(p-1)^2, rebuild
+ *     it by the Chinese remainder theorem (Garner) and reduce mod p.
+ * Both modes return the exact product: no rounding, no tolerance.
+ *
+ * Layout (all operands, device memory, coefficient-major: the "polynomial
+ * with matrix coefficients" representation that Section 3 describes after
+ * the PM-IntBasis algorithm): a polynomial matrix with
+ * R x S entries and D coefficients is D consecutive R x S row-major
+ * matrices; element (c, i, j) sits at offset (c*R + i)*S + j.  A holds d*m*n
+ * residues, B holds d*n*k, C receives (2d-1)*m*k.  Inputs must be canonical
+ * residues in [0, p); other values give an unspecified (memory-safe) result;
+ * pm_check_residues tests this on request.  Outputs are canonical.
+ *
+ * Ownership and streams: the caller owns A, B, C, the workspace and the
+ * stream (a hipStream_t passed as void*, NULL for the default stream).
+ * Every pm_mul* call only enqueues work on that stream and returns; results
+ * are valid once the stream has completed.  Buffers must stay alive until
+ * then.  The library keeps per-device tables of roots of unity, built on the
+ * first call that needs a given (prime, length) and reused until the process
+ * ends (this first call copies them synchronously, so make it before any
+ * stream capture).  Calls from several host threads are safe; two calls
+ * that share a workspace must be ordered on one stream.
+ *
+ * Errors: every argument check runs before anything is enqueued; a failed
+ * check returns a negative pm_status and writes nothing.  A device fault is
+ * reported as PM_EDEVICE by pm_sync or by a later call.  No C++ exception
+ * crosses this interface and the library never aborts the process.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pm_status {
+  PM_OK = 0,
+  PM_EINVAL = -1,        /* bad argument: size < 1, NULL pointer, p < 2, overlap */
+  PM_ERANGE = -2,        /* modulus or size outside what this API supports       */
+  PM_ENOMEM = -3,        /* the library could not allocate its tables            */
+  PM_EWORKSPACE = -4,    /* workspace NULL, misaligned or too small              */
+  PM_EDEVICE = -5,       /* a HIP call failed                                    */
+  PM_EUNSUPPORTED = -6,  /* no prime set covers the requested length/bound       */
+  PM_EBUSY = -7          /* reserved for admission control (serving layer)       */
+} pm_status;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* pm_status_str(int status);
+
+/* ABI version of this header; bumped on incompatible change. */
+#define PM_ABI_VERSION 1
+int pm_abi_version(void);
+
+/* Plan of one product, computed on the host without touching the device.
+ * mode: 0 = direct NTT mod p, 1 = CRT over num_primes NTT primes.
+ * pointwise: 0 = VALU Barrett kernel, 1 = int8-MFMA limb kernel. */
+typedef struct pm_plan_info {
+  int32_t mode;
+  int32_t log2_len;          /* L = 2^log2_len evaluation points            */
+  int32_t num_primes;        /* 1 in direct mode                            */
+  int32_t pointwise;
+  uint32_t primes[8];        /* q_1..q_r (primes[0] = p in direct mode)     */
+  uint64_t workspace_bytes;  /* what pm_mul_* needs for this product        */
+} pm_plan_info;
+
+/* Plan the product of an (m x n) by (n x k) matrix of degree < d mod p with
+ * elem_bytes-byte residues (4 or 8).  Host only.  Returns PM_EINVAL on sizes
+ * < 1, PM_ERANGE if p does not fit elem_bytes (p < 2^32 for 4, p < 2^62 for
+ * 8) or if a size product overflows, PM_EUNSUPPORTED if L exceeds 2^24. */
+pm_status pm_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                  int32_t elem_bytes, pm_plan_info* out);
+
+/* Workspace bytes pm_mul_u32 / pm_mul_u64 need for this product. */
+pm_status pm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k,
+                             int32_t d, int32_t elem_bytes, uint64_t* out);
+
+/* C = A B mod p for uint32 residues (p < 2^32).  A: d*m*n, B: d*n*k,
+ * C: (2d-1)*m*k elements, device pointers, 16-byte aligned, C must not
+ * overlap A or B.  workspace: device memory of at least
+ * pm_workspace_bytes(..., 4, ...) bytes, 256-byte aligned, not overlapping
+ * A, B or C; its contents on entry are ignored.  Asynchronous on `stream`. */
+pm_status pm_mul_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                     const uint32_t* A, const uint32_t* B, uint32_t* C,
+                     void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* Same for uint64 residues, any modulus 2 <= p < 2^62 (CRT mode unless p is
+ * an NTT-friendly prime below 2^31). */
+pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                     const uint64_t* A, const uint64_t* B, uint64_t* C,
+                     void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* One product of a batch; the pointers follow the pm_mul_* layout rules. */
+typedef struct pm_product {
+  int32_t m, n, k, d;
+  const void* A;
+  const void* B;
+  void* C;
+} pm_product;
+
+/* Workspace bytes for pm_mul_batched_* over `count` products (host array). */
+pm_status pm_batched_workspace_bytes(uint64_t p, int32_t count,
+                                     const pm_product* prods, int32_t elem_bytes,
+                                     uint64_t* out);
+
+/* All `count` products, each C = A B mod p, in one persistent launch per
+ * transform phase set (see the implementation notes in the source).  `prods`
+ * is a host array read during the call only.  Outputs are identical, byte
+ * for byte, to one pm_mul_* call per product.  Asynchronous on `stream`. */
+pm_status pm_mul_batched_u32(uint32_t p, int32_t count, const pm_product* prods,
+                             void* workspace, uint64_t workspace_bytes,
+                             void* stream);
+pm_status pm_mul_batched_u64(uint64_t p, int32_t count, const pm_product* prods,
+                             void* workspace, uint64_t workspace_bytes,
+                             void* stream);
+
+/* Count the elements of X (count residues of elem_bytes bytes, device
+ * memory) that are >= p; the count is written to *n_bad (host pointer) after
+ * the stream is synchronised.  workspace: at least 8 bytes of device memory.
+ * Not on the hot path: an opt-in input check. */
+pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count,
+                            int32_t elem_bytes, uint64_t* n_bad,
+                            void* workspace, void* stream);
+
+/* Wait for `stream` and report any device error raised by earlier calls. */
+pm_status pm_sync(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

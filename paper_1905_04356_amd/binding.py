@@ -1,0 +1,148 @@
+"""ctypes binding of libpm (include/pm.h): the same entry points, same names.
+
+Only argument marshalling happens here; every step of a product runs in the
+HIP kernels of libpm.so. PyTorch supplies device memory and streams. If the
+library is missing the calls raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpm.so")
+
+PM_OK = 0
+PM_EINVAL = -1
+PM_ERANGE = -2
+PM_ENOMEM = -3
+PM_EWORKSPACE = -4
+PM_EDEVICE = -5
+PM_EUNSUPPORTED = -6
+PM_EBUSY = -7
+
+# Every symbol include/pm.h declares.
+EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
+           "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
+           "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_check_residues",
+           "pm_sync")
+
+
+class PmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class pm_plan_info(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("log2_len", ctypes.c_int32),
+                ("num_primes", ctypes.c_int32), ("pointwise", ctypes.c_int32),
+                ("primes", ctypes.c_uint32 * 8), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class pm_product(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpm.so (built by paper_1905_04356_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1905_04356_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, u32, u64, vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+    L.pm_status_str.argtypes = [ctypes.c_int]
+    L.pm_status_str.restype = ctypes.c_char_p
+    L.pm_abi_version.argtypes = []
+    L.pm_abi_version.restype = ctypes.c_int
+    L.pm_plan.argtypes = [u64, i32, i32, i32, i32, i32, ctypes.POINTER(pm_plan_info)]
+    L.pm_workspace_bytes.argtypes = [u64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_mul_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
+    L.pm_mul_u64.argtypes = [u64, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
+    L.pm_batched_workspace_bytes.argtypes = [u64, i32, ctypes.POINTER(pm_product), i32,
+                                             ctypes.POINTER(u64)]
+    L.pm_mul_batched_u32.argtypes = [u32, i32, ctypes.POINTER(pm_product), vp, u64, vp]
+    L.pm_mul_batched_u64.argtypes = [u64, i32, ctypes.POINTER(pm_product), vp, u64, vp]
+    L.pm_check_residues.argtypes = [u64, vp, u64, i32, ctypes.POINTER(u64), vp, vp]
+    L.pm_sync.argtypes = [vp]
+    for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
+                 "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
+                 "pm_check_residues", "pm_sync"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return lib().pm_status_str(int(status)).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != PM_OK:
+        raise PmError(status, what)
+
+
+# ---- thin wrappers with the C names (raw pointers as ints) -----------------
+
+def pm_plan(p: int, m: int, n: int, k: int, d: int, elem_bytes: int) -> pm_plan_info:
+    info = pm_plan_info()
+    _check(lib().pm_plan(p, m, n, k, d, elem_bytes, ctypes.byref(info)), "pm_plan")
+    return info
+
+
+def pm_workspace_bytes(p: int, m: int, n: int, k: int, d: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_workspace_bytes(p, m, n, k, d, elem_bytes, ctypes.byref(out)),
+           "pm_workspace_bytes")
+    return out.value
+
+
+def pm_mul_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
+
+
+def pm_mul_u64(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_u64(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
+
+
+def products_array(prods) -> ctypes.Array:
+    """(m, n, k, d, A_ptr, B_ptr, C_ptr) tuples -> pm_product[count]."""
+    arr = (pm_product * max(1, len(prods)))()
+    for i, (m, n, k, d, a, b, c) in enumerate(prods):
+        arr[i] = pm_product(m, n, k, d, a, b, c)
+    return arr
+
+
+def pm_batched_workspace_bytes(p: int, prods_arr, count: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_batched_workspace_bytes(p, count, prods_arr, elem_bytes,
+                                            ctypes.byref(out)), "pm_batched_workspace_bytes")
+    return out.value
+
+
+def pm_mul_batched_u32(p, count, prods_arr, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_batched_u32(p, count, prods_arr, ws, ws_bytes, stream)
+
+
+def pm_mul_batched_u64(p, count, prods_arr, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_batched_u64(p, count, prods_arr, ws, ws_bytes, stream)
+
+
+def pm_check_residues(p: int, x_ptr: int, count: int, elem_bytes: int, ws_ptr: int,
+                      stream) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_check_residues(p, x_ptr, count, elem_bytes, ctypes.byref(out), ws_ptr,
+                                   stream), "pm_check_residues")
+    return out.value
+
+
+def pm_sync(stream) -> None:
+    _check(lib().pm_sync(stream), "pm_sync")

@@ -1,0 +1,73 @@
+// pm_kernels.h -- launch descriptors shared by the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm_plan.h"
+
+namespace pm {
+
+// Number-theoretic transforms of E = R*S polynomials (entries) at once.
+// Forward: input coefficient-major X[c][e] (c < nin, zero beyond) of TIn,
+// reduced mod each prime; output point-major Xhat[t][e] (u32), t < L, in the
+// bit-reversed order the in-place decimation-in-frequency passes produce.
+// Inverse: input point-major Chat[t][e]; output coefficient-major
+// C[c][e] for c < nin (the L^{-1} factor is applied by the pointwise kernel).
+struct NttLaunch {
+  int logL;
+  int npass;
+  int stages[kMaxPasses];
+  int stride_log[kMaxPasses];
+  uint32_t tw_off[kMaxPasses];
+  int nin;                   // forward: coefficients read; inverse: written
+  int E;                     // entries per point
+  int eb_log;                // log2(entries per workgroup)
+  int lds_stride;            // 32-bit words between entries in LDS
+  uint64_t in_prime_stride;  // elements between primes' input buffers
+  uint64_t out_prime_stride; // elements between primes' output buffers
+  const void* in;
+  void* out;
+  PrimeConst pc[kMaxPrimes];
+};
+
+// Pointwise products: for every point t and prime, Chat_t = L^{-1} Ahat_t Bhat_t
+// (m x n times n x k), all point-major u32.
+struct PointwiseLaunch {
+  int m, n, k, L;
+  uint64_t prime_stride;     // elements between primes' eval sets
+  const uint32_t* ahat;
+  const uint32_t* bhat;
+  uint32_t* chat;
+  PrimeConst pc[kMaxPrimes];
+};
+
+// Chinese remaindering of r residue arrays (u32, `count` each, stride
+// `prime_stride` elements) into residues mod p.
+struct CrtLaunch {
+  int r;
+  uint64_t count;
+  uint64_t prime_stride;
+  const uint32_t* cq;
+  void* out;
+  uint64_t p;
+  double pinv;
+  uint32_t q[kMaxPrimes];
+  uint64_t mu[kMaxPrimes];
+  uint32_t inv[kMaxPrimes][kMaxPrimes];    // q_j^{-1} mod q_i (j < i)
+  uint32_t inv_p[kMaxPrimes][kMaxPrimes];  // Shoup companions
+  uint64_t radix_mod_p[kMaxPrimes];        // prod_{j<i} q_j mod p
+};
+
+// Host launchers (return hipError_t as int).
+int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
+                   hipStream_t s);
+int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s);
+int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
+int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s);
+int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_bytes,
+                          unsigned long long* counter, hipStream_t s);
+
+// Fill the launch descriptor of a transform for (logL, E, nin).
+void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin);
+
+}  // namespace pm

@@ -1,0 +1,277 @@
+// pm_plan.cpp -- host planning: choice of transform prime(s), transform
+// length, pass structure, tables of roots of unity, workspace layout.
+//
+// Method (Hyun, Neiger, Schost, ISSAC 2019, Section 2, "Polynomial matrix
+// multiplication"): for FFT primes, evaluate and interpolate at roots of
+// unity; for other moduli, lift the product to Z[x] and compute it modulo a
+// few FFT primes ("3-primes" multiplication, Section 2, "Polynomial
+// multiplication").  The product of two entries of degree < d has 2d-1
+// coefficients, so L = 2^ceil(log2(2d-1)) points determine it.
+#include "pm_plan.h"
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pm.h"
+
+namespace pm {
+
+typedef unsigned __int128 u128;
+
+uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  while (e) {
+    if (e & 1) r = (uint64_t)((u128)r * b % m);
+    b = (uint64_t)((u128)b * b % m);
+    e >>= 1;
+  }
+  return r;
+}
+
+int v2_u64(uint64_t x) {
+  if (x == 0) return 64;
+  int v = 0;
+  while ((x & 1) == 0) { x >>= 1; ++v; }
+  return v;
+}
+
+// Deterministic Miller-Rabin for 64-bit n (bases: the primes up to 37).
+bool is_prime_u64(uint64_t n) {
+  static const uint64_t B[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return false;
+  for (uint64_t b : B)
+    if (n % b == 0) return n == b;
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) { d >>= 1; ++s; }
+  for (uint64_t b : B) {
+    uint64_t x = powmod_u64(b, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < s && comp; ++i) {
+      x = (uint64_t)((u128)x * x % n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+// Primes q < 2^31 with 2^24 | q-1, largest first.  Each supports transforms
+// up to length 2^24, above the 2^15 this library runs in LDS.
+static const uint32_t kCrtPrimes[] = {
+    2130706433u,  // 127 * 2^24 + 1
+    2113929217u,  //  63 * 2^25 + 1
+    2013265921u,  //  15 * 2^27 + 1
+    1811939329u,  //  27 * 2^26 + 1
+    1711276033u,  //  51 * 2^25 + 1
+    1224736769u,  //  73 * 2^24 + 1
+    1107296257u,  //  33 * 2^25 + 1
+    754974721u,   //  45 * 2^24 + 1
+    469762049u,   //   7 * 2^26 + 1
+    167772161u,   //   5 * 2^25 + 1
+};
+
+// Smallest generator of (Z/qZ)^*.
+static uint32_t primitive_root(uint32_t q) {
+  std::vector<uint64_t> f;
+  uint64_t x = q - 1;
+  for (uint64_t t = 2; t * t <= x; ++t) {
+    if (x % t == 0) {
+      f.push_back(t);
+      while (x % t == 0) x /= t;
+    }
+  }
+  if (x > 1) f.push_back(x);
+  for (uint32_t g = 2; g < q; ++g) {
+    bool ok = true;
+    for (uint64_t t : f)
+      if (powmod_u64(g, (q - 1) / t, q) == 1) { ok = false; break; }
+    if (ok) return g;
+  }
+  return 0;
+}
+
+PassPlan make_pass_plan(int logL) {
+  PassPlan P{};
+  P.logL = logL;
+  P.npass = (logL + 4) / 5;  // at most 5 stages (radix 32) per pass
+  int s = logL;
+  uint32_t off = 0;
+  for (int i = 0; i < P.npass; ++i) {
+    int base = logL / P.npass, extra = logL % P.npass;
+    P.stages[i] = base + (i < extra ? 1 : 0);
+    s -= P.stages[i];
+    P.stride_log[i] = s;
+    P.tw_off[i] = off;
+    off += (1u << s) * ((1u << P.stages[i]) - 1);
+  }
+  P.tw_count = off;
+  return P;
+}
+
+// Exact multi-precision helpers for the CRT bound (little-endian 32-bit limbs).
+typedef std::vector<uint32_t> Big;
+static Big big_from(uint64_t v) { return Big{(uint32_t)v, (uint32_t)(v >> 32)}; }
+static Big big_mul(const Big& a, uint64_t b) {
+  Big r(a.size() + 2, 0);
+  uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  for (int part = 0; part < 2; ++part) {
+    uint64_t bb = part ? b1 : b0, carry = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+      u128 t = (u128)a[i] * bb + r[i + part] + carry;
+      r[i + part] = (uint32_t)t;
+      carry = (uint64_t)(t >> 32);
+    }
+    for (size_t i = a.size() + part; carry && i < r.size(); ++i) {
+      uint64_t t = (uint64_t)r[i] + carry;
+      r[i] = (uint32_t)t;
+      carry = t >> 32;
+    }
+  }
+  while (r.size() > 1 && r.back() == 0) r.pop_back();
+  return r;
+}
+static int big_cmp(const Big& a, const Big& b) {
+  size_t n = a.size() > b.size() ? a.size() : b.size();
+  for (size_t i = n; i-- > 0;) {
+    uint32_t x = i < a.size() ? a[i] : 0, y = i < b.size() ? b[i] : 0;
+    if (x != y) return x < y ? -1 : 1;
+  }
+  return 0;
+}
+
+static int ceil_log2(uint64_t x) {
+  int l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out) {
+  if (!out) return PM_EINVAL;
+  if (elem_bytes != 4 && elem_bytes != 8) return PM_EINVAL;
+  if (m < 1 || n < 1 || k < 1 || d < 1) return PM_EINVAL;
+  if (p < 2) return PM_EINVAL;
+  if (elem_bytes == 4 && p > 0xFFFFFFFFull) return PM_ERANGE;
+  if (elem_bytes == 8 && p >= (1ull << 62)) return PM_ERANGE;
+  const int logL = ceil_log2(2ull * (uint64_t)d - 1);
+  if (logL > kMaxLogLen) return PM_EUNSUPPORTED;
+  const uint64_t L = 1ull << logL;
+  const uint64_t lim = 1ull << 32;
+  const uint64_t mn = (uint64_t)m * n, nk = (uint64_t)n * k, mk = (uint64_t)m * k;
+  if ((uint64_t)d * mn >= lim || (uint64_t)d * nk >= lim || (2ull * d - 1) * mk >= lim ||
+      L * mn >= lim || L * nk >= lim || L * mk >= lim)
+    return PM_ERANGE;
+
+  Plan P{};
+  P.p = p; P.m = m; P.n = n; P.k = k; P.d = d; P.elem_bytes = elem_bytes;
+  P.logL = logL;
+  if (p >= 3 && p < (1ull << 31) && is_prime_u64(p) && v2_u64(p - 1) >= logL) {
+    P.mode = 0;
+    P.r = 1;
+    P.q[0] = (uint32_t)p;
+  } else {
+    // Integer coefficients of the lifted product lie in [0, n*d*(p-1)^2].
+    Big bound = big_mul(big_mul(big_from(p - 1), p - 1), (uint64_t)n * d);
+    Big prod = big_from(1);
+    P.mode = 1;
+    P.r = 0;
+    for (uint32_t q : kCrtPrimes) {
+      if (v2_u64(q - 1) < logL) continue;
+      if (P.r == kMaxPrimes) return PM_EUNSUPPORTED;
+      P.q[P.r++] = q;
+      prod = big_mul(prod, q);
+      if (big_cmp(prod, bound) > 0) break;
+    }
+    if (big_cmp(prod, bound) <= 0) return PM_EUNSUPPORTED;
+  }
+  P.pointwise = 0;
+  uint64_t off = 0;
+  P.off_ahat = off; off = align_up(off + 4 * L * mn, 256);
+  P.off_bhat = off; off = align_up(off + 4 * L * nk, 256);
+  P.off_chat = off; off = align_up(off + 4 * L * mk, 256);
+  P.prime_stride = off;
+  P.off_cq = P.prime_stride * (uint64_t)P.r;
+  P.ws_bytes = P.off_cq;
+  if (P.mode == 1) P.ws_bytes = align_up(P.off_cq + 4ull * P.r * (2ull * d - 1) * mk, 256);
+  *out = P;
+  return PM_OK;
+}
+
+// ---- device tables --------------------------------------------------------
+
+namespace {
+struct TableEntry {
+  Tw* dev = nullptr;
+  uint32_t linv = 0, linv_p = 0;
+};
+std::mutex g_mu;
+std::map<std::tuple<int, uint32_t, int>, TableEntry> g_tables;
+}  // namespace
+
+static uint32_t shoup_of(uint32_t w, uint32_t q) {
+  return (uint32_t)(((uint64_t)w << 32) / q);
+}
+
+int get_prime_const(uint32_t q, int logL, PrimeConst* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
+  const PassPlan PP = make_pass_plan(logL);
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto key = std::make_tuple(dev, q, logL);
+  auto it = g_tables.find(key);
+  if (it == g_tables.end()) {
+    const uint64_t L = 1ull << logL;
+    const uint32_t g = primitive_root(q);
+    if (g == 0 || v2_u64(q - 1) < logL) return PM_EUNSUPPORTED;
+    const uint64_t w = powmod_u64(g, (q - 1) / L, q);
+    const uint64_t winv = powmod_u64(w, L - 1, q);
+    std::vector<uint32_t> pw(L), pwi(L);
+    uint64_t a = 1, b = 1;
+    for (uint64_t e = 0; e < L; ++e) {
+      pw[e] = (uint32_t)a; pwi[e] = (uint32_t)b;
+      a = a * w % q; b = b * winv % q;
+    }
+    const size_t cnt = PP.tw_count ? PP.tw_count : 1;
+    std::vector<Tw> host(2 * cnt);
+    for (int i = 0; i < PP.npass; ++i) {
+      const int r = PP.stages[i], s = PP.stride_log[i];
+      const uint32_t S = 1u << s, R = 1u << r;
+      for (uint32_t j = 0; j < S; ++j)
+        for (int v = 0; v < r; ++v)
+          for (uint32_t u = 0; u < (1u << v); ++u) {
+            // stage of half-size h = S * 2^v: exponent (j + u*S) * L / (2h)
+            uint64_t e = (uint64_t)(j + u * S) << (logL - s - v - 1);
+            size_t idx = PP.tw_off[i] + (size_t)j * (R - 1) + ((1u << v) - 1) + u;
+            host[idx] = Tw{pw[e], shoup_of(pw[e], q)};
+            host[cnt + idx] = Tw{pwi[e], shoup_of(pwi[e], q)};
+          }
+    }
+    TableEntry T;
+    if (hipMalloc(&T.dev, sizeof(Tw) * host.size()) != hipSuccess) return PM_ENOMEM;
+    if (hipMemcpy(T.dev, host.data(), sizeof(Tw) * host.size(), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      (void)hipFree(T.dev);
+      return PM_EDEVICE;
+    }
+    T.linv = (uint32_t)powmod_u64(L % q, q - 2, q);
+    T.linv_p = shoup_of(T.linv, q);
+    it = g_tables.emplace(key, T).first;
+  }
+  const size_t cnt = PP.tw_count ? PP.tw_count : 1;
+  out->q = q;
+  out->linv = it->second.linv;
+  out->linv_p = it->second.linv_p;
+  out->pad = 0;
+  out->mu = ~0ull / q;
+  out->tw_fwd = it->second.dev;
+  out->tw_inv = it->second.dev + cnt;
+  return PM_OK;
+}
+
+}  // namespace pm

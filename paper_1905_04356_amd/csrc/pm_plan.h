@@ -1,0 +1,74 @@
+// pm_plan.h -- host-side planning for libpm: moduli, transform lengths,
+// tables of roots of unity, workspace layout.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pm {
+
+constexpr int kMaxPrimes = 8;
+constexpr int kMaxLogLen = 15;     // transforms are LDS-resident: L <= 2^15
+constexpr int kMaxPasses = 6;
+
+// Twiddle pair for Shoup multiplication: w and floor(w * 2^32 / q).
+struct Tw {
+  uint32_t w, wp;
+};
+
+// Pass structure of a length-2^logL transform: the forward (decimation in
+// frequency) transform runs stages in passes of r_0, r_1, ... radix-2
+// stages; pass i works on groups of 2^r_i elements at stride S_i, with
+// S_0 = L / 2^r_0 and S_{i+1} = S_i / 2^r_{i+1} (the last stride is 1).  The
+// inverse (decimation in time) runs the same passes in reverse order.
+struct PassPlan {
+  int logL;
+  int npass;
+  int stages[kMaxPasses];      // forward order
+  int stride_log[kMaxPasses];  // log2 S_i, forward order
+  uint32_t tw_off[kMaxPasses]; // offset (in Tw units) of pass i's table
+  uint32_t tw_count;           // total Tw entries of one direction
+};
+
+PassPlan make_pass_plan(int logL);
+
+// Per-prime constants shared by all kernels.
+struct PrimeConst {
+  uint32_t q;
+  uint32_t linv, linv_p;   // L^{-1} mod q and its Shoup companion
+  uint32_t pad;
+  uint64_t mu;             // floor((2^64-1)/q) for Barrett reduction
+  const Tw* tw_fwd;        // device: forward tables (PassPlan order)
+  const Tw* tw_inv;        // device: inverse tables (same indexing, w^-1)
+};
+
+struct Plan {
+  int mode;              // 0 direct, 1 CRT
+  int logL;
+  int r;                 // number of primes
+  uint32_t q[kMaxPrimes];
+  int pointwise;         // 0 VALU, 1 MFMA
+  int m, n, k, d;
+  uint64_t p;
+  int elem_bytes;
+  // workspace layout (bytes, from the workspace base)
+  uint64_t off_ahat, off_bhat, off_chat;  // per-prime stride below
+  uint64_t prime_stride;                  // bytes between primes' eval sets
+  uint64_t off_cq;                        // CRT residues: r x (2d-1) x m x k u32
+  uint64_t ws_bytes;
+};
+
+// Status codes mirror pm_status in pm.h.
+int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out);
+
+// Host number theory (the library's own; the test oracle has separate code).
+bool is_prime_u64(uint64_t n);
+uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t m);
+int v2_u64(uint64_t x);
+
+// Device tables for (q, logL) on the current device: built on first use,
+// cached for the life of the process.  Returns 0 or a pm_status.
+int get_prime_const(uint32_t q, int logL, PrimeConst* out);
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace pm

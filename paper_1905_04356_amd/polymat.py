@@ -1,0 +1,108 @@
+"""Torch-facing helpers over the C ABI: allocate outputs and workspaces with
+PyTorch, pass raw pointers and the current stream to libpm.
+
+Tensors are coefficient-major: A has shape (d, m, n), B (d, n, k), and the
+product C has shape (2d-1, m, k), dtype torch.uint32 (p < 2^32) or
+torch.uint64 (p < 2^62), on a GPU device.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as _b
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _elem_bytes(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint32:
+        return 4
+    if t.dtype == torch.uint64:
+        return 8
+    raise TypeError(f"expected torch.uint32 or torch.uint64 residues, got {t.dtype}")
+
+
+class Workspace:
+    """A growable device byte buffer reused across calls on one stream."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device or "cuda")
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _workspace(device) -> Workspace:
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def plan(p: int, m: int, n: int, k: int, d: int, elem_bytes: int = 4):
+    return _b.pm_plan(p, m, n, k, d, elem_bytes)
+
+
+def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+        workspace: Workspace | None = None, stream=None) -> torch.Tensor:
+    """C = A B mod p on the GPU (asynchronous on `stream`)."""
+    if A.dim() != 3 or B.dim() != 3:
+        raise ValueError("A and B must be (d, rows, cols)")
+    d, m, n = A.shape
+    d2, n2, k = B.shape
+    if d2 != d or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    eb = _elem_bytes(A)
+    if B.dtype != A.dtype:
+        raise TypeError("A and B must have the same dtype")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be GPU tensors")
+    A = A.contiguous()
+    B = B.contiguous()
+    if out is None:
+        out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
+    ws_bytes = _b.pm_workspace_bytes(p, m, n, k, d, eb)
+    ws = (workspace or _workspace(A.device)).get(ws_bytes)
+    fn = _b.pm_mul_u32 if eb == 4 else _b.pm_mul_u64
+    st = fn(p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_mul")
+    return out
+
+
+def mul_batched(p: int, As, Bs, outs=None, workspace: Workspace | None = None,
+                stream=None):
+    """[A_i B_i mod p] for lists of tensors, in one batched call."""
+    if len(As) != len(Bs):
+        raise ValueError("As and Bs differ in length")
+    if not As:
+        return []
+    eb = _elem_bytes(As[0])
+    if outs is None:
+        outs = [torch.empty((2 * A.shape[0] - 1, A.shape[1], B.shape[2]), dtype=A.dtype,
+                            device=A.device) for A, B in zip(As, Bs)]
+    prods = []
+    for A, B, C in zip(As, Bs, outs):
+        d, m, n = A.shape
+        if B.shape[0] != d or B.shape[1] != n or _elem_bytes(B) != eb or _elem_bytes(A) != eb:
+            raise ValueError("inconsistent batch member")
+        prods.append((m, n, B.shape[2], d, A.data_ptr(), B.data_ptr(), C.data_ptr()))
+    arr = _b.products_array(prods)
+    need = _b.pm_batched_workspace_bytes(p, arr, len(prods), eb)
+    ws = (workspace or _workspace(As[0].device)).get(need)
+    fn = _b.pm_mul_batched_u32 if eb == 4 else _b.pm_mul_batched_u64
+    st = fn(p, len(prods), arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_mul_batched")
+    return outs

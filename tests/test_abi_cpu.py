@@ -1,0 +1,140 @@
+"""C-ABI library: loads, exports every declared symbol, plans correctly, and
+rejects bad arguments before touching a device. CPU only (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1905_04356_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions() -> list[str]:
+    text = open(os.path.join(ROOT, "include", "pm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = header_functions()
+    assert names, "no declarations parsed"
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B.EXPORTS)
+    assert L.pm_abi_version() == 1
+    assert B.status_str(B.PM_EWORKSPACE).startswith("PM_EWORKSPACE")
+
+
+def crt_bound(p, n, d):
+    return n * d * (p - 1) ** 2
+
+
+def test_plan_direct_mode():
+    info = B.pm_plan(998244353, 8, 8, 8, 256, 4)
+    assert (info.mode, info.log2_len, info.num_primes) == (0, 9, 1)
+    assert info.primes[0] == 998244353
+    info = B.pm_plan(2013265921, 64, 64, 32, 4096, 4)
+    assert (info.mode, info.log2_len, info.num_primes) == (0, 13, 1)
+    # workspace: three u32 evaluation sets of L points
+    L = 8192
+    assert info.workspace_bytes >= 4 * L * (64 * 64 + 64 * 32 + 64 * 32)
+    # d = 1: a single point
+    info = B.pm_plan(998244353, 3, 3, 3, 1, 4)
+    assert (info.mode, info.log2_len) == (0, 0)
+
+
+@pytest.mark.parametrize("p,n,d,eb", [
+    (1152921504606847009, 32, 2048, 8),   # 60-bit modulus
+    ((1 << 62) - 57, 128, 16384, 8),
+    (4294967291, 64, 4096, 4),            # largest 32-bit prime: no 2^13 roots
+    (998244353, 8, 1 << 15, 4),           # 2^23 | p-1 but L = 2^16 > LDS limit
+    (2, 3, 100, 4),
+    (1 << 40, 5, 77, 8),                  # composite modulus
+])
+def test_plan_crt_uses_the_fewest_primes(p, n, d, eb):
+    try:
+        info = B.pm_plan(p, 4, n, 4, d, eb)
+    except B.PmError as e:
+        assert e.status == B.PM_EUNSUPPORTED and 2 * d - 1 > (1 << 15)
+        return
+    assert info.mode == 1
+    qs = [info.primes[i] for i in range(info.num_primes)]
+    assert len(set(qs)) == len(qs)
+    for q in qs:
+        v2 = ((q - 1) & -(q - 1)).bit_length() - 1
+        assert v2 >= info.log2_len and q < (1 << 31)
+    bound = crt_bound(p, n, d)
+    assert math.prod(qs) > bound
+    assert math.prod(qs[:-1]) <= bound  # no prime is superfluous
+
+
+def test_plan_length_is_next_power_of_two():
+    for d in (1, 2, 3, 4, 5, 16, 17, 33, 4096, 4097, 8192):
+        info = B.pm_plan(2013265921, 2, 2, 2, d, 4)
+        assert info.log2_len == (2 * d - 2).bit_length() if d > 1 else info.log2_len == 0
+        assert (1 << info.log2_len) >= 2 * d - 1 > (1 << info.log2_len) // 2 or d == 1
+
+
+@pytest.mark.parametrize("args,status", [
+    ((1, 2, 2, 2, 4, 4), B.PM_EINVAL),             # p < 2
+    ((97, 0, 2, 2, 4, 4), B.PM_EINVAL),            # m = 0
+    ((97, 2, 2, 2, 0, 4), B.PM_EINVAL),            # d = 0
+    ((97, 2, -1, 2, 4, 4), B.PM_EINVAL),
+    ((97, 2, 2, 2, 4, 2), B.PM_EINVAL),            # elem_bytes
+    ((1 << 32, 2, 2, 2, 4, 4), B.PM_ERANGE),       # p too big for u32
+    ((1 << 62, 2, 2, 2, 4, 8), B.PM_ERANGE),       # p too big for u64
+    ((97, 65536, 65536, 2, 4, 4), B.PM_ERANGE),    # size overflow
+    ((998244353, 2, 2, 2, 1 << 20, 4), B.PM_EUNSUPPORTED),
+])
+def test_plan_rejects(args, status):
+    with pytest.raises(B.PmError) as e:
+        B.pm_plan(*args)
+    assert e.value.status == status
+
+
+def test_mul_argument_checks_fail_before_device_work():
+    L = B.lib()
+    A, Bp, C, WS = 1 << 20, 2 << 20, 3 << 20, 64 << 20  # never dereferenced
+    need = B.pm_workspace_bytes(998244353, 4, 4, 4, 16, 4)
+    cases = [
+        ((998244353, 4, 4, 4, 16, 0, Bp, C, WS, need, None), B.PM_EINVAL),     # NULL A
+        ((998244353, 4, 4, 4, 16, A + 4, Bp, C, WS, need, None), B.PM_EINVAL),  # misaligned
+        ((998244353, 4, 4, 4, 16, A, Bp, A + 64, WS, need, None), B.PM_EINVAL),  # C overlaps A
+        ((998244353, 4, 4, 4, 16, A, Bp, C, 0, need, None), B.PM_EWORKSPACE),
+        ((998244353, 4, 4, 4, 16, A, Bp, C, WS + 16, need, None), B.PM_EWORKSPACE),
+        ((998244353, 4, 4, 4, 16, A, Bp, C, WS, need - 1, None), B.PM_EWORKSPACE),
+        ((998244353, 4, 4, 4, 16, A, Bp, C, A, need, None), B.PM_EINVAL),       # ws overlaps A
+        ((998244353, 0, 4, 4, 16, A, Bp, C, WS, need, None), B.PM_EINVAL),
+    ]
+    for args, status in cases:
+        assert L.pm_mul_u32(*args) == status, args
+    assert L.pm_mul_u64(1 << 62, 4, 4, 4, 16, A, Bp, C, WS, need, None) == B.PM_ERANGE
+
+
+def test_batched_argument_checks():
+    A, Bp, C = 1 << 20, 2 << 20, 3 << 20
+    arr = B.products_array([(4, 4, 4, 16, A, Bp, C), (8, 4, 2, 100, A, Bp, C + (1 << 16))])
+    need = B.pm_batched_workspace_bytes(998244353, arr, 2, 4)
+    one = B.pm_workspace_bytes(998244353, 4, 4, 4, 16, 4)
+    two = B.pm_workspace_bytes(998244353, 8, 4, 2, 100, 4)
+    assert need >= one + two
+    L = B.lib()
+    assert L.pm_mul_batched_u32(998244353, 2, arr, 64 << 20, need - 1, None) == B.PM_EWORKSPACE
+    assert L.pm_mul_batched_u32(998244353, -1, arr, 64 << 20, need, None) == B.PM_EINVAL
+    assert L.pm_mul_batched_u32(998244353, 0, arr, 64 << 20, need, None) == B.PM_OK
+    bad = B.products_array([(4, 4, 4, 0, A, Bp, C)])
+    with pytest.raises(B.PmError):
+        B.pm_batched_workspace_bytes(998244353, bad, 1, 4)
+
+
+def test_check_residues_rejects_bad_arguments():
+    L = B.lib()
+    out = ctypes.c_uint64(0)
+    assert L.pm_check_residues(97, 0, 10, 4, ctypes.byref(out), 1 << 20, None) == B.PM_EINVAL
+    assert L.pm_check_residues(97, 1 << 20, 10, 3, ctypes.byref(out), 1 << 20, None) == B.PM_EINVAL

@@ -1,0 +1,179 @@
+"""GPU parity: libpm (HIP kernels through the C ABI) against the CPU oracle.
+
+Exact arithmetic, so the bar is bit-exact equality everywhere. Small sizes
+compare every coefficient with the oracle's full schoolbook product; the
+full-size configurations compare seeded whole output entries one by one plus
+random-point and Freivalds checks over all outputs.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1905_04356_amd import binding as Bd  # noqa: E402
+from paper_1905_04356_amd import inputs as I  # noqa: E402
+from paper_1905_04356_amd import polymat  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+P30 = 998244353
+P31 = 2013265921
+P32 = 4294967291          # largest prime below 2^32: not NTT-friendly
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tensors(p, m, n, k, d, seed, dtype=np.uint32, product=0):
+    A = I.polymat(seed, product, I.TENSOR_A, p, d, m, n, dtype)
+    B = I.polymat(seed, product, I.TENSOR_B, p, d, n, k, dtype)
+    return A, B
+
+
+def gpu_mul(p, A, B):
+    tA = torch.from_numpy(A).cuda()
+    tB = torch.from_numpy(B).cuda()
+    tC = polymat.mul(p, tA, tB)
+    torch.cuda.synchronize()
+    return tC.cpu().numpy()
+
+
+def full_check(p, m, n, k, d, seed=0, dtype=np.uint32):
+    say(f"[parity] p={p} m={m} n={n} k={k} d={d} seed={seed} dtype={np.dtype(dtype).name}")
+    A, B = tensors(p, m, n, k, d, seed, dtype)
+    C = gpu_mul(p, A, B)
+    ref = O.polymatmul(p, A, B)
+    assert C.shape == ref.shape
+    assert C.dtype == dtype
+    bad = np.argwhere(C.astype(np.uint64) != ref)
+    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+
+
+def test_config1_full_oracle():
+    """8x8 . 8x8, d = 256, p = 998244353: every coefficient."""
+    full_check(P30, 8, 8, 8, 256, seed=1)
+
+
+SMALL = [
+    (1, 1, 1, 1), (3, 2, 5, 1), (2, 3, 2, 2), (1, 1, 1, 3), (5, 7, 3, 17),
+    (4, 4, 4, 33), (2, 3, 1, 100), (16, 16, 16, 64), (7, 5, 9, 129),
+    (8, 12, 4, 257), (3, 3, 3, 1000), (1, 2, 1, 4097), (2, 1, 3, 2049),
+    (1, 1, 1, 8193), (1, 1, 2, 16384),
+]
+
+
+@pytest.mark.parametrize("m,n,k,d", SMALL)
+@pytest.mark.parametrize("p", [P30, P31])
+def test_direct_mode_small(p, m, n, k, d):
+    full_check(p, m, n, k, d, seed=2)
+
+
+@pytest.mark.parametrize("m,n,k,d", [(1, 1, 1, 1), (3, 2, 5, 7), (4, 4, 4, 33),
+                                     (2, 5, 3, 300), (1, 1, 1, 4097)])
+@pytest.mark.parametrize("p,dtype", [(P32, np.uint32), (97, np.uint32), (2, np.uint32),
+                                     (1 << 31, np.uint32),
+                                     (1152921504606846883, np.uint64),
+                                     ((1 << 62) - 57, np.uint64), (P31, np.uint64)])
+def test_crt_and_u64_small(p, dtype, m, n, k, d):
+    full_check(p, m, n, k, d, seed=3, dtype=dtype)
+
+
+@pytest.mark.parametrize("p,dtype", [(P30, np.uint32), (P31, np.uint32), (P32, np.uint32),
+                                     ((1 << 62) - 57, np.uint64)])
+def test_all_p_minus_one_hits_the_bound(p, dtype):
+    """(p-1)^2 = 1 mod p, and over Z each coefficient is exactly the bound
+    n*min(c+1, 2d-1-c)*(p-1)^2 used to size the prime set."""
+    m, n, k, d = 3, 8, 2, 64
+    say(f"[parity] all p-1 p={p}")
+    A = np.full((d, m, n), p - 1, dtype=dtype)
+    B = np.full((d, n, k), p - 1, dtype=dtype)
+    C = gpu_mul(p, A, B)
+    want = np.array([n * min(c + 1, 2 * d - 1 - c) % p for c in range(2 * d - 1)],
+                    dtype=np.uint64)
+    assert np.array_equal(C.astype(np.uint64), np.broadcast_to(want[:, None, None], C.shape))
+
+
+def test_identity_and_shift():
+    p, n, d = P31, 6, 40
+    A = np.zeros((d, n, n), dtype=np.uint32)
+    A[5] = np.eye(n, dtype=np.uint32)
+    _, B = tensors(p, n, n, n, d, 4)
+    C = gpu_mul(p, A, B)
+    assert not C[:5].any() and np.array_equal(C[5:5 + d], B) and not C[5 + d:].any()
+
+
+def sampled_check(p, A, B, C, seed, entries):
+    d, m, n = A.shape
+    k = B.shape[2]
+    pairs = I.sample_pairs(seed, m, k, entries)
+    ref = O.polymatmul_entries(p, A, B, pairs)
+    for s, (i, j) in enumerate(pairs):
+        assert np.array_equal(C[:, i, j].astype(np.uint64), ref[s]), (i, j)
+    assert O.point_check(p, A, B, C, seed=seed, points=2)
+    assert O.freivalds_check(p, A, B, C, seed=seed, rounds=1)
+
+
+def test_config2_full_size_sampled():
+    """64x64 . 64x32, d = 4096, p = 2013265921 at full size: 16 seeded whole
+    entries against the oracle, plus point and Freivalds checks on all."""
+    p, m, n, k, d = P31, 64, 64, 32, 4096
+    say("[parity] config 2 full size")
+    A, B = tensors(p, m, n, k, d, seed=2)
+    C = gpu_mul(p, A, B)
+    sampled_check(p, A, B, C, seed=2, entries=16)
+
+
+def test_config4_full_size_sampled():
+    """60-bit non-NTT prime, 32x32 . 32x32, d = 2048, uint64, five CRT primes."""
+    p = I.seeded_prime_60(4)
+    assert O.is_prime(p)
+    info = Bd.pm_plan(p, 32, 32, 32, 2048, 8)
+    assert info.mode == 1 and info.num_primes == 5
+    say(f"[parity] config 4 full size p={p}")
+    A, B = tensors(p, 32, 32, 32, 2048, seed=4, dtype=np.uint64)
+    C = gpu_mul(p, A, B)
+    sampled_check(p, A, B, C, seed=4, entries=8)
+
+
+def test_batched_equals_single_calls():
+    p = P30
+    shapes = I.batched_shapes(7, 12, log2_dmin=1.0, log2_dmax=10.0)
+    say(f"[parity] batched {len(shapes)} products")
+    As, Bs, refs = [], [], []
+    for idx, (m, n, k, d) in enumerate(shapes):
+        A, B = tensors(p, m, n, k, d, seed=7, product=idx)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        refs.append(polymat.mul(p, As[-1], Bs[-1]).clone())
+    outs = polymat.mul_batched(p, As, Bs)
+    torch.cuda.synchronize()
+    for (m, n, k, d), C, R, A, B in zip(shapes, outs, refs, As, Bs):
+        assert torch.equal(C, R)
+    # and against the oracle for the small ones
+    for (m, n, k, d), C, A, B in zip(shapes, outs, As, Bs):
+        if m * n * k * d * d <= 1 << 26:
+            ref = O.polymatmul(p, A.cpu().numpy(), B.cpu().numpy())
+            assert np.array_equal(C.cpu().numpy().astype(np.uint64), ref)
+
+
+def test_repeat_runs_are_identical():
+    p, m, n, k, d = P31, 16, 16, 16, 1000
+    A, B = tensors(p, m, n, k, d, seed=9)
+    first = gpu_mul(p, A, B)
+    for _ in range(3):
+        assert np.array_equal(gpu_mul(p, A, B), first)
+
+
+def test_check_residues():
+    x = torch.from_numpy(np.array([0, 5, 96, 97, 98, 1 << 31, 3], dtype=np.uint32)).cuda()
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    n = Bd.pm_check_residues(97, x.data_ptr(), x.numel(), 4, ws.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    assert n == 3
