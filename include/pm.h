@@ -137,12 +137,28 @@ pm_status pm_mul_batched_u64(uint64_t p, int32_t count, const pm_product* prods,
                              void* stream);
 
 /* Count the elements of X (count residues of elem_bytes bytes, device
- * memory) that are >= p; the count is written to *n_bad (host pointer) after
- * the stream is synchronised.  workspace: at least 8 bytes of device memory.
- * Not on the hot path: an opt-in input check. */
+ * memory) that are >= p and write the count to *n_bad (host pointer).  This
+ * call synchronises `stream`.  workspace: at least 8 bytes of device memory,
+ * 8-byte aligned.  Not on the hot path: an opt-in input check. */
 pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count,
                             int32_t elem_bytes, uint64_t* n_bad,
                             void* workspace, void* stream);
+
+/* Kernel timing for measurement.  Between pm_profile_begin and
+ * pm_profile_end, every kernel the library launches (from any thread) is
+ * bracketed by two HIP events recorded on the stream it is launched on;
+ * pm_profile_end waits for those events and returns, per kernel kind, the
+ * summed device time and the launch count.  Kinds (index into the arrays):
+ * 0 forward transform, 1 pointwise products, 2 inverse transform,
+ * 3 Chinese remaindering, 4 batched persistent kernel.  Returns PM_EDEVICE if
+ * an event could not be created or read; PM_EINVAL if out is NULL. */
+#define PM_KERNEL_KINDS 8
+typedef struct pm_kernel_stats {
+  double total_ms[PM_KERNEL_KINDS];
+  uint64_t launches[PM_KERNEL_KINDS];
+} pm_kernel_stats;
+pm_status pm_profile_begin(void);
+pm_status pm_profile_end(pm_kernel_stats* out);
 
 /* Wait for `stream` and report any device error raised by earlier calls. */
 pm_status pm_sync(void* stream);

@@ -25,7 +25,9 @@ PM_EBUSY = -7
 EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
            "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_check_residues",
-           "pm_sync")
+           "pm_profile_begin", "pm_profile_end", "pm_sync")
+
+KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
 
 class PmError(RuntimeError):
@@ -38,6 +40,10 @@ class pm_plan_info(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("log2_len", ctypes.c_int32),
                 ("num_primes", ctypes.c_int32), ("pointwise", ctypes.c_int32),
                 ("primes", ctypes.c_uint32 * 8), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class pm_kernel_stats(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
 
 
 class pm_product(ctypes.Structure):
@@ -73,9 +79,11 @@ def lib():
     L.pm_mul_batched_u64.argtypes = [u64, i32, ctypes.POINTER(pm_product), vp, u64, vp]
     L.pm_check_residues.argtypes = [u64, vp, u64, i32, ctypes.POINTER(u64), vp, vp]
     L.pm_sync.argtypes = [vp]
+    L.pm_profile_begin.argtypes = []
+    L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
-                 "pm_check_residues", "pm_sync"):
+                 "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -146,3 +154,15 @@ def pm_check_residues(p: int, x_ptr: int, count: int, elem_bytes: int, ws_ptr: i
 
 def pm_sync(stream) -> None:
     _check(lib().pm_sync(stream), "pm_sync")
+
+
+def pm_profile_begin() -> None:
+    _check(lib().pm_profile_begin(), "pm_profile_begin")
+
+
+def pm_profile_end() -> dict:
+    """{kind: (total_ms, launches)} for the kernels launched since begin."""
+    st = pm_kernel_stats()
+    _check(lib().pm_profile_end(ctypes.byref(st)), "pm_profile_end")
+    return {name: (st.total_ms[i], int(st.launches[i]))
+            for i, name in enumerate(KERNEL_KINDS)}

@@ -16,6 +16,7 @@
 #include "../../include/pm.h"
 #include "pm_kernels.h"
 #include "pm_plan.h"
+#include "pm_profile.h"
 
 using namespace pm;
 
@@ -136,21 +137,40 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   fa.out = ahat;
   fa.in_prime_stride = 0;
   fa.out_prime_stride = pstride;
-  if (launch_ntt_fwd(fa, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+  {
+    KernelTimer kt(K_NTT_FWD, s);
+    if (launch_ntt_fwd(fa, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+  }
 
   NttLaunch fb = fa;
   fill_ntt_launch(&fb, P.logL, n * k, d);
   fb.in = B;
   fb.out = bhat;
-  if (launch_ntt_fwd(fb, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+  {
+    KernelTimer kt(K_NTT_FWD, s);
+    if (launch_ntt_fwd(fb, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+  }
 
   PointwiseLaunch pw;
   memset(&pw, 0, sizeof pw);
   pw.m = m; pw.n = n; pw.k = k; pw.L = 1 << P.logL;
   pw.prime_stride = pstride;
   pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
-  for (int i = 0; i < P.r; ++i) pw.pc[i] = pc[i];
-  if (launch_pointwise(pw, P.r, s) != hipSuccess) return PM_EDEVICE;
+  for (int i = 0; i < P.r; ++i) {
+    pw.pc[i] = pc[i];
+    // weights of the limb accumulators: 256^s L^{-1} mod q
+    uint64_t w = pc[i].linv;
+    for (int t = 0; t < 7; ++t) {
+      pw.cs[i][t] = (uint32_t)w;
+      w = (w << 8) % P.q[i];
+    }
+  }
+  {
+    KernelTimer kt(K_POINTWISE, s);
+    const int st = P.pointwise == 1 ? launch_pointwise_mfma(pw, P.r, s)
+                                    : launch_pointwise(pw, P.r, s);
+    if (st != hipSuccess) return PM_EDEVICE;
+  }
 
   NttLaunch ic = fa;
   fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1);
@@ -159,6 +179,7 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   if (P.mode == 0) {
     ic.out = C;
     ic.out_prime_stride = 0;
+    KernelTimer kt(K_NTT_INV, s);
     if (launch_ntt_inv(ic, P.elem_bytes, 1, s) != hipSuccess) return PM_EDEVICE;
     return PM_OK;
   }
@@ -166,13 +187,17 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   const uint64_t nout = (2ull * d - 1) * m * k;
   ic.out = cq;
   ic.out_prime_stride = nout;
-  if (launch_ntt_inv(ic, 4, P.r, s) != hipSuccess) return PM_EDEVICE;
+  {
+    KernelTimer kt(K_NTT_INV, s);
+    if (launch_ntt_inv(ic, 4, P.r, s) != hipSuccess) return PM_EDEVICE;
+  }
   CrtLaunch cr;
   fill_crt(P, &cr);
   cr.count = nout;
   cr.prime_stride = nout;
   cr.cq = cq;
   cr.out = C;
+  KernelTimer kt(K_CRT, s);
   if (launch_crt(cr, P.elem_bytes, s) != hipSuccess) return PM_EDEVICE;
   return PM_OK;
 }

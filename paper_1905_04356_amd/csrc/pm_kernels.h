@@ -22,6 +22,7 @@ struct NttLaunch {
   int nin;                   // forward: coefficients read; inverse: written
   int E;                     // entries per point
   int eb_log;                // log2(entries per workgroup)
+  int vec;                   // residues per global load/store (1, 2, 4)
   int lds_stride;            // 32-bit words between entries in LDS
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers
@@ -39,6 +40,7 @@ struct PointwiseLaunch {
   const uint32_t* bhat;
   uint32_t* chat;
   PrimeConst pc[kMaxPrimes];
+  uint32_t cs[kMaxPrimes][8];  // MFMA variant: 256^s L^{-1} mod q, s < 7
 };
 
 // Chinese remaindering of r residue arrays (u32, `count` each, stride
@@ -63,6 +65,8 @@ int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
                    hipStream_t s);
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s);
 int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
+int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);
+size_t pointwise_mfma_lds(int m, int n, int k);
 int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s);
 int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_bytes,
                           unsigned long long* counter, hipStream_t s);

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <stdlib.h>
+
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -152,6 +154,18 @@ static int ceil_log2(uint64_t x) {
   return l;
 }
 
+// Pointwise variant: int8-MFMA limbs where the shape allows (contraction
+// length a multiple of 4 and below 2^12, both matrices' limb planes within
+// 64 KiB of LDS), else the VALU kernel.  Tuning knob PM_TUNE_POINTWISE=0/1
+// forces a variant (1 only where the MFMA kernel supports the shape).
+static int choose_pointwise(int m, int n, int k) {
+  const uint64_t mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
+  const bool mfma_ok = n % 4 == 0 && n < 4096 && 4 * (mp + kp) * (np + 16) <= 64 * 1024;
+  const char* env = getenv("PM_TUNE_POINTWISE");
+  if (env && *env == '0') return 0;
+  return mfma_ok ? 1 : 0;
+}
+
 int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out) {
   if (!out) return PM_EINVAL;
   if (elem_bytes != 4 && elem_bytes != 8) return PM_EINVAL;
@@ -190,7 +204,7 @@ int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out)
     }
     if (big_cmp(prod, bound) <= 0) return PM_EUNSUPPORTED;
   }
-  P.pointwise = 0;
+  P.pointwise = choose_pointwise(m, n, k);
   uint64_t off = 0;
   P.off_ahat = off; off = align_up(off + 4 * L * mn, 256);
   P.off_bhat = off; off = align_up(off + 4 * L * nk, 256);
@@ -241,13 +255,14 @@ int get_prime_const(uint32_t q, int logL, PrimeConst* out) {
     std::vector<Tw> host(2 * cnt);
     for (int i = 0; i < PP.npass; ++i) {
       const int r = PP.stages[i], s = PP.stride_log[i];
-      const uint32_t S = 1u << s, R = 1u << r;
+      const uint32_t S = 1u << s;
       for (uint32_t j = 0; j < S; ++j)
         for (int v = 0; v < r; ++v)
           for (uint32_t u = 0; u < (1u << v); ++u) {
             // stage of half-size h = S * 2^v: exponent (j + u*S) * L / (2h)
             uint64_t e = (uint64_t)(j + u * S) << (logL - s - v - 1);
-            size_t idx = PP.tw_off[i] + (size_t)j * (R - 1) + ((1u << v) - 1) + u;
+            // slot-major: consecutive threads j read consecutive pairs
+            size_t idx = PP.tw_off[i] + (size_t)(((1u << v) - 1) + u) * S + j;
             host[idx] = Tw{pw[e], shoup_of(pw[e], q)};
             host[cnt + idx] = Tw{pwi[e], shoup_of(pwi[e], q)};
           }

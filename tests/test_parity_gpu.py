@@ -177,3 +177,30 @@ def test_check_residues():
     n = Bd.pm_check_residues(97, x.data_ptr(), x.numel(), 4, ws.data_ptr(),
                              torch.cuda.current_stream().cuda_stream)
     assert n == 3
+
+
+@pytest.mark.parametrize("m,n,k,d", [(8, 8, 8, 256), (16, 64, 16, 100), (5, 12, 7, 33),
+                                     (17, 4, 33, 65), (64, 64, 32, 64), (3, 128, 2, 20),
+                                     (32, 68, 48, 9)])
+@pytest.mark.parametrize("p", [P30, P31, P32])
+def test_pointwise_variants_match_oracle(p, m, n, k, d, monkeypatch):
+    """Both pointwise kernels (int8-MFMA limbs and VALU) against the oracle."""
+    info = Bd.pm_plan(p, m, n, k, d, 4)
+    assert info.pointwise == 1, "shape expected on the MFMA path"
+    full_check(p, m, n, k, d, seed=11)
+    monkeypatch.setenv("PM_TUNE_POINTWISE", "0")
+    assert Bd.pm_plan(p, m, n, k, d, 4).pointwise == 0
+    full_check(p, m, n, k, d, seed=11)
+
+
+def test_mfma_limb_extremes():
+    """Residues at the centring boundary ((q-1)/2, (q+1)/2), 0, 1, q-1 in every
+    position exercise the largest limb magnitudes."""
+    p, m, n, k, d = P31, 16, 64, 16, 8
+    vals = np.array([0, 1, (p - 1) // 2, (p + 1) // 2, p - 1, p - 2], dtype=np.uint32)
+    rng = np.random.default_rng(12)
+    A = vals[rng.integers(0, len(vals), size=(d, m, n))]
+    B = vals[rng.integers(0, len(vals), size=(d, n, k))]
+    assert Bd.pm_plan(p, m, n, k, d, 4).pointwise == 1
+    C = gpu_mul(p, A, B)
+    assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
