@@ -13,15 +13,20 @@ namespace pm {
 // bit-reversed order the in-place decimation-in-frequency passes produce.
 // Inverse: input point-major Chat[t][e]; output coefficient-major
 // C[c][e] for c < nin (the L^{-1} factor is applied by the pointwise kernel).
+// With split > 0 the first forward pass (last inverse pass) is a separate
+// streaming kernel and the LDS kernel transforms blocks of 2^blk_log
+// positions in place in the point-major buffer.
 struct NttLaunch {
   int logL;
   int npass;
+  int split;                 // stages of the streaming pass (0: none)
+  int blk_log;               // log2 positions per LDS block
   int stages[kMaxPasses];
   int stride_log[kMaxPasses];
   uint32_t tw_off[kMaxPasses];
   int nin;                   // forward: coefficients read; inverse: written
   int E;                     // entries per point
-  int eb_log;                // log2(entries per workgroup)
+  int eb_log;                // log2(entries per workgroup) in the LDS kernel
   int vec;                   // residues per global load/store (1, 2, 4)
   int lds_stride;            // 32-bit words between entries in LDS
   uint64_t in_prime_stride;  // elements between primes' input buffers

@@ -5,136 +5,42 @@
 // multiplication" (FFT paragraph) and "Polynomial matrix multiplication"
 // (evaluation/interpolation at roots of unity for FFT primes)).
 //
-// One workgroup transforms 2^eb_log polynomials held in LDS (L <= 2^15).
-// Stages are grouped in passes of up to five radix-2 stages: each thread
-// loads 2^r values at stride S from LDS into registers, runs r butterfly
-// stages there, and writes them back.  Multiplication by a root of unity uses
-// Shoup's precomputed quotient (pm_arith.h); the 2^r - 1 twiddles a thread
-// needs in a pass are stored slot-major, so the lanes of a wave (consecutive
-// j) read consecutive pairs.  Residues stay canonical ([0, q)) between stages,
-// because 2q < 2^32 but 4q may not be (q can exceed 2^30).
-//
 // Forward = decimation in frequency on natural-order input: position t of the
 // output holds the value at w^bitrev(t).  Inverse = decimation in time on that
-// order with w^-1, giving L times the natural-order coefficients.
-#include <stdlib.h>
-
+// order with w^-1, giving L times the natural-order coefficients (the
+// pointwise kernel applies L^{-1}).  Residues stay canonical ([0, q)) between
+// stages, because 2q < 2^32 but 4q may not be (q can exceed 2^30).
+// Multiplication by a root of unity uses Shoup's precomputed quotient
+// (pm_arith.h).
+//
+// Data layout in HBM: inputs are coefficient-major X[c][e] and evaluations
+// point-major Xhat[t][e] (e = entry), so a transform reads and writes rows of
+// consecutive entries.  Two kernel shapes:
+//   * LDS kernel: a workgroup holds 2^eb_log entries x 2^blk_log positions in
+//     LDS and runs passes of up to 4 radix-2 stages; in a pass a thread
+//     loads 2^r values at stride S into registers, runs r stages there and
+//     writes them back.  The 2^r - 1 twiddles a thread needs are stored
+//     slot-major (consecutive j read consecutive pairs), loaded once per
+//     item and applied to every entry of the item.
+//   * Column kernel (split > 0): the first forward pass (last inverse pass),
+//     of stride S = L / 2^split, streams rows straight from HBM to HBM with
+//     one thread per (j, entry), so every row access is a contiguous run of
+//     entries.  The remaining passes act on independent blocks of S
+//     consecutive positions; the LDS kernel then holds many entries of one
+//     block and transforms it in place.
 #include "pm_arith.h"
 #include "pm_kernels.h"
 
 namespace pm {
 
+constexpr int kNT = 512;      // threads of the LDS kernel
+constexpr int kColNT = 256;   // threads of the column kernel
+
 __device__ __forceinline__ int lds_pos(int pos) { return pos + (pos >> 5); }
-
-// Items of a pass: a thread takes one (blk, j) position group and EPI entries;
-// it loads the 2^r - 1 twiddles of its j once, up front, and applies them to
-// all EPI entries (twiddles do not depend on the entry).
-template <int r, int EPI, bool DIF>
-__device__ __forceinline__ void ntt_pass(uint32_t* lds, int lds_stride, int logL, int s,
-                                         const Tw* __restrict__ tw, int eb_log, uint32_t q) {
-  constexpr int R = 1 << r;
-  constexpr int epi_log = EPI == 4 ? 2 : EPI == 2 ? 1 : 0;
-  const int S = 1 << s;
-  const int per_entry_log = logL - r;
-  const int items = 1 << (per_entry_log + eb_log - epi_log);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int eg = it >> per_entry_log;
-    const int w = it & ((1 << per_entry_log) - 1);
-    const int blk = w >> s, j = w & (S - 1);
-    const int pos0 = (blk << (s + r)) + j;
-    Tw t[R - 1];
-#pragma unroll
-    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
-#pragma unroll
-    for (int ee = 0; ee < EPI; ++ee) {
-      uint32_t* base = lds + ((eg << epi_log) + ee) * lds_stride;
-      uint32_t x[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) x[u] = base[lds_pos(pos0 + u * S)];
-      if (DIF) {
-#pragma unroll
-        for (int v = r - 1; v >= 0; --v) {
-#pragma unroll
-          for (int u = 0; u < R; ++u) {
-            if (u & (1 << v)) continue;
-            const int u2 = u | (1 << v);
-            const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
-            const uint32_t a0 = x[u], b0 = x[u2];
-            x[u] = add_mod(a0, b0, q);
-            x[u2] = mul_shoup(a0 + (q - b0), tt.w, tt.wp, q);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < r; ++v) {
-#pragma unroll
-          for (int u = 0; u < R; ++u) {
-            if (u & (1 << v)) continue;
-            const int u2 = u | (1 << v);
-            const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
-            const uint32_t a0 = x[u];
-            const uint32_t b0 = mul_shoup(x[u2], tt.w, tt.wp, q);
-            x[u] = add_mod(a0, b0, q);
-            x[u2] = sub_mod(a0, b0, q);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < R; ++u) base[lds_pos(pos0 + u * S)] = x[u];
-    }
-  }
-}
-
-// Entries per item: enough that the block's 256 threads have about one item
-// each, at most the entries the block holds, at most 2.
-__device__ __forceinline__ int pass_epi(int logL, int r, int eb_log) {
-  const int triples_log = logL - r + eb_log;
-  int epi_log = triples_log - 8;
-  if (epi_log > eb_log) epi_log = eb_log;
-  if (epi_log > 1) epi_log = 1;
-  return epi_log < 0 ? 0 : epi_log;
-}
-
-template <bool DIF, int r>
-__device__ __forceinline__ void pass_r(const NttLaunch& a, uint32_t* lds, const Tw* tw,
-                                       int s, uint32_t q) {
-  if (pass_epi(a.logL, r, a.eb_log) == 1)
-    ntt_pass<r, 2, DIF>(lds, a.lds_stride, a.logL, s, tw, a.eb_log, q);
-  else
-    ntt_pass<r, 1, DIF>(lds, a.lds_stride, a.logL, s, tw, a.eb_log, q);
-}
-
-template <bool DIF>
-__device__ __forceinline__ void run_pass(const NttLaunch& a, uint32_t* lds, const Tw* tw,
-                                         int ps, uint32_t q) {
-  const int s = a.stride_log[ps];
-  switch (a.stages[ps]) {
-    case 1: pass_r<DIF, 1>(a, lds, tw, s, q); break;
-    case 2: pass_r<DIF, 2>(a, lds, tw, s, q); break;
-    case 3: pass_r<DIF, 3>(a, lds, tw, s, q); break;
-    case 4: pass_r<DIF, 4>(a, lds, tw, s, q); break;
-    default: pass_r<DIF, 5>(a, lds, tw, s, q); break;
-  }
-}
-
-__device__ __forceinline__ void run_dif(const NttLaunch& a, uint32_t* lds, const PrimeConst& P) {
-  for (int ps = 0; ps < a.npass; ++ps) {
-    run_pass<true>(a, lds, P.tw_fwd + a.tw_off[ps], ps, P.q);
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ void run_dit(const NttLaunch& a, uint32_t* lds, const PrimeConst& P) {
-  for (int ps = a.npass - 1; ps >= 0; --ps) {
-    run_pass<false>(a, lds, P.tw_inv + a.tw_off[ps], ps, P.q);
-    __syncthreads();
-  }
-}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that consecutive entry blocks, which share cache
-// lines of the coefficient-major input and point-major output, run on the
-// same XCD.
+// lines of the row-major buffers, run on the same XCD.
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int nx = 8;
   const int q = nb / nx, r = nb % nx;
@@ -147,8 +53,117 @@ struct alignas(sizeof(T) * V) Vec {
   T v[V];
 };
 
+// r radix-2 stages on x[0..2^r) held in registers.  DIF: stage distance
+// 2^v for v = r-1 .. 0, (a, b) -> (a + b, (a - b) w).  DIT: v = 0 .. r-1,
+// (a, b) -> (a + b w, a - b w).  ZHI (DIF only): x[2^(r-1) ..] are zero, so
+// the first stage is (a, 0) -> (a, a w).  t[(2^v - 1) + u'] is the twiddle of
+// stage v for butterflies whose lower index is u' mod 2^v.
+template <int r, bool DIF, bool ZHI>
+__device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q) {
+  constexpr int R = 1 << r;
+  if (DIF) {
+#pragma unroll
+    for (int v = r - 1; v >= 0; --v) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (u & (1 << v)) continue;
+        const int u2 = u | (1 << v);
+        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        if (ZHI && v == r - 1) {
+          x[u2] = mul_shoup(x[u], tt.w, tt.wp, q);
+        } else {
+          const uint32_t a0 = x[u], b0 = x[u2];
+          x[u] = add_mod(a0, b0, q);
+          x[u2] = mul_shoup(a0 + (q - b0), tt.w, tt.wp, q);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < r; ++v) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (u & (1 << v)) continue;
+        const int u2 = u | (1 << v);
+        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        const uint32_t a0 = x[u];
+        const uint32_t b0 = mul_shoup(x[u2], tt.w, tt.wp, q);
+        x[u] = add_mod(a0, b0, q);
+        x[u2] = sub_mod(a0, b0, q);
+      }
+    }
+  }
+}
+
+// One pass of r stages at stride 2^s over LDS blocks of 2^glog positions.
+// Items: a thread takes one (blk, j) position group and EPI entries; it loads
+// the 2^r - 1 twiddles of its j once and applies them to all EPI entries.
+template <int r, int EPI, bool DIF, bool ZHI>
+__device__ __forceinline__ void lds_pass(uint32_t* lds, int lds_stride, int glog, int s,
+                                         const Tw* __restrict__ tw, int eb_log, uint32_t q) {
+  constexpr int R = 1 << r;
+  constexpr int epi_log = EPI == 2 ? 1 : 0;
+  const int S = 1 << s;
+  const int per_entry_log = glog - r;
+  const int items = 1 << (per_entry_log + eb_log - epi_log);
+  for (int it = threadIdx.x; it < items; it += kNT) {
+    const int eg = it >> per_entry_log;
+    const int w = it & ((1 << per_entry_log) - 1);
+    const int blk = w >> s, j = w & (S - 1);
+    const int pos0 = (blk << (s + r)) + j;
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+#pragma unroll
+    for (int ee = 0; ee < EPI; ++ee) {
+      uint32_t* base = lds + ((eg << epi_log) + ee) * lds_stride;
+      uint32_t x[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        x[u] = (ZHI && u >= R / 2) ? 0u : base[lds_pos(pos0 + u * S)];
+      butterflies<r, DIF, ZHI>(x, t, q);
+#pragma unroll
+      for (int u = 0; u < R; ++u) base[lds_pos(pos0 + u * S)] = x[u];
+    }
+  }
+}
+
+// Entries per item: enough that the block's threads have about one item
+// each, at most the entries the block holds, at most 2.
+__device__ __forceinline__ int pass_epi(int glog, int r, int eb_log) {
+  int epi_log = glog - r + eb_log - 9;  // 2^9 = kNT
+  if (epi_log > eb_log) epi_log = eb_log;
+  if (epi_log > 1) epi_log = 1;
+  return epi_log < 0 ? 0 : epi_log;
+}
+
+template <bool DIF, bool ZHI, int r>
+__device__ __forceinline__ void pass_r(const NttLaunch& a, uint32_t* lds, const Tw* tw, int glog,
+                                       int s, uint32_t q) {
+  if (pass_epi(glog, r, a.eb_log) == 1)
+    lds_pass<r, 2, DIF, ZHI>(lds, a.lds_stride, glog, s, tw, a.eb_log, q);
+  else
+    lds_pass<r, 1, DIF, ZHI>(lds, a.lds_stride, glog, s, tw, a.eb_log, q);
+}
+
+template <bool DIF, bool ZHI>
+__device__ __forceinline__ void run_pass(const NttLaunch& a, uint32_t* lds, const Tw* tw,
+                                         int glog, int ps, uint32_t q) {
+  const int s = a.stride_log[ps];
+  switch (a.stages[ps]) {
+    case 1: pass_r<DIF, ZHI, 1>(a, lds, tw, glog, s, q); break;
+    case 2: pass_r<DIF, ZHI, 2>(a, lds, tw, glog, s, q); break;
+    case 3: pass_r<DIF, ZHI, 3>(a, lds, tw, glog, s, q); break;
+    default: pass_r<DIF, ZHI, 4>(a, lds, tw, glog, s, q); break;
+  }
+}
+
+// ---- LDS kernels ------------------------------------------------------------
+
+// Unsplit forward transform: coefficient-major input (rows < nin, nin <= L/2
+// unless L == 1) to point-major output.
 template <typename TIn, bool REDUCE, int V>
-__global__ __launch_bounds__(256, 2) void ntt_fwd_kernel(NttLaunch a) {
+__global__ __launch_bounds__(kNT) void ntt_fwd_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];
   const int prime = blockIdx.y;
   const PrimeConst& P = a.pc[prime];
@@ -158,7 +173,10 @@ __global__ __launch_bounds__(256, 2) void ntt_fwd_kernel(NttLaunch a) {
   const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
   const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);  // vector groups per row
   const int total = 1 << (a.logL + glog);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  // rows at or beyond L/2 are never read by the first pass when nin <= L/2
+  const bool zhi = a.npass > 0 && 2 * a.nin <= (1 << a.logL);
+  const int ltotal = 1 << ((zhi ? a.logL - 1 : a.logL) + glog);
+  for (int idx = threadIdx.x; idx < ltotal; idx += kNT) {
     const int c = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     Vec<TIn, V> x;
     if (c < a.nin && e0 + e < a.E) {
@@ -173,9 +191,15 @@ __global__ __launch_bounds__(256, 2) void ntt_fwd_kernel(NttLaunch a) {
           REDUCE ? reduce_u64((uint64_t)x.v[v], q, P.mu) : (uint32_t)x.v[v];
   }
   __syncthreads();
-  run_dif(a, lds, P);
+  for (int ps = 0; ps < a.npass; ++ps) {
+    if (ps == 0 && zhi)
+      run_pass<true, true>(a, lds, P.tw_fwd + a.tw_off[ps], a.logL, ps, q);
+    else
+      run_pass<true, false>(a, lds, P.tw_fwd + a.tw_off[ps], a.logL, ps, q);
+    __syncthreads();
+  }
   uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
     const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     if (e0 + e < a.E) {
       Vec<uint32_t, V> y;
@@ -186,8 +210,10 @@ __global__ __launch_bounds__(256, 2) void ntt_fwd_kernel(NttLaunch a) {
   }
 }
 
+// Unsplit inverse transform: point-major input to coefficient-major output
+// (rows < nin).
 template <typename TOut, int V>
-__global__ __launch_bounds__(256, 2) void ntt_inv_kernel(NttLaunch a) {
+__global__ __launch_bounds__(kNT) void ntt_inv_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];
   const int prime = blockIdx.y;
   const PrimeConst& P = a.pc[prime];
@@ -196,7 +222,7 @@ __global__ __launch_bounds__(256, 2) void ntt_inv_kernel(NttLaunch a) {
   const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
   const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
   const int total = 1 << (a.logL + glog);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
     const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     Vec<uint32_t, V> x;
     if (e0 + e < a.E) {
@@ -209,10 +235,13 @@ __global__ __launch_bounds__(256, 2) void ntt_inv_kernel(NttLaunch a) {
     for (int v = 0; v < V; ++v) lds[(e + v) * a.lds_stride + lds_pos(t)] = x.v[v];
   }
   __syncthreads();
-  run_dit(a, lds, P);
+  for (int ps = a.npass - 1; ps >= 0; --ps) {
+    run_pass<false, false>(a, lds, P.tw_inv + a.tw_off[ps], a.logL, ps, P.q);
+    __syncthreads();
+  }
   TOut* out = (TOut*)a.out + a.out_prime_stride * prime;
   const int nout = a.nin << glog;
-  for (int idx = threadIdx.x; idx < nout; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < nout; idx += kNT) {
     const int c = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     if (e0 + e < a.E) {
       Vec<TOut, V> y;
@@ -223,26 +252,133 @@ __global__ __launch_bounds__(256, 2) void ntt_inv_kernel(NttLaunch a) {
   }
 }
 
+// Split transforms, LDS part: block z of 2^blk_log consecutive positions of
+// the point-major buffer `out`, transformed in place by passes 1 .. npass-1
+// (forward, DIF) or npass-1 .. 1 (inverse, DIT).
+template <bool DIF, int V>
+__global__ __launch_bounds__(kNT) void ntt_block_kernel(NttLaunch a) {
+  extern __shared__ uint32_t lds[];
+  const int prime = blockIdx.y;
+  const PrimeConst& P = a.pc[prime];
+  const int EB = 1 << a.eb_log;
+  const int e0 = xcd_block(blockIdx.x, gridDim.x) * EB;
+  uint32_t* buf = (uint32_t*)a.out + a.out_prime_stride * prime +
+                  ((size_t)blockIdx.z << a.blk_log) * a.E;
+  const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
+  const int total = 1 << (a.blk_log + glog);
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    Vec<uint32_t, V> x;
+    if (e0 + e < a.E) {
+      x = *(const Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) x.v[v] = 0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[(e + v) * a.lds_stride + lds_pos(t)] = x.v[v];
+  }
+  __syncthreads();
+  if (DIF) {
+    for (int ps = 1; ps < a.npass; ++ps) {
+      run_pass<true, false>(a, lds, P.tw_fwd + a.tw_off[ps], a.blk_log, ps, P.q);
+      __syncthreads();
+    }
+  } else {
+    for (int ps = a.npass - 1; ps >= 1; --ps) {
+      run_pass<false, false>(a, lds, P.tw_inv + a.tw_off[ps], a.blk_log, ps, P.q);
+      __syncthreads();
+    }
+  }
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    if (e0 + e < a.E) {
+      Vec<uint32_t, V> y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.v[v] = lds[(e + v) * a.lds_stride + lds_pos(t)];
+      *(Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e) = y;
+    }
+  }
+}
+
+// ---- column kernels (split transforms) -----------------------------------------
+
+// First forward pass, r stages at stride S = L / 2^r: thread (j, e) reads rows
+// j + u S (u < 2^(r-1); the upper half is zero padding since nin <= L/2) of
+// the coefficient-major input, and writes all 2^r rows of the point-major
+// buffer.
+template <typename TIn, bool REDUCE, int r>
+__global__ __launch_bounds__(kColNT) void ntt_col_fwd_kernel(NttLaunch a) {
+  constexpr int R = 1 << r;
+  const int prime = blockIdx.y;
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t q = P.q;
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E;
+  const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
+  uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
+  const Tw* tw = P.tw_fwd + a.tw_off[0];
+  const uint32_t items = S * E;
+  for (uint32_t it = blockIdx.x * kColNT + threadIdx.x; it < items; it += gridDim.x * kColNT) {
+    const uint32_t j = it / E, e = it - j * E;
+    uint32_t x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t row = j + u * S;
+      x[u] = 0;
+      if (u < R / 2 && row < (uint32_t)a.nin) {
+        const TIn v = in[(size_t)row * E + e];
+        x[u] = REDUCE ? reduce_u64((uint64_t)v, q, P.mu) : (uint32_t)v;
+      }
+    }
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+    butterflies<r, true, true>(x, t, q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) out[(size_t)(j + u * S) * E + e] = x[u];
+  }
+}
+
+// Last inverse pass, r stages at stride S: thread (j, e) reads rows j + u S of
+// the point-major buffer and writes the rows below nin of the
+// coefficient-major output.
+template <typename TOut, int r>
+__global__ __launch_bounds__(kColNT) void ntt_col_inv_kernel(NttLaunch a) {
+  constexpr int R = 1 << r;
+  const int prime = blockIdx.y;
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E;
+  const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
+  TOut* out = (TOut*)a.out + a.out_prime_stride * prime;
+  const Tw* tw = P.tw_inv + a.tw_off[0];
+  const uint32_t items = S * E;
+  for (uint32_t it = blockIdx.x * kColNT + threadIdx.x; it < items; it += gridDim.x * kColNT) {
+    const uint32_t j = it / E, e = it - j * E;
+    uint32_t x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) x[u] = in[(size_t)(j + u * S) * E + e];
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+    butterflies<r, false, false>(x, t, P.q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t row = j + u * S;
+      if (row < (uint32_t)a.nin) out[(size_t)row * E + e] = (TOut)x[u];
+    }
+  }
+}
+
 // ---- host side ---------------------------------------------------------------
-
-static int env_int(const char* name, int dflt) {
-  const char* v = getenv(name);
-  return v && *v ? atoi(v) : dflt;
-}
-
-// log2 of the entries one workgroup transforms.  Tuning knob
-// PM_TUNE_NTT_LDS_LOG: log2 of the residues held in LDS per workgroup
-// (default 14, i.e. 64 KiB, two workgroups per CU).
-static int entries_log_per_block(int logL) {
-  static const int lds_log = env_int("PM_TUNE_NTT_LDS_LOG", 14);
-  int eb = lds_log - logL;
-  return eb < 0 ? 0 : eb;
-}
 
 void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin) {
   const PassPlan PP = make_pass_plan(logL);
   a->logL = logL;
   a->npass = PP.npass;
+  a->split = PP.split;
+  a->blk_log = logL - PP.split;
   for (int i = 0; i < kMaxPasses; ++i) {
     a->stages[i] = i < PP.npass ? PP.stages[i] : 0;
     a->stride_log[i] = i < PP.npass ? PP.stride_log[i] : 0;
@@ -250,15 +386,18 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin) {
   }
   a->nin = nin;
   a->E = E;
-  int eb = entries_log_per_block(logL);
-  while (eb > 0 && (1 << (eb - 1)) >= E) --eb;  // no more slots than entries
+  // about 2^lds_log residues of LDS per workgroup, at least one entry, no
+  // more slots than entries
+  int eb = ntt_tune().lds_log - a->blk_log;
+  if (eb < 0) eb = 0;
+  while (eb > 0 && (1 << (eb - 1)) >= E) --eb;
   a->eb_log = eb;
-  // Entries move between HBM and LDS in vectors of V consecutive residues.
+  // entries move between HBM and LDS in vectors of V consecutive residues
   int v = 4;
   while (v > 1 && ((E % v) != 0 || (1 << eb) % v != 0)) v >>= 1;
   a->vec = v;
-  const int L = 1 << logL;
-  a->lds_stride = L + (L >> 5) + 1;
+  const int B = 1 << a->blk_log;
+  a->lds_stride = B + (B >> 5) + 1;
 }
 
 static size_t lds_bytes(const NttLaunch& a) {
@@ -266,7 +405,7 @@ static size_t lds_bytes(const NttLaunch& a) {
 }
 
 template <typename K>
-static int launch(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) {
+static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hipStream_t s) {
   const size_t lds = lds_bytes(a);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
@@ -275,38 +414,88 @@ static int launch(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const int EB = 1 << a.eb_log;
-  dim3 grid((a.E + EB - 1) / EB, nprimes);
-  hipLaunchKernelGGL(kernel, grid, dim3(256), lds, s, a);
+  dim3 grid((a.E + EB - 1) / EB, nprimes, zblocks);
+  hipLaunchKernelGGL(kernel, grid, dim3(kNT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename K>
+static int launch_col(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) {
+  const uint64_t items = ((uint64_t)1 << (a.logL - a.split)) * (uint64_t)a.E;
+  uint64_t blocks = (items + kColNT - 1) / kColNT;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)blocks, nprimes), dim3(kColNT), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename TIn, bool REDUCE>
-static int launch_fwd_v(const NttLaunch& a, int nprimes, hipStream_t s) {
-  // 64-bit inputs move in vectors of at most 16 bytes
-  if (a.vec == 4 && sizeof(TIn) == 4) return launch(ntt_fwd_kernel<TIn, REDUCE, 4>, a, nprimes, s);
-  if (a.vec == 4) return launch(ntt_fwd_kernel<TIn, REDUCE, 2>, a, nprimes, s);
-  if (a.vec == 2) return launch(ntt_fwd_kernel<TIn, REDUCE, 2>, a, nprimes, s);
-  return launch(ntt_fwd_kernel<TIn, REDUCE, 1>, a, nprimes, s);
+static int launch_col_fwd_r(const NttLaunch& a, int nprimes, hipStream_t s) {
+  switch (a.split) {
+    case 2: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 2>, a, nprimes, s);
+    case 3: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 3>, a, nprimes, s);
+    case 4: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 4>, a, nprimes, s);
+    default: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 5>, a, nprimes, s);
+  }
+}
+
+template <typename TOut>
+static int launch_col_inv_r(const NttLaunch& a, int nprimes, hipStream_t s) {
+  switch (a.split) {
+    case 2: return launch_col(ntt_col_inv_kernel<TOut, 2>, a, nprimes, s);
+    case 3: return launch_col(ntt_col_inv_kernel<TOut, 3>, a, nprimes, s);
+    case 4: return launch_col(ntt_col_inv_kernel<TOut, 4>, a, nprimes, s);
+    default: return launch_col(ntt_col_inv_kernel<TOut, 5>, a, nprimes, s);
+  }
+}
+
+template <bool DIF>
+static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
+  const int zb = 1 << a.split;
+  if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4>, a, nprimes, zb, s);
+  if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2>, a, nprimes, zb, s);
+  return launch_lds(ntt_block_kernel<DIF, 1>, a, nprimes, zb, s);
+}
+
+template <typename TIn, bool REDUCE>
+static int launch_fwd_t(const NttLaunch& a, int nprimes, hipStream_t s) {
+  if (a.split) {
+    int st = launch_col_fwd_r<TIn, REDUCE>(a, nprimes, s);
+    if (st != hipSuccess) return st;
+    return launch_block<true>(a, nprimes, s);
+  }
+  // 32-bit inputs move in 16-byte vectors when E allows, 64-bit ones in 16 bytes
+  constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;
+  if (a.vec >= VW) return launch_lds(ntt_fwd_kernel<TIn, REDUCE, VW>, a, nprimes, 1, s);
+  return launch_lds(ntt_fwd_kernel<TIn, REDUCE, 1>, a, nprimes, 1, s);
 }
 
 int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
                    hipStream_t s) {
-  if (elem_bytes == 8) return launch_fwd_v<uint64_t, true>(a, nprimes, s);
-  if (reduce) return launch_fwd_v<uint32_t, true>(a, nprimes, s);
-  return launch_fwd_v<uint32_t, false>(a, nprimes, s);
+  if (elem_bytes == 8) return launch_fwd_t<uint64_t, true>(a, nprimes, s);
+  if (reduce) return launch_fwd_t<uint32_t, true>(a, nprimes, s);
+  return launch_fwd_t<uint32_t, false>(a, nprimes, s);
 }
 
+// Split inverse: the block kernel works in place on the evaluation buffer
+// a.in, then the column kernel writes the coefficients.
 template <typename TOut>
-static int launch_inv_v(const NttLaunch& a, int nprimes, hipStream_t s) {
-  if (a.vec == 4 && sizeof(TOut) == 4) return launch(ntt_inv_kernel<TOut, 4>, a, nprimes, s);
-  if (a.vec == 4) return launch(ntt_inv_kernel<TOut, 2>, a, nprimes, s);
-  if (a.vec == 2) return launch(ntt_inv_kernel<TOut, 2>, a, nprimes, s);
-  return launch(ntt_inv_kernel<TOut, 1>, a, nprimes, s);
+static int launch_inv_t(const NttLaunch& a, int nprimes, hipStream_t s) {
+  if (a.split) {
+    NttLaunch b = a;
+    b.out = (void*)a.in;
+    b.out_prime_stride = a.in_prime_stride;
+    int st = launch_block<false>(b, nprimes, s);
+    if (st != hipSuccess) return st;
+    return launch_col_inv_r<TOut>(a, nprimes, s);
+  }
+  constexpr int VW = sizeof(TOut) == 4 ? 4 : 2;
+  if (a.vec >= VW) return launch_lds(ntt_inv_kernel<TOut, VW>, a, nprimes, 1, s);
+  return launch_lds(ntt_inv_kernel<TOut, 1>, a, nprimes, 1, s);
 }
 
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s) {
-  if (out_elem_bytes == 8) return launch_inv_v<uint64_t>(a, nprimes, s);
-  return launch_inv_v<uint32_t>(a, nprimes, s);
+  if (out_elem_bytes == 8) return launch_inv_t<uint64_t>(a, nprimes, s);
+  return launch_inv_t<uint32_t>(a, nprimes, s);
 }
 
 }  // namespace pm

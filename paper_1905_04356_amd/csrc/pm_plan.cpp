@@ -99,15 +99,45 @@ static uint32_t primitive_root(uint32_t q) {
   return 0;
 }
 
+static int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  int x = atoi(v);
+  return x < lo ? lo : x > hi ? hi : x;
+}
+
+const NttTune& ntt_tune() {
+  static const NttTune T = {env_int("PM_TUNE_NTT_MAXR", 4, 2, 4),
+                            env_int("PM_TUNE_NTT_LDS_LOG", 14, 11, 15),
+                            env_int("PM_TUNE_NTT_SPLIT", 5, 0, 5),
+                            env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16)};
+  return T;
+}
+
+int split_stages(int logL) {
+  const NttTune& T = ntt_tune();
+  if (T.split_r1 <= 0 || logL < T.split_min_log || T.split_r1 >= logL) return 0;
+  return T.split_r1;
+}
+
 PassPlan make_pass_plan(int logL) {
+  const NttTune& T = ntt_tune();
   PassPlan P{};
   P.logL = logL;
-  P.npass = (logL + 4) / 5;  // at most 5 stages (radix 32) per pass
+  P.split = split_stages(logL);
+  int rest = logL, first = 0;
+  if (P.split) {
+    P.stages[0] = P.split;
+    rest -= P.split;
+    first = 1;
+  }
+  const int nrest = (rest + T.maxr - 1) / T.maxr;  // at most maxr stages per pass
+  P.npass = first + nrest;
+  for (int i = 0; i < nrest; ++i)
+    P.stages[first + i] = rest / nrest + (i < rest % nrest ? 1 : 0);
   int s = logL;
   uint32_t off = 0;
   for (int i = 0; i < P.npass; ++i) {
-    int base = logL / P.npass, extra = logL % P.npass;
-    P.stages[i] = base + (i < extra ? 1 : 0);
     s -= P.stages[i];
     P.stride_log[i] = s;
     P.tw_off[i] = off;

@@ -20,8 +20,12 @@ struct Tw {
 // stages; pass i works on groups of 2^r_i elements at stride S_i, with
 // S_0 = L / 2^r_0 and S_{i+1} = S_i / 2^r_{i+1} (the last stride is 1).  The
 // inverse (decimation in time) runs the same passes in reverse order.
+// split > 0: pass 0 (split stages at stride L / 2^split) runs as a streaming
+// column kernel; the later passes act on independent blocks of
+// L / 2^split consecutive positions, which an LDS kernel transforms in place.
 struct PassPlan {
   int logL;
+  int split;
   int npass;
   int stages[kMaxPasses];      // forward order
   int stride_log[kMaxPasses];  // log2 S_i, forward order
@@ -30,6 +34,17 @@ struct PassPlan {
 };
 
 PassPlan make_pass_plan(int logL);
+
+// Tuning of the transform kernels, read from the environment once:
+// PM_TUNE_NTT_MAXR (largest stages per LDS pass, 2..4, default 4),
+// PM_TUNE_NTT_LDS_LOG (log2 residues of LDS per workgroup, 11..15, default 14),
+// PM_TUNE_NTT_SPLIT (stages of the streaming column pass, 0 = none, default 5),
+// PM_TUNE_NTT_SPLIT_MINLOG (smallest log2 L that is split, default 11).
+struct NttTune {
+  int maxr, lds_log, split_r1, split_min_log;
+};
+const NttTune& ntt_tune();
+int split_stages(int logL);
 
 // Per-prime constants shared by all kernels.
 struct PrimeConst {
