@@ -11,9 +11,12 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/pm.h"
+#include "pm_batch.h"
 #include "pm_kernels.h"
 #include "pm_plan.h"
 #include "pm_profile.h"
@@ -113,9 +116,15 @@ void fill_crt(const Plan& P, CrtLaunch* c) {
   }
 }
 
-// Enqueue one product.  A, B, C are device pointers of elem_bytes residues.
-int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                hipStream_t s) {
+}  // namespace
+
+namespace pm {
+
+// All launch descriptors of one product; A, B, C device pointers, ws the
+// product's workspace (laid out by make_plan).
+int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
+                          ProductLaunches* L) {
+  memset(L, 0, sizeof *L);
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
     int st = get_prime_const(P.q[i], P.logL, &pc[i]);
@@ -126,33 +135,28 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   uint32_t* ahat = (uint32_t*)(ws + P.off_ahat);
   uint32_t* bhat = (uint32_t*)(ws + P.off_bhat);
   uint32_t* chat = (uint32_t*)(ws + P.off_chat);
-  // In direct mode the inputs are already residues mod q = p.
-  const int reduce = P.mode == 1;
+  L->elem_bytes = P.elem_bytes;
+  L->reduce = P.mode == 1;  // in direct mode the inputs are already residues mod q = p
+  L->pointwise = P.pointwise;
+  L->mode = P.mode;
+  L->nprimes = P.r;
+  L->pw_staged = 4ull * ((uint64_t)m * n + (uint64_t)n * k) <= 128 * 1024;
 
-  NttLaunch fa;
-  memset(&fa, 0, sizeof fa);
+  NttLaunch& fa = L->f[0];
   fill_ntt_launch(&fa, P.logL, m * n, d);
   for (int i = 0; i < P.r; ++i) fa.pc[i] = pc[i];
   fa.in = A;
   fa.out = ahat;
   fa.in_prime_stride = 0;
   fa.out_prime_stride = pstride;
-  {
-    KernelTimer kt(K_NTT_FWD, s);
-    if (launch_ntt_fwd(fa, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
-  }
 
-  NttLaunch fb = fa;
+  NttLaunch& fb = L->f[1];
+  fb = fa;
   fill_ntt_launch(&fb, P.logL, n * k, d);
   fb.in = B;
   fb.out = bhat;
-  {
-    KernelTimer kt(K_NTT_FWD, s);
-    if (launch_ntt_fwd(fb, P.elem_bytes, reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
-  }
 
-  PointwiseLaunch pw;
-  memset(&pw, 0, sizeof pw);
+  PointwiseLaunch& pw = L->pw;
   pw.m = m; pw.n = n; pw.k = k; pw.L = 1 << P.logL;
   pw.prime_stride = pstride;
   pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
@@ -165,40 +169,61 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
       w = (w << 8) % P.q[i];
     }
   }
-  {
-    KernelTimer kt(K_POINTWISE, s);
-    const int st = P.pointwise == 1 ? launch_pointwise_mfma(pw, P.r, s)
-                                    : launch_pointwise(pw, P.r, s);
-    if (st != hipSuccess) return PM_EDEVICE;
-  }
 
-  NttLaunch ic = fa;
+  NttLaunch& ic = L->inv;
+  ic = fa;
   fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1);
   ic.in = chat;
   ic.in_prime_stride = pstride;
+  const uint64_t nout = (2ull * d - 1) * m * k;
   if (P.mode == 0) {
     ic.out = C;
     ic.out_prime_stride = 0;
-    KernelTimer kt(K_NTT_INV, s);
-    if (launch_ntt_inv(ic, P.elem_bytes, 1, s) != hipSuccess) return PM_EDEVICE;
-    return PM_OK;
+  } else {
+    ic.out = ws + P.off_cq;
+    ic.out_prime_stride = nout;
+    CrtLaunch& cr = L->crt;
+    fill_crt(P, &cr);
+    cr.count = nout;
+    cr.prime_stride = nout;
+    cr.cq = (const uint32_t*)(ws + P.off_cq);
+    cr.out = C;
   }
-  uint32_t* cq = (uint32_t*)(ws + P.off_cq);
-  const uint64_t nout = (2ull * d - 1) * m * k;
-  ic.out = cq;
-  ic.out_prime_stride = nout;
+  // LDS block step of a split inverse: in place on the evaluations of C
+  L->ib = ic;
+  L->ib.out = chat;
+  L->ib.out_prime_stride = pstride;
+  return PM_OK;
+}
+
+}  // namespace pm
+
+namespace {
+
+// Enqueue one product, one launch (or two for split transforms) per phase.
+int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
+                hipStream_t s) {
+  ProductLaunches L;
+  int st = fill_product_launches(P, A, B, C, ws, &L);
+  if (st != PM_OK) return st;
+  for (int op = 0; op < 2; ++op) {
+    KernelTimer kt(K_NTT_FWD, s);
+    if (launch_ntt_fwd(L.f[op], P.elem_bytes, L.reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+  }
+  {
+    KernelTimer kt(K_POINTWISE, s);
+    st = P.pointwise == 1 ? launch_pointwise_mfma(L.pw, P.r, s) : launch_pointwise(L.pw, P.r, s);
+    if (st != hipSuccess) return PM_EDEVICE;
+  }
   {
     KernelTimer kt(K_NTT_INV, s);
-    if (launch_ntt_inv(ic, 4, P.r, s) != hipSuccess) return PM_EDEVICE;
+    if (launch_ntt_inv(L.inv, P.mode == 0 ? P.elem_bytes : 4, P.r, s) != hipSuccess)
+      return PM_EDEVICE;
   }
-  CrtLaunch cr;
-  fill_crt(P, &cr);
-  cr.count = nout;
-  cr.prime_stride = nout;
-  cr.cq = cq;
-  cr.out = C;
-  KernelTimer kt(K_CRT, s);
-  if (launch_crt(cr, P.elem_bytes, s) != hipSuccess) return PM_EDEVICE;
+  if (P.mode == 1) {
+    KernelTimer kt(K_CRT, s);
+    if (launch_crt(L.crt, P.elem_bytes, s) != hipSuccess) return PM_EDEVICE;
+  }
   return PM_OK;
 }
 
@@ -266,16 +291,164 @@ pm_status pm_sync(void* stream) {
 
 namespace {
 
+// Segments a product contributes to the six phases (see pm_batch.h).
+int count_segments(const Plan& P) {
+  const int split = split_stages(P.logL) ? 1 : 0;
+  return 2 * P.r                 // forward first pass / unsplit forward
+         + 2 * P.r * split       // forward blocks
+         + P.r                   // pointwise
+         + P.r * split           // inverse blocks
+         + P.r                   // inverse last pass / unsplit inverse
+         + (P.mode == 1 ? 1 : 0);
+}
+
+struct BatchLayout {
+  uint64_t prod_off;   // ProductLaunches[count]
+  uint64_t seg_off;    // BatchSeg[total segments]
+  uint64_t total;
+  uint64_t nseg;
+};
+
 int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_bytes,
-               Plan* plans, uint64_t* total) {
-  uint64_t off = 0;
+               std::vector<Plan>& plans, std::vector<uint64_t>& offs, BatchLayout* lay) {
+  plans.resize(count);
+  offs.resize(count);
+  uint64_t off = 0, nseg = 0;
   for (int32_t i = 0; i < count; ++i) {
     const pm_product& pr = prods[i];
     int st = make_plan(p, pr.m, pr.n, pr.k, pr.d, elem_bytes, &plans[i]);
     if (st != PM_OK) return st;
+    offs[i] = off;
     off = align_up(off + plans[i].ws_bytes, 256);
+    nseg += count_segments(plans[i]);
   }
-  *total = off;
+  lay->prod_off = off;
+  off = align_up(off + sizeof(ProductLaunches) * (uint64_t)count, 256);
+  lay->seg_off = off;
+  off = align_up(off + sizeof(BatchSeg) * nseg, 256);
+  lay->total = off;
+  lay->nseg = nseg;
+  return PM_OK;
+}
+
+struct HostSeg {
+  BatchSeg g;
+  uint32_t count;
+  double cost;  // per tile
+};
+
+size_t ntt_lds_bytes(const NttLaunch& a) { return 4 * (size_t)a.lds_stride << a.eb_log; }
+
+// Build the segments of one product into the per-phase lists; track LDS needs.
+void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
+                      std::vector<HostSeg>* ph, size_t* lds) {
+  auto add = [&](int phase, uint16_t kind, uint16_t op, uint16_t prime, uint32_t nx,
+                 uint32_t count, double cost, size_t need, uint16_t zpts) {
+    HostSeg h;
+    memset(&h, 0, sizeof h);
+    h.g.prod = idx; h.g.nx = nx; h.g.kind = kind; h.g.op = op; h.g.prime = prime;
+    h.g.zpts = zpts;
+    h.count = count;
+    h.cost = cost;
+    ph[phase].push_back(h);
+    if (need > lds[phase]) lds[phase] = need;
+  };
+  const uint32_t L_ = 1u << P.logL;
+  for (int op = 0; op < 2; ++op) {
+    const NttLaunch& a = L.f[op];
+    const uint32_t EB = 1u << a.eb_log;
+    const uint32_t neb = ((uint32_t)a.E + EB - 1) / EB;
+    for (int q = 0; q < P.r; ++q) {
+      if (a.split) {
+        const uint32_t items = (L_ >> a.split) * (uint32_t)a.E;
+        const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
+        add(0, BK_COL_FWD, op, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
+                                              (1 << a.split), 0, 0);
+        add(1, BK_BLOCK_FWD, op, q, neb, neb << a.split,
+            (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
+      } else {
+        add(0, BK_FWD_LDS, op, q, neb, neb, (double)EB * L_ * (P.logL + 1), ntt_lds_bytes(a), 0);
+      }
+    }
+  }
+  {
+    const double mnk = (double)P.m * P.n * P.k;
+    uint32_t z = (uint32_t)(65536.0 / mnk);
+    if (z < 1) z = 1;
+    if (z > L_) z = L_;
+    if (z > 65535) z = 65535;
+    const uint32_t nt = (L_ + z - 1) / z;
+    size_t need = 0;
+    if (L.pointwise == 1) need = pointwise_mfma_lds(P.m, P.n, P.k);
+    else if (L.pw_staged) need = 4ull * ((uint64_t)P.m * P.n + (uint64_t)P.n * P.k);
+    for (int q = 0; q < P.r; ++q) add(2, BK_PW, 0, q, nt, nt, z * mnk, need, (uint16_t)z);
+  }
+  {
+    const NttLaunch& a = L.inv;
+    const uint32_t EB = 1u << a.eb_log;
+    const uint32_t neb = ((uint32_t)a.E + EB - 1) / EB;
+    for (int q = 0; q < P.r; ++q) {
+      if (a.split) {
+        add(3, BK_BLOCK_INV, 0, q, neb, neb << a.split,
+            (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
+        const uint32_t items = (L_ >> a.split) * (uint32_t)a.E;
+        const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
+        add(4, BK_COL_INV, 0, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
+                                             (1 << a.split), 0, 0);
+      } else {
+        add(4, BK_INV_LDS, 0, q, neb, neb, (double)EB * L_ * (P.logL + 1), ntt_lds_bytes(a), 0);
+      }
+    }
+  }
+  if (P.mode == 1) {
+    const uint32_t n = (uint32_t)((L.crt.count + kCrtChunk - 1) / kCrtChunk);
+    add(5, BK_CRT, 0, 0, n, n, (double)kCrtChunk * P.r, 0, 0);
+  }
+}
+
+int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
+              const BatchLayout& lay, const pm_product* prods, uint8_t* ws, hipStream_t s) {
+  const int count = (int)plans.size();
+  std::vector<uint8_t> host(lay.total - lay.prod_off, 0);
+  ProductLaunches* hp = (ProductLaunches*)host.data();
+  std::vector<HostSeg> ph[kBatchPhases];
+  size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < count; ++i) {
+    int st = fill_product_launches(plans[i], prods[i].A, prods[i].B, prods[i].C, ws + offs[i],
+                                   &hp[i]);
+    if (st != PM_OK) return st;
+    product_segments((uint32_t)i, plans[i], hp[i], ph, lds);
+  }
+  // Per phase: largest tiles first, then prefix sums of tile counts.
+  BatchSeg* hs = (BatchSeg*)(host.data() + (lay.seg_off - lay.prod_off));
+  uint64_t seg_base = 0;
+  uint64_t phase_first_seg[kBatchPhases], phase_tiles[kBatchPhases];
+  for (int f = 0; f < kBatchPhases; ++f) {
+    std::stable_sort(ph[f].begin(), ph[f].end(),
+                     [](const HostSeg& a, const HostSeg& b) { return a.cost > b.cost; });
+    uint64_t first = 0;
+    phase_first_seg[f] = seg_base;
+    for (auto& h : ph[f]) {
+      h.g.first = (uint32_t)first;
+      first += h.count;
+      hs[seg_base++] = h.g;
+    }
+    if (first > 0x7fffffffull) return PM_ERANGE;
+    phase_tiles[f] = first;
+  }
+  if (seg_base > lay.nseg) return PM_EINVAL;
+  if (hipMemcpyAsync(ws + lay.prod_off, host.data(), host.size(), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return PM_EDEVICE;
+  const ProductLaunches* dprods = (const ProductLaunches*)(ws + lay.prod_off);
+  const BatchSeg* dsegs = (const BatchSeg*)(ws + lay.seg_off);
+  KernelTimer kt(K_BATCHED, s);
+  for (int f = 0; f < kBatchPhases; ++f) {
+    if (phase_tiles[f] == 0) continue;
+    if (launch_batch_phase(f, dprods, dsegs + phase_first_seg[f], (int)ph[f].size(),
+                           (uint32_t)phase_tiles[f], lds[f], s) != hipSuccess)
+      return PM_EDEVICE;
+  }
   return PM_OK;
 }
 
@@ -286,13 +459,12 @@ extern "C" {
 pm_status pm_batched_workspace_bytes(uint64_t p, int32_t count, const pm_product* prods,
                                      int32_t elem_bytes, uint64_t* out) {
   if (!out || count < 0 || (count > 0 && !prods)) return PM_EINVAL;
-  Plan* plans = new (std::nothrow) Plan[count > 0 ? count : 1];
-  if (!plans) return PM_ENOMEM;
-  uint64_t total = 0;
-  int st = plan_batch(p, count, prods, elem_bytes, plans, &total);
-  delete[] plans;
+  std::vector<Plan> plans;
+  std::vector<uint64_t> offs;
+  BatchLayout lay;
+  int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
   if (st != PM_OK) return (pm_status)st;
-  *out = total;
+  *out = lay.total;
   return PM_OK;
 }
 
@@ -300,21 +472,22 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
                                 int elem_bytes, void* ws, uint64_t ws_bytes, void* stream) {
   if (count < 0 || (count > 0 && !prods)) return PM_EINVAL;
   if (count == 0) return PM_OK;
-  Plan* plans = new (std::nothrow) Plan[count];
-  if (!plans) return PM_ENOMEM;
-  uint64_t total = 0;
-  int st = plan_batch(p, count, prods, elem_bytes, plans, &total);
-  for (int32_t i = 0; st == PM_OK && i < count; ++i)
+  std::vector<Plan> plans;
+  std::vector<uint64_t> offs;
+  BatchLayout lay;
+  int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
+  if (st != PM_OK) return (pm_status)st;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < lay.total) return PM_EWORKSPACE;
+  for (int32_t i = 0; i < count; ++i) {
     st = check_operands(plans[i], prods[i].A, prods[i].B, prods[i].C);
-  if (st == PM_OK && (!ws || ((uintptr_t)ws & 255) || ws_bytes < total)) st = PM_EWORKSPACE;
-  uint64_t off = 0;
-  for (int32_t i = 0; st == PM_OK && i < count; ++i) {
-    st = run_product(plans[i], prods[i].A, prods[i].B, prods[i].C, (uint8_t*)ws + off,
-                     (hipStream_t)stream);
-    off = align_up(off + plans[i].ws_bytes, 256);
+    if (st != PM_OK) return (pm_status)st;
+    const uint64_t eb = (uint64_t)elem_bytes;
+    const Plan& P = plans[i];
+    st = check_workspace(ws, ws_bytes, lay.total, prods[i].A, eb * P.d * P.m * P.n, prods[i].B,
+                         eb * P.d * P.n * P.k, prods[i].C, eb * (2ull * P.d - 1) * P.m * P.k);
+    if (st != PM_OK) return (pm_status)st;
   }
-  delete[] plans;
-  return (pm_status)st;
+  return (pm_status)run_batch(plans, offs, lay, prods, (uint8_t*)ws, (hipStream_t)stream);
 }
 
 pm_status pm_mul_batched_u32(uint32_t p, int32_t count, const pm_product* prods, void* workspace,

@@ -1,0 +1,370 @@
+// pm_ntt_dev.h -- device side of the batched number-theoretic transforms.
+//
+// Evaluation at the L-th roots of unity of an FFT prime q and interpolation
+// back (Hyun, Neiger, Schost, ISSAC 2019, Section 2, "Polynomial
+// multiplication" (FFT paragraph) and "Polynomial matrix multiplication"
+// (evaluation/interpolation at roots of unity for FFT primes)).
+//
+// Forward = decimation in frequency on natural-order input: position t of the
+// output holds the value at w^bitrev(t).  Inverse = decimation in time on that
+// order with w^-1, giving L times the natural-order coefficients (the
+// pointwise kernel applies L^{-1}).  Residues stay canonical ([0, q)) between
+// stages, because 2q < 2^32 but 4q may not be (q can exceed 2^30).
+// Multiplication by a root of unity uses Shoup's precomputed quotient
+// (pm_arith.h).
+//
+// Data layout in HBM: inputs are coefficient-major X[c][e] and evaluations
+// point-major Xhat[t][e] (e = entry), so a transform reads and writes rows of
+// consecutive entries.  Two kernel shapes:
+//   * LDS kernel: a workgroup holds 2^eb_log entries x 2^blk_log positions in
+//     LDS and runs passes of up to 4 radix-2 stages; in a pass a thread
+//     loads 2^r values at stride S into registers, runs r stages there and
+//     writes them back.  The 2^r - 1 twiddles a thread needs are stored
+//     slot-major (consecutive j read consecutive pairs), loaded once per
+//     item and applied to every entry of the item.
+//   * Column kernel (split > 0): the first forward pass (last inverse pass),
+//     of stride S = L / 2^split, streams rows straight from HBM to HBM with
+//     one thread per (j, entry), so every row access is a contiguous run of
+//     entries.  The remaining passes act on independent blocks of S
+//     consecutive positions; the LDS kernel then holds many entries of one
+//     block and transforms it in place.
+#pragma once
+#include "pm_arith.h"
+#include "pm_kernels.h"
+
+namespace pm {
+
+constexpr int kNT = 512;      // threads of the LDS kernels
+constexpr int kColNT = 256;   // threads of the single-product column kernel
+
+__device__ __forceinline__ int lds_pos(int pos) { return pos + (pos >> 5); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that consecutive entry blocks, which share cache
+// lines of the row-major buffers, run on the same XCD.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int nx = 8;
+  const int q = nb / nx, r = nb % nx;
+  const int x = b % nx, i = b / nx;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+  T v[V];
+};
+
+// r radix-2 stages on x[0..2^r) held in registers.  DIF: stage distance
+// 2^v for v = r-1 .. 0, (a, b) -> (a + b, (a - b) w).  DIT: v = 0 .. r-1,
+// (a, b) -> (a + b w, a - b w).  ZHI (DIF only): x[2^(r-1) ..] are zero, so
+// the first stage is (a, 0) -> (a, a w).  t[(2^v - 1) + u'] is the twiddle of
+// stage v for butterflies whose lower index is u' mod 2^v.
+template <int r, bool DIF, bool ZHI>
+__device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q) {
+  constexpr int R = 1 << r;
+  if (DIF) {
+#pragma unroll
+    for (int v = r - 1; v >= 0; --v) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (u & (1 << v)) continue;
+        const int u2 = u | (1 << v);
+        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        if (ZHI && v == r - 1) {
+          x[u2] = mul_shoup(x[u], tt.w, tt.wp, q);
+        } else {
+          const uint32_t a0 = x[u], b0 = x[u2];
+          x[u] = add_mod(a0, b0, q);
+          x[u2] = mul_shoup(a0 + (q - b0), tt.w, tt.wp, q);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < r; ++v) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (u & (1 << v)) continue;
+        const int u2 = u | (1 << v);
+        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        const uint32_t a0 = x[u];
+        const uint32_t b0 = mul_shoup(x[u2], tt.w, tt.wp, q);
+        x[u] = add_mod(a0, b0, q);
+        x[u2] = sub_mod(a0, b0, q);
+      }
+    }
+  }
+}
+
+// One pass of r stages at stride 2^s over LDS blocks of 2^glog positions.
+// Items: a thread takes one (blk, j) position group and EPI entries; it loads
+// the 2^r - 1 twiddles of its j once and applies them to all EPI entries.
+template <int r, int EPI, bool DIF, bool ZHI>
+__device__ __forceinline__ void lds_pass(uint32_t* lds, int lds_stride, int glog, int s,
+                                         const Tw* __restrict__ tw, int eb_log, uint32_t q) {
+  constexpr int R = 1 << r;
+  constexpr int epi_log = EPI == 2 ? 1 : 0;
+  const int S = 1 << s;
+  const int per_entry_log = glog - r;
+  const int items = 1 << (per_entry_log + eb_log - epi_log);
+  for (int it = threadIdx.x; it < items; it += kNT) {
+    const int eg = it >> per_entry_log;
+    const int w = it & ((1 << per_entry_log) - 1);
+    const int blk = w >> s, j = w & (S - 1);
+    const int pos0 = (blk << (s + r)) + j;
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+#pragma unroll
+    for (int ee = 0; ee < EPI; ++ee) {
+      uint32_t* base = lds + ((eg << epi_log) + ee) * lds_stride;
+      uint32_t x[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        x[u] = (ZHI && u >= R / 2) ? 0u : base[lds_pos(pos0 + u * S)];
+      butterflies<r, DIF, ZHI>(x, t, q);
+#pragma unroll
+      for (int u = 0; u < R; ++u) base[lds_pos(pos0 + u * S)] = x[u];
+    }
+  }
+}
+
+// Entries per item: enough that the block's threads have about one item
+// each, at most the entries the block holds, at most 2.
+__device__ __forceinline__ int pass_epi(int glog, int r, int eb_log) {
+  int epi_log = glog - r + eb_log - 9;  // 2^9 = kNT
+  if (epi_log > eb_log) epi_log = eb_log;
+  if (epi_log > 1) epi_log = 1;
+  return epi_log < 0 ? 0 : epi_log;
+}
+
+template <bool DIF, bool ZHI, int r>
+__device__ __forceinline__ void pass_r(const NttLaunch& a, uint32_t* lds, const Tw* tw, int glog,
+                                       int s, uint32_t q) {
+  if (pass_epi(glog, r, a.eb_log) == 1)
+    lds_pass<r, 2, DIF, ZHI>(lds, a.lds_stride, glog, s, tw, a.eb_log, q);
+  else
+    lds_pass<r, 1, DIF, ZHI>(lds, a.lds_stride, glog, s, tw, a.eb_log, q);
+}
+
+template <bool DIF, bool ZHI>
+__device__ __forceinline__ void run_pass(const NttLaunch& a, uint32_t* lds, const Tw* tw,
+                                         int glog, int ps, uint32_t q) {
+  const int s = a.stride_log[ps];
+  switch (a.stages[ps]) {
+    case 1: pass_r<DIF, ZHI, 1>(a, lds, tw, glog, s, q); break;
+    case 2: pass_r<DIF, ZHI, 2>(a, lds, tw, glog, s, q); break;
+    case 3: pass_r<DIF, ZHI, 3>(a, lds, tw, glog, s, q); break;
+    default: pass_r<DIF, ZHI, 4>(a, lds, tw, glog, s, q); break;
+  }
+}
+
+// ---- tiles ------------------------------------------------------------------
+// Each function below is the work of one workgroup; the single-product
+// kernels and the batched phase kernels both call them.  eb = entry block
+// index, z = position block index (split transforms).
+
+// Unsplit forward transform: coefficient-major input (rows < nin, nin <= L/2
+// unless L == 1) to point-major output.
+template <typename TIn, bool REDUCE, int V>
+__device__ __forceinline__ void fwd_lds_tile(const NttLaunch& a, int prime, int eb,
+                                             uint32_t* lds) {
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t q = P.q;
+  const int EB = 1 << a.eb_log;
+  const int e0 = eb * EB;
+  const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
+  const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);  // vector groups per row
+  const int total = 1 << (a.logL + glog);
+  // rows at or beyond L/2 are never read by the first pass when nin <= L/2
+  const bool zhi = a.npass > 0 && 2 * a.nin <= (1 << a.logL);
+  const int ltotal = 1 << ((zhi ? a.logL - 1 : a.logL) + glog);
+  for (int idx = threadIdx.x; idx < ltotal; idx += kNT) {
+    const int c = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    Vec<TIn, V> x;
+    if (c < a.nin && e0 + e < a.E) {
+      x = *(const Vec<TIn, V>*)(in + (size_t)c * a.E + e0 + e);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) x.v[v] = 0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      lds[(e + v) * a.lds_stride + lds_pos(c)] =
+          REDUCE ? reduce_u64((uint64_t)x.v[v], q, P.mu) : (uint32_t)x.v[v];
+  }
+  __syncthreads();
+  for (int ps = 0; ps < a.npass; ++ps) {
+    if (ps == 0 && zhi)
+      run_pass<true, true>(a, lds, P.tw_fwd + a.tw_off[ps], a.logL, ps, q);
+    else
+      run_pass<true, false>(a, lds, P.tw_fwd + a.tw_off[ps], a.logL, ps, q);
+    __syncthreads();
+  }
+  uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    if (e0 + e < a.E) {
+      Vec<uint32_t, V> y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.v[v] = lds[(e + v) * a.lds_stride + lds_pos(t)];
+      *(Vec<uint32_t, V>*)(out + (size_t)t * a.E + e0 + e) = y;
+    }
+  }
+}
+
+// Unsplit inverse transform: point-major input to coefficient-major output
+// (rows < nin).
+template <typename TOut, int V>
+__device__ __forceinline__ void inv_lds_tile(const NttLaunch& a, int prime, int eb,
+                                             uint32_t* lds) {
+  const PrimeConst& P = a.pc[prime];
+  const int EB = 1 << a.eb_log;
+  const int e0 = eb * EB;
+  const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
+  const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
+  const int total = 1 << (a.logL + glog);
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    Vec<uint32_t, V> x;
+    if (e0 + e < a.E) {
+      x = *(const Vec<uint32_t, V>*)(in + (size_t)t * a.E + e0 + e);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) x.v[v] = 0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[(e + v) * a.lds_stride + lds_pos(t)] = x.v[v];
+  }
+  __syncthreads();
+  for (int ps = a.npass - 1; ps >= 0; --ps) {
+    run_pass<false, false>(a, lds, P.tw_inv + a.tw_off[ps], a.logL, ps, P.q);
+    __syncthreads();
+  }
+  TOut* out = (TOut*)a.out + a.out_prime_stride * prime;
+  const int nout = a.nin << glog;
+  for (int idx = threadIdx.x; idx < nout; idx += kNT) {
+    const int c = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    if (e0 + e < a.E) {
+      Vec<TOut, V> y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.v[v] = (TOut)lds[(e + v) * a.lds_stride + lds_pos(c)];
+      *(Vec<TOut, V>*)(out + (size_t)c * a.E + e0 + e) = y;
+    }
+  }
+}
+
+// Split transforms, LDS part: block z of 2^blk_log consecutive positions of
+// the point-major buffer `out`, transformed in place by passes 1 .. npass-1
+// (forward, DIF) or npass-1 .. 1 (inverse, DIT).
+template <bool DIF, int V>
+__device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb, int z,
+                                           uint32_t* lds) {
+  const PrimeConst& P = a.pc[prime];
+  const int EB = 1 << a.eb_log;
+  const int e0 = eb * EB;
+  uint32_t* buf = (uint32_t*)a.out + a.out_prime_stride * prime + ((size_t)z << a.blk_log) * a.E;
+  const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
+  const int total = 1 << (a.blk_log + glog);
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    Vec<uint32_t, V> x;
+    if (e0 + e < a.E) {
+      x = *(const Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) x.v[v] = 0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[(e + v) * a.lds_stride + lds_pos(t)] = x.v[v];
+  }
+  __syncthreads();
+  if (DIF) {
+    for (int ps = 1; ps < a.npass; ++ps) {
+      run_pass<true, false>(a, lds, P.tw_fwd + a.tw_off[ps], a.blk_log, ps, P.q);
+      __syncthreads();
+    }
+  } else {
+    for (int ps = a.npass - 1; ps >= 1; --ps) {
+      run_pass<false, false>(a, lds, P.tw_inv + a.tw_off[ps], a.blk_log, ps, P.q);
+      __syncthreads();
+    }
+  }
+  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+    const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
+    if (e0 + e < a.E) {
+      Vec<uint32_t, V> y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.v[v] = lds[(e + v) * a.lds_stride + lds_pos(t)];
+      *(Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e) = y;
+    }
+  }
+}
+
+// First forward pass of a split transform, r stages at stride S = L / 2^r,
+// items [it0, it1) with stride `step`: item (j, e) reads rows j + u S
+// (u < 2^(r-1); the upper half is zero padding since nin <= L/2) of the
+// coefficient-major input and writes all 2^r rows of the point-major buffer.
+template <typename TIn, bool REDUCE, int r>
+__device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint32_t it0,
+                                             uint32_t it1, uint32_t step) {
+  constexpr int R = 1 << r;
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t q = P.q;
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E;
+  const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
+  uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
+  const Tw* tw = P.tw_fwd + a.tw_off[0];
+  for (uint32_t it = it0; it < it1; it += step) {
+    const uint32_t j = it / E, e = it - j * E;
+    uint32_t x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t row = j + u * S;
+      x[u] = 0;
+      if (u < R / 2 && row < (uint32_t)a.nin) {
+        const TIn v = in[(size_t)row * E + e];
+        x[u] = REDUCE ? reduce_u64((uint64_t)v, q, P.mu) : (uint32_t)v;
+      }
+    }
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+    butterflies<r, true, true>(x, t, q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) out[(size_t)(j + u * S) * E + e] = x[u];
+  }
+}
+
+// Last inverse pass of a split transform: item (j, e) reads rows j + u S of
+// the point-major buffer and writes the rows below nin of the
+// coefficient-major output.
+template <typename TOut, int r>
+__device__ __forceinline__ void col_inv_tile(const NttLaunch& a, int prime, uint32_t it0,
+                                             uint32_t it1, uint32_t step) {
+  constexpr int R = 1 << r;
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E;
+  const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
+  TOut* out = (TOut*)a.out + a.out_prime_stride * prime;
+  const Tw* tw = P.tw_inv + a.tw_off[0];
+  for (uint32_t it = it0; it < it1; it += step) {
+    const uint32_t j = it / E, e = it - j * E;
+    uint32_t x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) x[u] = in[(size_t)(j + u * S) * E + e];
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+    butterflies<r, false, false>(x, t, P.q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t row = j + u * S;
+      if (row < (uint32_t)a.nin) out[(size_t)row * E + e] = (TOut)x[u];
+    }
+  }
+}
+
+}  // namespace pm

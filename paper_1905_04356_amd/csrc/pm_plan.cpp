@@ -109,14 +109,14 @@ static int env_int(const char* name, int dflt, int lo, int hi) {
 const NttTune& ntt_tune() {
   static const NttTune T = {env_int("PM_TUNE_NTT_MAXR", 4, 2, 4),
                             env_int("PM_TUNE_NTT_LDS_LOG", 14, 11, 15),
-                            env_int("PM_TUNE_NTT_SPLIT", 5, 0, 5),
+                            env_int("PM_TUNE_NTT_SPLIT", 4, 0, 4),
                             env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16)};
   return T;
 }
 
 int split_stages(int logL) {
   const NttTune& T = ntt_tune();
-  if (T.split_r1 <= 0 || logL < T.split_min_log || T.split_r1 >= logL) return 0;
+  if (T.split_r1 < 2 || logL < T.split_min_log || T.split_r1 >= logL) return 0;
   return T.split_r1;
 }
 

@@ -38,7 +38,8 @@ PassPlan make_pass_plan(int logL);
 // Tuning of the transform kernels, read from the environment once:
 // PM_TUNE_NTT_MAXR (largest stages per LDS pass, 2..4, default 4),
 // PM_TUNE_NTT_LDS_LOG (log2 residues of LDS per workgroup, 11..15, default 14),
-// PM_TUNE_NTT_SPLIT (stages of the streaming column pass, 0 = none, default 5),
+// PM_TUNE_NTT_SPLIT (stages of the streaming column pass, 0 = none, else
+// 2..4, default 4),
 // PM_TUNE_NTT_SPLIT_MINLOG (smallest log2 L that is split, default 11).
 struct NttTune {
   int maxr, lds_log, split_r1, split_min_log;

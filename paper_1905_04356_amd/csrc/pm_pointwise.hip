@@ -1,55 +1,18 @@
-// pm_pointwise.hip -- the matrix products at the evaluation points.
-//
-// After evaluation, the polynomial-matrix product becomes L independent
-// products of an m x n by an n x k matrix over F_q, one per point
-// (Hyun, Neiger, Schost, ISSAC 2019, Section 2, "Polynomial matrix
-// multiplication": the n^omega d term of the evaluation/interpolation
-// bound; plain cubic products per point, Section 2, "Matrix
-// multiplication").  The factor L^{-1} of the inverse transform is applied
-// here, once per output value.
-//
-// VALU variant: one workgroup per point; the two matrices are staged in LDS,
-// each thread accumulates full 64-bit products in a 96-bit sum (64-bit low
-// word plus carry count) and reduces once per output.
-#include "pm_arith.h"
-#include "pm_kernels.h"
+// pm_pointwise.hip -- single-product pointwise kernels and launchers (the
+// per-workgroup work is in pm_pointwise_dev.h).
+#include "pm_pointwise_dev.h"
 
 namespace pm {
 
 template <bool STAGED>
 __global__ __launch_bounds__(256) void pointwise_valu_kernel(PointwiseLaunch a) {
   extern __shared__ uint32_t sm[];
-  const int t = blockIdx.x;
-  const int prime = blockIdx.y;
-  const PrimeConst& P = a.pc[prime];
-  const uint32_t q = P.q;
-  const size_t mn = (size_t)a.m * a.n, nk = (size_t)a.n * a.k, mk = (size_t)a.m * a.k;
-  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * mn;
-  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * nk;
-  uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * mk;
-  const uint32_t* sa = A;
-  const uint32_t* sb = B;
-  if (STAGED) {
-    for (size_t i = threadIdx.x; i < mn; i += blockDim.x) sm[i] = A[i];
-    for (size_t i = threadIdx.x; i < nk; i += blockDim.x) sm[mn + i] = B[i];
-    __syncthreads();
-    sa = sm;
-    sb = sm + mn;
-  }
-  // 2^64 mod q, to fold the carry count back in.
-  const uint64_t r64 = ((~0ull) % q + 1) % q;
-  for (size_t o = threadIdx.x; o < mk; o += blockDim.x) {
-    const int i = (int)(o / a.k), j = (int)(o % a.k);
-    uint64_t lo = 0;
-    uint32_t hi = 0;
-    for (int l = 0; l < a.n; ++l) {
-      const uint64_t prod = (uint64_t)sa[(size_t)i * a.n + l] * sb[(size_t)l * a.k + j];
-      lo += prod;
-      hi += lo < prod;
-    }
-    const uint32_t v = reduce_u64((uint64_t)hi * r64 + reduce_u64(lo, q, P.mu), q, P.mu);
-    C[o] = mul_shoup(v, P.linv, P.linv_p, q);
-  }
+  pointwise_valu_tile<STAGED>(a, blockIdx.x, blockIdx.y, sm);
+}
+
+__global__ __launch_bounds__(256) void pointwise_mfma_kernel(PointwiseLaunch a) {
+  extern __shared__ uint32_t smem[];
+  pointwise_mfma_tile(a, blockIdx.x, blockIdx.y, smem);
 }
 
 int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
@@ -68,126 +31,6 @@ int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   return hipGetLastError();
 }
 
-
-// ---- int8-MFMA variant ---------------------------------------------------------
-//
-// Exact products on the matrix cores.  A residue x in [0, q) is centred,
-// x' = x - q if x > q/2, so |x'| < 2^30, and written with four balanced
-// base-256 digits x' = sum_a x_a 256^a, x_a in [-128, 127]: adding
-// 0x80808080 turns x' into an unsigned word whose bytes are x_a + 128, so
-// (x' + 0x80808080) ^ 0x80808080 holds the four int8 digits.  Then
-//   A_t B_t = sum_{s=0..6} 256^s acc_s,   acc_s = sum_{a+b=s} A_a B_b,
-// 16 int8 GEMMs with int32 accumulation (|acc_s| <= 4 n 2^14 < 2^31 for
-// n < 2^15), recombined as sum_s c_s acc_s mod q in int64 with
-// c_s = 256^s L^{-1} mod q (exact while n < 2^13).
-//
-// One workgroup (4 waves) per point: the two matrices are loaded with
-// coalesced 16-byte reads, split, and stored as limb planes in LDS
-// (A: plane, row i, contraction index l; B transposed: plane, column j, l);
-// each wave then computes 16x16 output tiles with v_mfma_i32_16x16x64_i8.
-// Lane layout of that instruction (checked on gfx950): lane L supplies
-// A[L%16][16(L/16) + b] and B[16(L/16) + b][L%16] for bytes b < 16, and
-// receives C[4(L/16) + r][L%16] for r < 4.
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// Byte-transpose of four words: out[a] byte c = in[c] byte a.
-__device__ __forceinline__ void transpose4x4(const uint32_t in[4], uint32_t out[4]) {
-  // v_perm_b32(hi, lo, sel): selector bytes 0-3 pick from lo, 4-7 from hi.
-  const uint32_t t0 = __builtin_amdgcn_perm(in[1], in[0], 0x05010400u);  // in0.0 in1.0 in0.1 in1.1
-  const uint32_t t1 = __builtin_amdgcn_perm(in[1], in[0], 0x07030602u);  // in0.2 in1.2 in0.3 in1.3
-  const uint32_t t2 = __builtin_amdgcn_perm(in[3], in[2], 0x05010400u);
-  const uint32_t t3 = __builtin_amdgcn_perm(in[3], in[2], 0x07030602u);
-  out[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);  // t0.0 t0.1 t2.0 t2.1
-  out[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);  // t0.2 t0.3 t2.2 t2.3
-  out[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
-  out[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
-}
-
-__device__ __forceinline__ uint32_t limbs_of(uint32_t x, uint32_t q, uint32_t half_q) {
-  const uint32_t c = x > half_q ? x - q : x;  // centred, as a two's-complement word
-  return (c + 0x80808080u) ^ 0x80808080u;
-}
-
-__global__ __launch_bounds__(256) void pointwise_mfma_kernel(PointwiseLaunch a) {
-  extern __shared__ uint32_t smem[];
-  const int t = blockIdx.x;
-  const int prime = blockIdx.y;
-  const PrimeConst& P = a.pc[prime];
-  const uint32_t q = P.q, half_q = P.q >> 1;
-  const int m = a.m, n = a.n, k = a.k;
-  const int mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
-  const int rs = np + 16;                   // bytes per LDS row (padded)
-  uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
-  uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]
-  const size_t mn = (size_t)m * n, nk = (size_t)n * k, mk = (size_t)m * k;
-  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * mn;
-  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * nk;
-  uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * mk;
-
-  // A: each item is 4 consecutive l of one row i (n % 4 == 0).
-  const int ng = np >> 2;
-  for (int it = threadIdx.x; it < mp * ng; it += blockDim.x) {
-    const int i = it / ng, l0 = (it - i * ng) * 4;
-    uint32_t in[4] = {0, 0, 0, 0}, out[4];
-    if (i < m && l0 < n) {
-      const uint4 v = *(const uint4*)(A + (size_t)i * n + l0);
-      in[0] = limbs_of(v.x, q, half_q); in[1] = limbs_of(v.y, q, half_q);
-      in[2] = limbs_of(v.z, q, half_q); in[3] = limbs_of(v.w, q, half_q);
-    }
-    transpose4x4(in, out);
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * rs + l0) = out[pl];
-  }
-  // B transposed: item = column j, 4 consecutive l.
-  for (int it = threadIdx.x; it < kp * ng; it += blockDim.x) {
-    const int g = it / kp, j = it - g * kp, l0 = g * 4;
-    uint32_t in[4] = {0, 0, 0, 0}, out[4];
-    if (j < k && l0 < n) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) in[c] = limbs_of(B[(size_t)(l0 + c) * k + j], q, half_q);
-    }
-    transpose4x4(in, out);
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * rs + l0) = out[pl];
-  }
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tiles_m = mp >> 4, tiles = tiles_m * (kp >> 4);
-  const int lr = lane & 15, lk = (lane >> 4) * 16;
-  for (int tile = wave; tile < tiles; tile += 4) {
-    const int ti = tile % tiles_m, tj = tile / tiles_m;
-    v4i acc[7];
-#pragma unroll
-    for (int s = 0; s < 7; ++s) acc[s] = (v4i){0, 0, 0, 0};
-    for (int kc = 0; kc < np; kc += 64) {
-      v4i av[4], bv[4];
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        av[pl] = *(const v4i*)(As + (pl * mp + ti * 16 + lr) * rs + kc + lk);
-        bv[pl] = *(const v4i*)(Bs + (pl * kp + tj * 16 + lr) * rs + kc + lk);
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x + y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[x], bv[y], acc[x + y], 0, 0, 0);
-    }
-    const int j = tj * 16 + lr;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = ti * 16 + (lane >> 4) * 4 + r;
-      int64_t S = 0;
-#pragma unroll
-      for (int s = 0; s < 7; ++s) S += (int64_t)a.cs[prime][s] * (int64_t)acc[s][r];
-      const uint64_t mag = S < 0 ? (uint64_t)(-S) : (uint64_t)S;
-      uint32_t v = reduce_u64(mag, q, P.mu);
-      if (S < 0 && v) v = q - v;
-      if (i < m && j < k) C[(size_t)i * k + j] = v;
-    }
-  }
-}
 
 size_t pointwise_mfma_lds(int m, int n, int k) {
   const size_t mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;

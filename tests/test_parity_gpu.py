@@ -204,3 +204,58 @@ def test_mfma_limb_extremes():
     assert Bd.pm_plan(p, m, n, k, d, 4).pointwise == 1
     C = gpu_mul(p, A, B)
     assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
+
+
+def _batch_vs_single(p, shapes, seed, dtype=np.uint32, oracle_limit=1 << 26):
+    As, Bs, refs = [], [], []
+    for idx, (m, n, k, d) in enumerate(shapes):
+        A, B = tensors(p, m, n, k, d, seed=seed, product=idx, dtype=dtype)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        refs.append(polymat.mul(p, As[-1], Bs[-1]).clone())
+    torch.cuda.synchronize()
+    outs = polymat.mul_batched(p, As, Bs)
+    torch.cuda.synchronize()
+    for i, (C, R) in enumerate(zip(outs, refs)):
+        assert torch.equal(C, R), f"product {i} {shapes[i]} differs from its single call"
+    checked = 0
+    for (m, n, k, d), C, A, B in zip(shapes, outs, As, Bs):
+        if m * n * k * d * d <= oracle_limit:
+            ref = O.polymatmul(p, A.cpu().numpy(), B.cpu().numpy())
+            assert np.array_equal(C.cpu().numpy().astype(np.uint64), ref)
+            checked += 1
+        else:
+            Cn, An, Bn = C.cpu().numpy(), A.cpu().numpy(), B.cpu().numpy()
+            assert O.point_check(p, An, Bn, Cn, seed=seed, points=1)
+    return checked
+
+
+def test_batched_config3_distribution_subset():
+    """24 products drawn by the batched shape rule (degrees up to 8192, so
+    split and unsplit transforms and both pointwise kernels mix in one batch):
+    byte-identical to one call per product; oracle on the small ones, a
+    random-point check on the rest."""
+    shapes = [(min(m, 32), min(n, 32), min(k, 32), d) for (m, n, k, d) in
+              I.batched_shapes(3, 24)]
+    say(f"[parity] batched subset {shapes}")
+    _batch_vs_single(P30, shapes, seed=13)
+
+
+def test_batched_crt_u64_and_u32():
+    p = I.seeded_prime_60(5)
+    shapes = [(3, 4, 2, 40), (8, 8, 8, 300), (1, 1, 1, 1), (16, 32, 16, 1500), (5, 3, 7, 3000)]
+    say("[parity] batched CRT u64")
+    _batch_vs_single(p, shapes, seed=14, dtype=np.uint64)
+    say("[parity] batched CRT u32")
+    _batch_vs_single(P32, shapes, seed=15)
+
+
+def test_batched_single_product_and_repeats():
+    shapes = [(64, 64, 32, 4096)]
+    A, B = tensors(P31, 64, 64, 32, 4096, seed=16)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = polymat.mul(P31, tA, tB).clone()
+    for _ in range(2):
+        (C,) = polymat.mul_batched(P31, [tA], [tB])
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref)
