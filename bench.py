@@ -127,6 +127,63 @@ def cpu_baseline(p, A, B, m, n, k, d, target_s):
             "seconds": dt}
 
 
+def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
+    """Config 3: `count` products with the batched shape rule, all in one
+    batched call per step, against one pm_mul call per product on the same
+    stream (same inputs, outputs, device)."""
+    import torch
+
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+
+    dev = torch.device("cuda:0")
+    shapes = I.batched_shapes(seed, count)
+    As = [I.polymat_torch(seed, i, I.TENSOR_A, p, d, m, n, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    Bs = [I.polymat_torch(seed, i, I.TENSOR_B, p, d, n, k, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    outs = [torch.empty((2 * d - 1, m, k), dtype=torch.uint32, device=dev)
+            for (m, n, k, d) in shapes]
+    work = float(sum(m * n * k * d for (m, n, k, d) in shapes))
+    stream = torch.cuda.current_stream()
+    wsb = polymat.Workspace(dev)
+    for _ in range(warmup):
+        polymat.mul_batched(p, As, Bs, outs, workspace=wsb, stream=stream)
+    torch.cuda.synchronize()
+    Bd.pm_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        polymat.mul_batched(p, As, Bs, outs, workspace=wsb, stream=stream)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    kb = Bd.pm_profile_end()
+    batched_ws = wsb.buf.numel()
+    del wsb
+    wss = polymat.Workspace(dev)
+    for _ in range(warmup):
+        for A, B, C in zip(As, Bs, outs):
+            polymat.mul(p, A, B, out=C, workspace=wss, stream=stream)
+    torch.cuda.synchronize()
+    Bd.pm_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for A, B, C in zip(As, Bs, outs):
+            polymat.mul(p, A, B, out=C, workspace=wss, stream=stream)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / steps
+    ks = Bd.pm_profile_end()
+    return {"workload": f"{count} products, (m,k) uniform over pairs of {{4..128}} with k<=m, "
+                        f"n uniform, degrees log-uniform in [32, 8192], mod {p}, seed {seed}",
+            "value": work / t_b, "unit": "coefficient-MAC/s", "ms_per_batch": t_b * 1e3,
+            "device_ms_per_batch": kb["batched"][0] / steps,
+            "one_per_call_value": work / t_s, "one_per_call_ms": t_s * 1e3,
+            "speedup_vs_one_per_call": t_s / t_b, "sum_mnkd": work,
+            "batched_workspace_GB": batched_ws / 1e9, "steps": steps, "warmup": warmup,
+            "batched_kernel_ms": {kk: v[0] / steps for kk, v in kb.items() if v[1]},
+            "one_per_call_kernel_ms": {kk: v[0] / steps for kk, v in ks.items() if v[1]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +192,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every product on a single "
@@ -216,6 +275,11 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    del tA, tB, tC, ws
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batched_steps, 1)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, A, B, m, n, k, d, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -9,6 +9,7 @@
 // All primes of a CRT plan go through each phase in the same launch
 // (grid dimension y = prime).
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -168,6 +169,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
       pw.cs[i][t] = (uint32_t)w;
       w = (w << 8) % P.q[i];
     }
+    pw.bias[i] = ((1ull << 62) + P.q[i] - 1) / P.q[i] * P.q[i];
   }
 
   NttLaunch& ic = L->inv;
@@ -334,8 +336,19 @@ int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_
 struct HostSeg {
   BatchSeg g;
   uint32_t count;
-  double cost;  // per tile
+  double cost;     // per tile
+  uint32_t lds;    // bytes of LDS a tile needs
 };
+
+// LDS classes: tiles of one phase are launched in up to four groups so that
+// small tiles are not held to the occupancy of the largest.
+constexpr int kLdsClasses = 4;
+static const uint32_t kLdsClassMax[kLdsClasses] = {16 * 1024, 40 * 1024, 80 * 1024, 160 * 1024};
+int lds_class(uint32_t bytes) {
+  for (int c = 0; c < kLdsClasses; ++c)
+    if (bytes <= kLdsClassMax[c]) return c;
+  return kLdsClasses - 1;
+}
 
 size_t ntt_lds_bytes(const NttLaunch& a) { return 4 * (size_t)a.lds_stride << a.eb_log; }
 
@@ -350,8 +363,9 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
     h.g.zpts = zpts;
     h.count = count;
     h.cost = cost;
+    h.lds = (uint32_t)need;
     ph[phase].push_back(h);
-    if (need > lds[phase]) lds[phase] = need;
+    (void)lds;
   };
   const uint32_t L_ = 1u << P.logL;
   for (int op = 0; op < 2; ++op) {
@@ -372,8 +386,14 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
     }
   }
   {
+    // points per tile: about PM_TUNE_BATCH_PW_WORK (default 8192) MACs of work
+    static const double pw_work = [] {
+      const char* v = getenv("PM_TUNE_BATCH_PW_WORK");
+      const double x = v && *v ? atof(v) : 8192.0;
+      return x < 1.0 ? 1.0 : x;
+    }();
     const double mnk = (double)P.m * P.n * P.k;
-    uint32_t z = (uint32_t)(65536.0 / mnk);
+    uint32_t z = (uint32_t)(pw_work / mnk);
     if (z < 1) z = 1;
     if (z > L_) z = L_;
     if (z > 65535) z = 65535;
@@ -412,29 +432,36 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
   std::vector<uint8_t> host(lay.total - lay.prod_off, 0);
   ProductLaunches* hp = (ProductLaunches*)host.data();
   std::vector<HostSeg> ph[kBatchPhases];
-  size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};
+  size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
     int st = fill_product_launches(plans[i], prods[i].A, prods[i].B, prods[i].C, ws + offs[i],
                                    &hp[i]);
     if (st != PM_OK) return st;
     product_segments((uint32_t)i, plans[i], hp[i], ph, lds);
   }
-  // Per phase: largest tiles first, then prefix sums of tile counts.
+  // Per phase and LDS class: largest tiles first, then prefix sums of tile
+  // counts; one launch per non-empty (phase, class).
   BatchSeg* hs = (BatchSeg*)(host.data() + (lay.seg_off - lay.prod_off));
+  struct Group { int phase; uint64_t first_seg, nseg, tiles; uint32_t lds; };
+  std::vector<Group> groups;
   uint64_t seg_base = 0;
-  uint64_t phase_first_seg[kBatchPhases], phase_tiles[kBatchPhases];
   for (int f = 0; f < kBatchPhases; ++f) {
-    std::stable_sort(ph[f].begin(), ph[f].end(),
-                     [](const HostSeg& a, const HostSeg& b) { return a.cost > b.cost; });
-    uint64_t first = 0;
-    phase_first_seg[f] = seg_base;
-    for (auto& h : ph[f]) {
-      h.g.first = (uint32_t)first;
-      first += h.count;
-      hs[seg_base++] = h.g;
+    std::vector<HostSeg> cls[kLdsClasses];
+    for (auto& h : ph[f]) cls[lds_class(h.lds)].push_back(h);
+    for (int c = 0; c < kLdsClasses; ++c) {
+      if (cls[c].empty()) continue;
+      std::stable_sort(cls[c].begin(), cls[c].end(),
+                       [](const HostSeg& a, const HostSeg& b) { return a.cost > b.cost; });
+      Group G{f, seg_base, cls[c].size(), 0, 0};
+      for (auto& h : cls[c]) {
+        h.g.first = (uint32_t)G.tiles;
+        G.tiles += h.count;
+        if (h.lds > G.lds) G.lds = h.lds;
+        hs[seg_base++] = h.g;
+      }
+      if (G.tiles > 0x7fffffffull) return PM_ERANGE;
+      groups.push_back(G);
     }
-    if (first > 0x7fffffffull) return PM_ERANGE;
-    phase_tiles[f] = first;
   }
   if (seg_base > lay.nseg) return PM_EINVAL;
   if (hipMemcpyAsync(ws + lay.prod_off, host.data(), host.size(), hipMemcpyHostToDevice, s) !=
@@ -442,11 +469,13 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
     return PM_EDEVICE;
   const ProductLaunches* dprods = (const ProductLaunches*)(ws + lay.prod_off);
   const BatchSeg* dsegs = (const BatchSeg*)(ws + lay.seg_off);
+  static const int kind_of_phase[kBatchPhases] = {K_NTT_FWD, K_NTT_FWD, K_POINTWISE,
+                                                  K_NTT_INV, K_NTT_INV, K_CRT};
   KernelTimer kt(K_BATCHED, s);
-  for (int f = 0; f < kBatchPhases; ++f) {
-    if (phase_tiles[f] == 0) continue;
-    if (launch_batch_phase(f, dprods, dsegs + phase_first_seg[f], (int)ph[f].size(),
-                           (uint32_t)phase_tiles[f], lds[f], s) != hipSuccess)
+  for (const Group& G : groups) {
+    KernelTimer kp(kind_of_phase[G.phase], s);
+    if (launch_batch_phase(G.phase, dprods, dsegs + G.first_seg, (int)G.nseg,
+                           (uint32_t)G.tiles, G.lds, s) != hipSuccess)
       return PM_EDEVICE;
   }
   return PM_OK;

@@ -46,6 +46,7 @@ struct PointwiseLaunch {
   uint32_t* chat;
   PrimeConst pc[kMaxPrimes];
   uint32_t cs[kMaxPrimes][8];  // MFMA variant: 256^s L^{-1} mod q, s < 7
+  uint64_t bias[kMaxPrimes];   // MFMA variant: a multiple of q in [2^62, 2^62 + q)
 };
 
 // Chinese remaindering of r residue arrays (u32, `count` each, stride

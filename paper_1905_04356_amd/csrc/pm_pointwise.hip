@@ -10,7 +10,8 @@ __global__ __launch_bounds__(256) void pointwise_valu_kernel(PointwiseLaunch a) 
   pointwise_valu_tile<STAGED>(a, blockIdx.x, blockIdx.y, sm);
 }
 
-__global__ __launch_bounds__(256) void pointwise_mfma_kernel(PointwiseLaunch a) {
+template <int NT>
+__global__ __launch_bounds__(NT) void pointwise_mfma_kernel(PointwiseLaunch a) {
   extern __shared__ uint32_t smem[];
   pointwise_mfma_tile(a, blockIdx.x, blockIdx.y, smem);
 }
@@ -37,14 +38,19 @@ size_t pointwise_mfma_lds(int m, int n, int k) {
   return 4 * (mp + kp) * (np + 16);
 }
 
+// Up to 64 KiB of limb planes: 256 threads, several workgroups per CU; larger
+// shapes take most of the LDS, so one workgroup of 512 threads per CU.
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   const size_t lds = pointwise_mfma_lds(a.m, a.n, a.k);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)pointwise_mfma_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds <= 64 * 1024) {
+    hipLaunchKernelGGL(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(pointwise_mfma_kernel, dim3(a.L, nprimes), dim3(256), lds, s, a);
+  hipError_t e = hipFuncSetAttribute((const void*)pointwise_mfma_kernel<512>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pointwise_mfma_kernel<512>, dim3(a.L, nprimes), dim3(512), lds, s, a);
   return hipGetLastError();
 }
 

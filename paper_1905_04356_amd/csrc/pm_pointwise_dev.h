@@ -61,7 +61,7 @@ __device__ __forceinline__ void pointwise_valu_tile(const PointwiseLaunch& a, in
 //   A_t B_t = sum_{s=0..6} 256^s acc_s,   acc_s = sum_{a+b=s} A_a B_b,
 // 16 int8 GEMMs with int32 accumulation (|acc_s| <= 4 n 2^14 < 2^31 for
 // n < 2^15), recombined as sum_s c_s acc_s mod q in int64 with
-// c_s = 256^s L^{-1} mod q (exact while n < 2^13).
+// c_s = 256^s L^{-1} mod q (|sum| < n 2^49, exact while n < 2^13).
 //
 // One workgroup (4 waves) per point: the two matrices are loaded with
 // coalesced 16-byte reads, split, and stored as limb planes in LDS
@@ -100,42 +100,54 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
   const int rs = np + 16;                   // bytes per LDS row (padded)
   uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
   uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]
-  const size_t mn = (size_t)m * n, nk = (size_t)n * k, mk = (size_t)m * k;
-  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * mn;
-  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * nk;
-  uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * mk;
+  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * ((size_t)m * n);
+  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * ((size_t)n * k);
+  uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * ((size_t)m * k);
+  const int nt = blockDim.x;
+  const int ng = np >> 2;                   // groups of 4 contraction indices (multiple of 16)
+  const int l16 = threadIdx.x & 15, r16 = threadIdx.x >> 4, nr = nt >> 4;
 
-  // A: each item is 4 consecutive l of one row i (n % 4 == 0).
-  const int ng = np >> 2;
-  for (int it = threadIdx.x; it < mp * ng; it += blockDim.x) {
-    const int i = it / ng, l0 = (it - i * ng) * 4;
-    uint32_t in[4] = {0, 0, 0, 0}, out[4];
-    if (i < m && l0 < n) {
-      const uint4 v = *(const uint4*)(A + (size_t)i * n + l0);
-      in[0] = limbs_of(v.x, q, half_q); in[1] = limbs_of(v.y, q, half_q);
-      in[2] = limbs_of(v.z, q, half_q); in[3] = limbs_of(v.w, q, half_q);
-    }
-    transpose4x4(in, out);
+  // A: row i, 4 consecutive l per item; 16 lanes cover 64 consecutive l.
+  for (int i = r16; i < mp; i += nr) {
+    for (int g = l16; g < ng; g += 16) {
+      const int l0 = g * 4;
+      uint32_t in[4] = {0, 0, 0, 0}, out[4];
+      if (i < m && l0 < n) {
+        const uint4 v = *(const uint4*)(A + i * n + l0);
+        in[0] = limbs_of(v.x, q, half_q); in[1] = limbs_of(v.y, q, half_q);
+        in[2] = limbs_of(v.z, q, half_q); in[3] = limbs_of(v.w, q, half_q);
+      }
+      transpose4x4(in, out);
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * rs + l0) = out[pl];
+      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * rs + l0) = out[pl];
+    }
   }
-  // B transposed: item = column j, 4 consecutive l.
-  for (int it = threadIdx.x; it < kp * ng; it += blockDim.x) {
-    const int g = it / kp, j = it - g * kp, l0 = g * 4;
-    uint32_t in[4] = {0, 0, 0, 0}, out[4];
-    if (j < k && l0 < n) {
+  // B transposed: column j, 4 consecutive l; 16 lanes cover 16 consecutive j.
+  for (int g = r16; g < ng; g += nr) {
+    const int l0 = g * 4;
+    for (int j = l16; j < kp; j += 16) {
+      uint32_t in[4] = {0, 0, 0, 0}, out[4];
+      if (j < k && l0 < n) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) in[c] = limbs_of(B[(size_t)(l0 + c) * k + j], q, half_q);
+        for (int c = 0; c < 4; ++c) in[c] = limbs_of(B[(l0 + c) * k + j], q, half_q);
+      }
+      transpose4x4(in, out);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * rs + l0) = out[pl];
     }
-    transpose4x4(in, out);
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * rs + l0) = out[pl];
   }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = nt >> 6;
   const int tiles_m = mp >> 4, tiles = tiles_m * (kp >> 4);
   const int lr = lane & 15, lk = (lane >> 4) * 16;
+  // c_s < q < 2^31, so each weight is a non-negative int32 and each term a
+  // single signed 32x32->64 multiply-add; the bias (a multiple of q, at least
+  // 2^62) makes the sum non-negative for the unsigned Barrett reduction.
+  int32_t cs[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) cs[s] = (int32_t)a.cs[prime][s];
+  const uint64_t bias = a.bias[prime];
   for (int tile = wave; tile < tiles; tile += nwaves) {
     const int ti = tile % tiles_m, tj = tile / tiles_m;
     v4i acc[7];
@@ -158,16 +170,13 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = ti * 16 + (lane >> 4) * 4 + r;
-      int64_t S = 0;
+      int64_t S = (int64_t)bias;
 #pragma unroll
-      for (int s = 0; s < 7; ++s) S += (int64_t)a.cs[prime][s] * (int64_t)acc[s][r];
-      const uint64_t mag = S < 0 ? (uint64_t)(-S) : (uint64_t)S;
-      uint32_t v = reduce_u64(mag, q, P.mu);
-      if (S < 0 && v) v = q - v;
-      if (i < m && j < k) C[(size_t)i * k + j] = v;
+      for (int s = 0; s < 7; ++s) S += (int64_t)cs[s] * (int64_t)acc[s][r];
+      const uint32_t v = reduce_u64((uint64_t)S, q, P.mu);
+      if (i < m && j < k) C[i * k + j] = v;
     }
   }
 }
-
 
 }  // namespace pm

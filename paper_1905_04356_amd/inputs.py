@@ -90,6 +90,59 @@ def uniform_residues(seed: int, stream: int, count: int, p: int,
         return _mulhi64_np(_mix64_np(z), p)
 
 
+def _to_i64(v: int) -> int:
+    """A 64-bit pattern as a signed Python int (for torch.int64 constants)."""
+    v &= MASK64
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def uniform_residues_torch(seed: int, stream: int, count: int, p: int, device,
+                           start: int = 0):
+    """Same values as uniform_residues, computed with torch int64 tensors on
+    `device` (wrapping products and logical shifts give the unsigned bits).
+    Returns an int64 tensor holding values in [0, p), p < 2^63."""
+    import torch
+    if not (2 <= p < (1 << 63)):
+        raise ValueError("modulus out of range")
+
+    def lsr(x, s):
+        return (x >> s) & ((1 << (64 - s)) - 1)
+
+    m32 = 0xFFFFFFFF
+    key = _to_i64(stream_key(seed, stream))
+    e = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z = e * _to_i64(GOLDEN) + key
+    z = (z ^ lsr(z, 30)) * _to_i64(_M1)
+    z = (z ^ lsr(z, 27)) * _to_i64(_M2)
+    z = z ^ lsr(z, 31)
+    a0 = z & m32
+    a1 = lsr(z, 32)
+    p0, p1 = p & m32, p >> 32
+    t = a0 * p0
+    k = lsr(t, 32)
+    t = a1 * p0 + k
+    w1 = t & m32
+    w2 = lsr(t, 32)
+    t = a0 * p1 + w1
+    k = lsr(t, 32)
+    return a1 * p1 + w2 + k
+
+
+def polymat_torch(seed: int, product: int, tensor: int, p: int, deg: int, rows: int,
+                  cols: int, device, dtype=None):
+    """polymat() generated on `device`; dtype torch.uint32 (default) or
+    torch.uint64."""
+    import torch
+    dtype = dtype or torch.uint32
+    x = uniform_residues_torch(seed, product_stream(product, tensor), deg * rows * cols, p,
+                               device)
+    if dtype == torch.uint32:
+        x = x.to(torch.int32).view(torch.uint32)
+    else:
+        x = x.view(torch.uint64)
+    return x.reshape(deg, rows, cols)
+
+
 def uniform_residue_at(seed: int, stream: int, index: int, p: int) -> int:
     """Scalar version of uniform_residues for one index (pure Python ints)."""
     z = (stream_key(seed, stream) + (index + 1) * GOLDEN) & MASK64

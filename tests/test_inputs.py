@@ -68,3 +68,14 @@ def test_poisson_rate():
     t = I.poisson_arrivals(1, 2000.0, 2.0)
     assert abs(len(t) - 4000) < 300
     assert all(a < b for a, b in zip(t, t[1:]))
+
+
+def test_torch_generator_matches_numpy_on_cpu():
+    import torch
+    for p in (2, 97, 998244353, 2013265921, 4294967291, (1 << 62) - 57):
+        a = I.uniform_residues(9, 4, 5000, p, start=3)
+        b = I.uniform_residues_torch(9, 4, 5000, p, "cpu", start=3).numpy().astype(np.uint64)
+        assert np.array_equal(a, b), p
+    x = I.polymat_torch(2, 5, I.TENSOR_B, 4294967291, 7, 3, 5, "cpu")
+    assert x.dtype == torch.uint32
+    assert np.array_equal(x.numpy(), I.polymat(2, 5, I.TENSOR_B, 4294967291, 7, 3, 5))

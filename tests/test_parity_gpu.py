@@ -181,7 +181,8 @@ def test_check_residues():
 
 @pytest.mark.parametrize("m,n,k,d", [(8, 8, 8, 256), (16, 64, 16, 100), (5, 12, 7, 33),
                                      (17, 4, 33, 65), (64, 64, 32, 64), (3, 128, 2, 20),
-                                     (32, 68, 48, 9)])
+                                     (32, 68, 48, 9), (128, 128, 128, 6), (128, 64, 96, 5),
+                                     (20, 252, 3, 2)])
 @pytest.mark.parametrize("p", [P30, P31, P32])
 def test_pointwise_variants_match_oracle(p, m, n, k, d, monkeypatch):
     """Both pointwise kernels (int8-MFMA limbs and VALU) against the oracle."""
@@ -259,3 +260,43 @@ def test_batched_single_product_and_repeats():
         (C,) = polymat.mul_batched(P31, [tA], [tB])
         torch.cuda.synchronize()
         assert torch.equal(C, ref)
+
+
+def test_config3_full_batch_sampled():
+    """Config 3 at full size and in the launch configuration the benchmark
+    times: 512 products (batched shape rule, seed 3) in one batched call.
+    Checks: the device generator reproduces the host generator; 16 seeded
+    products are byte-identical to their single calls; 12 seeded products
+    against the oracle (whole product when small, else 2 whole output entries
+    plus a random-point check when affordable)."""
+    p, seed = P30, 3
+    shapes = I.batched_shapes(seed, 512)
+    dev = torch.device("cuda")
+    say("[parity] config 3 full batch: generating")
+    As = [I.polymat_torch(seed, i, I.TENSOR_A, p, d, m, n, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    Bs = [I.polymat_torch(seed, i, I.TENSOR_B, p, d, n, k, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    m0, n0, k0, d0 = shapes[5]
+    assert np.array_equal(Bs[5].cpu().numpy(), I.polymat(seed, 5, I.TENSOR_B, p, d0, n0, k0))
+    say("[parity] config 3 full batch: batched call")
+    outs = polymat.mul_batched(p, As, Bs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(512, size=16, replace=False):
+        R = polymat.mul(p, As[i], Bs[i])
+        torch.cuda.synchronize()
+        assert torch.equal(R, outs[i]), f"product {i} {shapes[i]}"
+    for i in rng.choice(512, size=12, replace=False):
+        m, n, k, d = shapes[i]
+        A, B, C = As[i].cpu().numpy(), Bs[i].cpu().numpy(), outs[i].cpu().numpy()
+        say(f"[parity] config 3 product {i} {shapes[i]}")
+        if m * n * k * d * d <= 1 << 31:
+            assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
+            continue
+        pairs = I.sample_pairs(seed + int(i), m, k, 2)
+        ref = O.polymatmul_entries(p, A, B, pairs)
+        for s, (a, b) in enumerate(pairs):
+            assert np.array_equal(C[:, a, b].astype(np.uint64), ref[s])
+        if d * (m * n + n * k + m * k) < 40_000_000:
+            assert O.point_check(p, A, B, C, seed=int(i), points=1)
