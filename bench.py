@@ -184,6 +184,142 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
             "one_per_call_kernel_ms": {kk: v[0] / steps for kk, v in ks.items() if v[1]}}
 
 
+KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing
+    ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_block_kernel<true", "ntt_fwd"),
+    ("ntt_fwd_kernel", "ntt_fwd"), ("pointwise", "pointwise"),
+    ("ntt_block_kernel<false", "ntt_inv"), ("ntt_col_inv_kernel", "ntt_inv"),
+    ("ntt_inv_kernel", "ntt_inv"), ("crt_kernel", "crt"), ("batch_kernel", "batched"))
+
+
+def kind_of(name):
+    for frag, kind in KERNEL_KIND_OF:
+        if frag in name:
+            return kind
+    return None
+
+
+def source_hash():
+    """Hash of the library sources, so counters taken on older kernels are
+    not reused."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1905_04356_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_profiles(root, steps_stats, steps_pmc, workload):
+    """Turn rocprofv3 CSV output under `root` (st/: --kernel-trace --stats,
+    f/ and w/: --pmc FETCH_SIZE / WRITE_SIZE of the benchmark, cf/ and cw/:
+    the same counters on the calibration copy) into profiles/ summaries."""
+    import collections
+    import csv
+
+    def rows(sub, name):
+        import glob
+        files = glob.glob(os.path.join(root, sub, f"*{name}*.csv"))
+        return list(csv.DictReader(open(files[0]))) if files else []
+
+    stats = rows("st", "kernel_stats")
+    per_kind = collections.defaultdict(lambda: [0.0, 0])
+    lines = []
+    for r in stats:
+        kd = kind_of(r["Name"])
+        lines.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                      float(r["TotalDurationNs"]) / 1e6, kd))
+        if kd:
+            per_kind[kd][0] += float(r["TotalDurationNs"]) / 1e6
+            per_kind[kd][1] += int(r["Calls"])
+
+    def counter(sub, cname):
+        out = collections.defaultdict(float)
+        for r in rows(sub, "counter_collection"):
+            if r["Counter_Name"] == cname:
+                out[r["Kernel_Name"]] += float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+        return out
+
+    # the calibration run also fills its source tensor; only the copies count
+    cal_bytes = 3 * (256 << 20) * 4
+    cf = sum(v for k, v in counter("cf", "FETCH_SIZE").items() if "copy" in k.lower())
+    cw = sum(v for k, v in counter("cw", "WRITE_SIZE").items() if "copy" in k.lower())
+    fscale = cal_bytes / cf if cf else None
+    wscale = cal_bytes / cw if cw else None
+    fetch, write = counter("f", "FETCH_SIZE"), counter("w", "WRITE_SIZE")
+    traffic = collections.defaultdict(float)
+    for name, v in fetch.items():
+        if kind_of(name) and fscale:
+            traffic[kind_of(name)] += v * fscale / steps_pmc
+    for name, v in write.items():
+        if kind_of(name) and wscale:
+            traffic[kind_of(name)] += v * wscale / steps_pmc
+    cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
+              f"python3 bench.py --steps {steps_stats} --warmup 2 --no-cpu-baseline --no-batched")
+    md = [f"# Kernel profile: {workload}", "",
+          "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
+          "| kernel | calls | avg us | total ms | kind |", "|---|---|---|---|---|"]
+    for name, calls, avg, tot, kd in sorted(lines, key=lambda x: -x[3]):
+        md.append(f"| `{name}` | {calls} | {avg:.1f} | {tot:.3f} | {kd} |")
+    md += ["", f"Per benchmark step ({steps_stats} timed + 2 warm-up steps profiled):", "",
+           "| kind | device ms per step |", "|---|---|"]
+    for kd, (tot, calls) in sorted(per_kind.items()):
+        md.append(f"| {kd} | {tot / (steps_stats + 2):.4f} |")
+    md += ["", "## HBM traffic (rocprofv3 --pmc)", "",
+           "Commands:", "", "```"]
+    for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
+        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
+                  f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
+                  "--no-cpu-baseline --no-batched")
+    for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
+        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
+                  f"-o {sub} -- python3 bench.py --calibration-copy")
+    md += ["```", "",
+           f"Calibration: a plain copy of 3 x 1 GiB reads back FETCH_SIZE x {fscale:.3f} and "
+           f"WRITE_SIZE x {wscale:.3f} of the bytes it moves; these factors scale the kernels' "
+           "counters below.", "", "| kind | HBM bytes per step (fetch + write, scaled) |",
+           "|---|---|"]
+    for kd, b in sorted(traffic.items()):
+        md.append(f"| {kd} | {b / 1e6:.1f} MB |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{workload}_kernels.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    with open(os.path.join(ROOT, "profiles", f"{workload}_traffic.json"), "w") as f:
+        json.dump({"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+                   "bytes_per_step": dict(traffic),
+                   "device_ms_per_step": {k: v[0] / (steps_stats + 2)
+                                          for k, v in per_kind.items()}}, f, indent=1)
+    print("wrote profiles for", workload)
+
+
+def load_traffic(workload):
+    """Per-step HBM bytes by kernel kind from profiles/, or None when the
+    library sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_step")
+
+
+def calibration_copy():
+    """A plain device copy of known size (1 GiB, three times), the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 256 << 20
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes_per_launch": n * 4, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,7 +330,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run only the 1 GiB copy used to calibrate HBM byte counters")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 CSV output in DIR")
     args = ap.parse_args()
+    if args.calibration_copy:
+        calibration_copy()
+        return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, 10, 3, args.workload)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every product on a single "
               "MI355X and has no multi-GPU path (see the sharding design).", file=sys.stderr)
@@ -250,6 +396,9 @@ def main():
                          launches / args.steps, "algorithmic_bytes": byts,
                          "ops": ops}
         kernels[kind]["roofline"] = roofline_for(kind, byts, ops, sec, plan)
+    traffic = load_traffic(args.workload)
+    for kind in kernels:
+        kernels[kind]["roofline"]["traffic"] = traffic.get(kind) if traffic else None
     dominant = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
     roof = dict(kernels[dominant]["roofline"])
 

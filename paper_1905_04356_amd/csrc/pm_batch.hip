@@ -77,9 +77,9 @@ __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, ui
   }
 }
 
-template <int PHASE>
-__global__ __launch_bounds__(kBatchNT) void batch_kernel(const ProductLaunches* prods,
-                                                         const BatchSeg* segs, int nseg) {
+template <int PHASE, int NT>
+__global__ __launch_bounds__(NT) void batch_kernel(const ProductLaunches* prods,
+                                                   const BatchSeg* segs, int nseg) {
   extern __shared__ uint32_t lds[];
   const uint32_t b = blockIdx.x;
   const BatchSeg g = segs[find_segment(segs, nseg, b)];
@@ -117,29 +117,34 @@ __global__ __launch_bounds__(kBatchNT) void batch_kernel(const ProductLaunches* 
   }
 }
 
-template <int PHASE>
+template <int PHASE, int NT>
 static int launch_phase_t(const ProductLaunches* prods, const BatchSeg* segs, int nseg,
                           uint32_t ntiles, size_t lds, hipStream_t s) {
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)batch_kernel<PHASE>,
+    hipError_t e = hipFuncSetAttribute((const void*)batch_kernel<PHASE, NT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(batch_kernel<PHASE>, dim3(ntiles), dim3(kBatchNT), lds, s, prods, segs,
+  hipLaunchKernelGGL((batch_kernel<PHASE, NT>), dim3(ntiles), dim3(NT), lds, s, prods, segs,
                      nseg);
   return hipGetLastError();
 }
 
 int launch_batch_phase(int phase, const ProductLaunches* prods, const BatchSeg* segs, int nseg,
                        uint32_t ntiles, size_t lds, hipStream_t s) {
+  // The transform tiles are written for kBatchNT threads; pointwise tiles
+  // that fit in 64 KiB of LDS run with 256 threads so more of them share a CU
+  // (as in the single-product launch).
   switch (phase) {
-    case 0: return launch_phase_t<0>(prods, segs, nseg, ntiles, lds, s);
-    case 1: return launch_phase_t<1>(prods, segs, nseg, ntiles, lds, s);
-    case 2: return launch_phase_t<2>(prods, segs, nseg, ntiles, lds, s);
-    case 3: return launch_phase_t<3>(prods, segs, nseg, ntiles, lds, s);
-    case 4: return launch_phase_t<4>(prods, segs, nseg, ntiles, lds, s);
-    default: return launch_phase_t<5>(prods, segs, nseg, ntiles, lds, s);
+    case 0: return launch_phase_t<0, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    case 1: return launch_phase_t<1, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    case 2:
+      if (lds <= 64 * 1024) return launch_phase_t<2, 256>(prods, segs, nseg, ntiles, lds, s);
+      return launch_phase_t<2, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    case 3: return launch_phase_t<3, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    case 4: return launch_phase_t<4, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    default: return launch_phase_t<5, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
   }
 }
 
