@@ -307,6 +307,36 @@ def load_traffic(workload):
     return t.get("bytes_per_step")
 
 
+def bench_serving(seconds, seed=5, rate=2000.0, pool_size=64, p=998244353,
+                  budget_gb=64.0, streams=4):
+    """Config 5: Poisson arrivals (`rate` per second) of products with the
+    batched shape rule, operands and their evaluations resident in a pool;
+    continuous batching vs one pm_mul call per request on the same trace."""
+    import torch
+
+    from paper_1905_04356_amd import serving as S
+
+    dev = torch.device("cuda:0")
+    pool = S.make_pool(p, seed, pool_size, dev, with_evals=True)
+    # warm-up: a short trace through both servers (table builds, allocator)
+    wa, wi = S.trace(seed + 1000, rate, 0.5, pool_size)
+    S.Server(p, pool, int(budget_gb * 2 ** 30), streams=streams).run(wa, wi)
+    S.run_fifo(p, pool, wa, wi)
+    torch.cuda.synchronize()
+    arrivals, items = S.trace(seed, rate, seconds, pool_size)
+    srv = S.Server(p, pool, int(budget_gb * 2 ** 30), streams=streams)
+    cb = srv.run(arrivals, items)
+    torch.cuda.synchronize()
+    fifo, _ = S.run_fifo(p, pool, arrivals, items)
+    torch.cuda.synchronize()
+    offered = sum(pool[i].m * pool[i].n * pool[i].k * pool[i].d for i in items) / seconds
+    return {"workload": f"Poisson {rate:g} req/s for {seconds:g} s, {pool_size} resident operand "
+                        f"pairs (batched shape rule, seed {seed}), mod {p}",
+            "offered_coef_mac_per_s": offered,
+            "continuous_batching": cb, "one_call_per_request": fifo,
+            "budget_GB": budget_gb, "streams": streams}
+
+
 def calibration_copy():
     """A plain device copy of known size (1 GiB, three times), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -330,6 +360,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the serving trace (0: skip)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run only the 1 GiB copy used to calibrate HBM byte counters")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -428,6 +460,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_steps, 1)
+        torch.cuda.empty_cache()
+    if args.serving_seconds > 0:
+        out["serving"] = bench_serving(args.serving_seconds)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, A, B, m, n, k, d, args.cpu_seconds)

@@ -71,7 +71,7 @@ typedef enum pm_status {
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 1
+#define PM_ABI_VERSION 2
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -112,13 +112,35 @@ pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                      const uint64_t* A, const uint64_t* B, uint64_t* C,
                      void* workspace, uint64_t workspace_bytes, void* stream);
 
-/* One product of a batch; the pointers follow the pm_mul_* layout rules. */
+/* One product of a batch; the pointers follow the pm_mul_* layout rules.
+ * A_eval / B_eval: optional evaluations of A / B made by pm_eval_* (NULL:
+ * the batch transforms the operand itself).  Given evaluations are used in
+ * place of A / B, which are then not read (but must still be valid
+ * pointers for the overlap checks). */
 typedef struct pm_product {
   int32_t m, n, k, d;
   const void* A;
   const void* B;
   void* C;
+  const void* A_eval;
+  const void* B_eval;
 } pm_product;
+
+/* Evaluations of one operand at the points of the product's transform: the
+ * precomputation that the paper's "multiplier classes" keep for repeated
+ * products by the same matrix (Section 2, "Polynomial matrix
+ * multiplication").  role 0: X is a left operand (rows = m, cols = n);
+ * role 1: a right operand (rows = n, cols = k).  X: d*rows*cols residues,
+ * coefficient-major, device memory.  The result (X_eval, device memory of at
+ * least pm_eval_bytes bytes, 256-byte aligned, owned by the caller) serves
+ * every product with the same p, contraction length n and degree bound d,
+ * through pm_product.A_eval / B_eval.  Asynchronous on `stream`. */
+pm_status pm_eval_bytes(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                        int32_t elem_bytes, uint64_t* out);
+pm_status pm_eval_u32(uint32_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                      const uint32_t* X, void* X_eval, uint64_t eval_bytes, void* stream);
+pm_status pm_eval_u64(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                      const uint64_t* X, void* X_eval, uint64_t eval_bytes, void* stream);
 
 /* Workspace bytes for pm_mul_batched_* over `count` products (host array). */
 pm_status pm_batched_workspace_bytes(uint64_t p, int32_t count,

@@ -24,8 +24,9 @@ PM_EBUSY = -7
 # Every symbol include/pm.h declares.
 EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
-           "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_check_residues",
-           "pm_profile_begin", "pm_profile_end", "pm_sync")
+           "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_eval_bytes", "pm_eval_u32",
+           "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
+           "pm_sync")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
@@ -49,7 +50,8 @@ class pm_kernel_stats(ctypes.Structure):
 class pm_product(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
-                ("C", ctypes.c_void_p)]
+                ("C", ctypes.c_void_p), ("A_eval", ctypes.c_void_p),
+                ("B_eval", ctypes.c_void_p)]
 
 
 _lib = None
@@ -79,11 +81,15 @@ def lib():
     L.pm_mul_batched_u64.argtypes = [u64, i32, ctypes.POINTER(pm_product), vp, u64, vp]
     L.pm_check_residues.argtypes = [u64, vp, u64, i32, ctypes.POINTER(u64), vp, vp]
     L.pm_sync.argtypes = [vp]
+    L.pm_eval_bytes.argtypes = [u64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_eval_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, u64, vp]
+    L.pm_eval_u64.argtypes = [u64, i32, i32, i32, i32, vp, vp, u64, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
-                 "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end"):
+                 "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
+                 "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -122,10 +128,14 @@ def pm_mul_u64(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
 
 
 def products_array(prods) -> ctypes.Array:
-    """(m, n, k, d, A_ptr, B_ptr, C_ptr) tuples -> pm_product[count]."""
+    """(m, n, k, d, A_ptr, B_ptr, C_ptr[, A_eval_ptr, B_eval_ptr]) tuples ->
+    pm_product[count] (evaluation pointers None/0 when absent)."""
     arr = (pm_product * max(1, len(prods)))()
-    for i, (m, n, k, d, a, b, c) in enumerate(prods):
-        arr[i] = pm_product(m, n, k, d, a, b, c)
+    for i, t in enumerate(prods):
+        m, n, k, d, a, b, c = t[:7]
+        ae = t[7] if len(t) > 7 else None
+        be = t[8] if len(t) > 8 else None
+        arr[i] = pm_product(m, n, k, d, a, b, c, ae or None, be or None)
     return arr
 
 
@@ -166,3 +176,18 @@ def pm_profile_end() -> dict:
     _check(lib().pm_profile_end(ctypes.byref(st)), "pm_profile_end")
     return {name: (st.total_ms[i], int(st.launches[i]))
             for i, name in enumerate(KERNEL_KINDS)}
+
+
+def pm_eval_bytes(p: int, role: int, rows: int, cols: int, d: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_eval_bytes(p, role, rows, cols, d, elem_bytes, ctypes.byref(out)),
+           "pm_eval_bytes")
+    return out.value
+
+
+def pm_eval_u32(p, role, rows, cols, d, X, X_eval, eval_bytes, stream) -> int:
+    return lib().pm_eval_u32(p, role, rows, cols, d, X, X_eval, eval_bytes, stream)
+
+
+def pm_eval_u64(p, role, rows, cols, d, X, X_eval, eval_bytes, stream) -> int:
+    return lib().pm_eval_u64(p, role, rows, cols, d, X, X_eval, eval_bytes, stream)

@@ -160,6 +160,8 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   PointwiseLaunch& pw = L->pw;
   pw.m = m; pw.n = n; pw.k = k; pw.L = 1 << P.logL;
   pw.prime_stride = pstride;
+  pw.a_prime_stride = pstride;
+  pw.b_prime_stride = pstride;
   pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
   for (int i = 0; i < P.r; ++i) {
     pw.pc[i] = pc[i];
@@ -202,13 +204,14 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
 namespace {
 
-// Enqueue one product, one launch (or two for split transforms) per phase.
-int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                hipStream_t s) {
-  ProductLaunches L;
-  int st = fill_product_launches(P, A, B, C, ws, &L);
-  if (st != PM_OK) return st;
+// Enqueue one product from its launch descriptors, one launch (or two for
+// split transforms) per phase; skip_fwd[op]: that operand's evaluations are
+// given (already pointed to by L.pw).
+int launch_product(const Plan& P, const ProductLaunches& L, const bool skip_fwd[2],
+                   hipStream_t s) {
+  int st;
   for (int op = 0; op < 2; ++op) {
+    if (skip_fwd[op]) continue;
     KernelTimer kt(K_NTT_FWD, s);
     if (launch_ntt_fwd(L.f[op], P.elem_bytes, L.reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
   }
@@ -227,6 +230,15 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
     if (launch_crt(L.crt, P.elem_bytes, s) != hipSuccess) return PM_EDEVICE;
   }
   return PM_OK;
+}
+
+int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
+                hipStream_t s) {
+  ProductLaunches L;
+  int st = fill_product_launches(P, A, B, C, ws, &L);
+  if (st != PM_OK) return st;
+  const bool none[2] = {false, false};
+  return launch_product(P, L, none, s);
 }
 
 pm_status mul_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int elem_bytes,
@@ -285,6 +297,74 @@ pm_status pm_sync(void* stream) {
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PM_EDEVICE;
   if (hipGetLastError() != hipSuccess) return PM_EDEVICE;
   return PM_OK;
+}
+
+}  // extern "C"
+
+// ---- operand evaluations (multiplier precomputation) -----------------------------
+
+namespace {
+
+// Plan of a product in which X is the left (role 0) or right (role 1) operand.
+int eval_plan(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d, int eb, Plan* P) {
+  if (role != 0 && role != 1) return PM_EINVAL;
+  return role == 0 ? make_plan(p, rows, cols, 1, d, eb, P) : make_plan(p, 1, rows, cols, d, eb, P);
+}
+
+uint64_t eval_prime_stride_bytes(const Plan& P, int32_t rows, int32_t cols) {
+  return align_up(4ull * ((uint64_t)1 << P.logL) * (uint64_t)rows * cols, 256);
+}
+
+pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d, int eb,
+                      const void* X, void* Xe, uint64_t xe_bytes, void* stream) {
+  Plan P;
+  int st = eval_plan(p, role, rows, cols, d, eb, &P);
+  if (st != PM_OK) return (pm_status)st;
+  if (!X || !Xe || ((uintptr_t)X & 15) || ((uintptr_t)Xe & 255)) return PM_EINVAL;
+  const uint64_t need = eval_prime_stride_bytes(P, rows, cols) * P.r;
+  if (xe_bytes < need) return PM_EWORKSPACE;
+  if (overlap(X, (uint64_t)eb * d * rows * cols, Xe, need)) return PM_EINVAL;
+  PrimeConst pc[kMaxPrimes];
+  for (int i = 0; i < P.r; ++i) {
+    st = get_prime_const(P.q[i], P.logL, &pc[i]);
+    if (st != PM_OK) return (pm_status)st;
+  }
+  NttLaunch a;
+  memset(&a, 0, sizeof a);
+  fill_ntt_launch(&a, P.logL, rows * cols, d);
+  for (int i = 0; i < P.r; ++i) a.pc[i] = pc[i];
+  a.in = X;
+  a.out = Xe;
+  a.in_prime_stride = 0;
+  a.out_prime_stride = eval_prime_stride_bytes(P, rows, cols) / 4;
+  hipStream_t s = (hipStream_t)stream;
+  KernelTimer kt(K_NTT_FWD, s);
+  if (launch_ntt_fwd(a, eb, P.mode == 1, P.r, s) != hipSuccess) return PM_EDEVICE;
+  return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_eval_bytes(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                        int32_t elem_bytes, uint64_t* out) {
+  if (!out) return PM_EINVAL;
+  Plan P;
+  int st = eval_plan(p, role, rows, cols, d, elem_bytes, &P);
+  if (st != PM_OK) return (pm_status)st;
+  *out = eval_prime_stride_bytes(P, rows, cols) * P.r;
+  return PM_OK;
+}
+
+pm_status pm_eval_u32(uint32_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                      const uint32_t* X, void* X_eval, uint64_t eval_bytes, void* stream) {
+  return eval_common(p, role, rows, cols, d, 4, X, X_eval, eval_bytes, stream);
+}
+
+pm_status pm_eval_u64(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
+                      const uint64_t* X, void* X_eval, uint64_t eval_bytes, void* stream) {
+  return eval_common(p, role, rows, cols, d, 8, X, X_eval, eval_bytes, stream);
 }
 
 }  // extern "C"
@@ -353,8 +433,8 @@ int lds_class(uint32_t bytes) {
 size_t ntt_lds_bytes(const NttLaunch& a) { return 4 * (size_t)a.lds_stride << a.eb_log; }
 
 // Build the segments of one product into the per-phase lists; track LDS needs.
-void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
-                      std::vector<HostSeg>* ph, size_t* lds) {
+void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, bool a_given,
+                      bool b_given, std::vector<HostSeg>* ph, size_t* lds) {
   auto add = [&](int phase, uint16_t kind, uint16_t op, uint16_t prime, uint32_t nx,
                  uint32_t count, double cost, size_t need, uint16_t zpts) {
     HostSeg h;
@@ -369,6 +449,7 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
   };
   const uint32_t L_ = 1u << P.logL;
   for (int op = 0; op < 2; ++op) {
+    if ((op == 0 && a_given) || (op == 1 && b_given)) continue;
     const NttLaunch& a = L.f[op];
     const uint32_t EB = 1u << a.eb_log;
     const uint32_t neb = ((uint32_t)a.E + EB - 1) / EB;
@@ -429,15 +510,52 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L,
 int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
               const BatchLayout& lay, const pm_product* prods, uint8_t* ws, hipStream_t s) {
   const int count = (int)plans.size();
+  // Small batches: per-product launches with their parameters in kernel
+  // arguments (no descriptor upload, no phase tables).  Tuning knob
+  // PM_TUNE_BATCH_DIRECT_MAX (default 2) is the largest batch run this way.
+  static const int direct_max = [] {
+    const char* v = getenv("PM_TUNE_BATCH_DIRECT_MAX");
+    return v && *v ? atoi(v) : 2;
+  }();
+  if (count <= direct_max) {
+    for (int i = 0; i < count; ++i) {
+      const Plan& P = plans[i];
+      ProductLaunches L;
+      int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &L);
+      if (st != PM_OK) return st;
+      if (prods[i].A_eval) {
+        L.pw.ahat = (const uint32_t*)prods[i].A_eval;
+        L.pw.a_prime_stride = eval_prime_stride_bytes(P, P.m, P.n) / 4;
+      }
+      if (prods[i].B_eval) {
+        L.pw.bhat = (const uint32_t*)prods[i].B_eval;
+        L.pw.b_prime_stride = eval_prime_stride_bytes(P, P.n, P.k) / 4;
+      }
+      const bool skip[2] = {prods[i].A_eval != nullptr, prods[i].B_eval != nullptr};
+      st = launch_product(P, L, skip, s);
+      if (st != PM_OK) return st;
+    }
+    return PM_OK;
+  }
   std::vector<uint8_t> host(lay.total - lay.prod_off, 0);
   ProductLaunches* hp = (ProductLaunches*)host.data();
   std::vector<HostSeg> ph[kBatchPhases];
   size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
-    int st = fill_product_launches(plans[i], prods[i].A, prods[i].B, prods[i].C, ws + offs[i],
-                                   &hp[i]);
+    const Plan& P = plans[i];
+    int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i]);
     if (st != PM_OK) return st;
-    product_segments((uint32_t)i, plans[i], hp[i], ph, lds);
+    // given evaluations replace the forward transforms of that operand
+    if (prods[i].A_eval) {
+      hp[i].pw.ahat = (const uint32_t*)prods[i].A_eval;
+      hp[i].pw.a_prime_stride = eval_prime_stride_bytes(P, P.m, P.n) / 4;
+    }
+    if (prods[i].B_eval) {
+      hp[i].pw.bhat = (const uint32_t*)prods[i].B_eval;
+      hp[i].pw.b_prime_stride = eval_prime_stride_bytes(P, P.n, P.k) / 4;
+    }
+    product_segments((uint32_t)i, P, hp[i], prods[i].A_eval != nullptr,
+                     prods[i].B_eval != nullptr, ph, lds);
   }
   // Per phase and LDS class: largest tiles first, then prefix sums of tile
   // counts; one launch per non-empty (phase, class).
@@ -510,6 +628,7 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
   for (int32_t i = 0; i < count; ++i) {
     st = check_operands(plans[i], prods[i].A, prods[i].B, prods[i].C);
     if (st != PM_OK) return (pm_status)st;
+    if (((uintptr_t)prods[i].A_eval | (uintptr_t)prods[i].B_eval) & 255) return PM_EINVAL;
     const uint64_t eb = (uint64_t)elem_bytes;
     const Plan& P = plans[i];
     st = check_workspace(ws, ws_bytes, lay.total, prods[i].A, eb * P.d * P.m * P.n, prods[i].B,

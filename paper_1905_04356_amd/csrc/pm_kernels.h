@@ -40,7 +40,9 @@ struct NttLaunch {
 // (m x n times n x k), all point-major u32.
 struct PointwiseLaunch {
   int m, n, k, L;
-  uint64_t prime_stride;     // elements between primes' eval sets
+  uint64_t prime_stride;     // elements between primes' evaluations of C
+  uint64_t a_prime_stride;   // ... of A
+  uint64_t b_prime_stride;   // ... of B
   const uint32_t* ahat;
   const uint32_t* bhat;
   uint32_t* chat;

@@ -23,8 +23,8 @@ __device__ __forceinline__ void pointwise_valu_tile(const PointwiseLaunch& a, in
   const PrimeConst& P = a.pc[prime];
   const uint32_t q = P.q;
   const size_t mn = (size_t)a.m * a.n, nk = (size_t)a.n * a.k, mk = (size_t)a.m * a.k;
-  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * mn;
-  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * nk;
+  const uint32_t* A = a.ahat + a.a_prime_stride * prime + (size_t)t * mn;
+  const uint32_t* B = a.bhat + a.b_prime_stride * prime + (size_t)t * nk;
   uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * mk;
   const uint32_t* sa = A;
   const uint32_t* sb = B;
@@ -100,8 +100,8 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
   const int rs = np + 16;                   // bytes per LDS row (padded)
   uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
   uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]
-  const uint32_t* A = a.ahat + a.prime_stride * prime + (size_t)t * ((size_t)m * n);
-  const uint32_t* B = a.bhat + a.prime_stride * prime + (size_t)t * ((size_t)n * k);
+  const uint32_t* A = a.ahat + a.a_prime_stride * prime + (size_t)t * ((size_t)m * n);
+  const uint32_t* B = a.bhat + a.b_prime_stride * prime + (size_t)t * ((size_t)n * k);
   uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * ((size_t)m * k);
   const int nt = blockDim.x;
   const int ng = np >> 2;                   // groups of 4 contraction indices (multiple of 16)

@@ -81,9 +81,26 @@ def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = Non
     return out
 
 
+def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
+    """Evaluations of one operand (role 0: left factor A, 1: right factor B)
+    as a device byte tensor, reusable by every product with the same p,
+    contraction length and degree bound (pass it to mul_batched)."""
+    d, rows, cols = X.shape
+    eb = _elem_bytes(X)
+    X = X.contiguous()
+    nbytes = _b.pm_eval_bytes(p, role, rows, cols, d, eb)
+    out = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    fn = _b.pm_eval_u32 if eb == 4 else _b.pm_eval_u64
+    st = fn(p, role, rows, cols, d, X.data_ptr(), out.data_ptr(), nbytes, _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_eval")
+    return out
+
+
 def mul_batched(p: int, As, Bs, outs=None, workspace: Workspace | None = None,
-                stream=None):
-    """[A_i B_i mod p] for lists of tensors, in one batched call."""
+                stream=None, A_evals=None, B_evals=None):
+    """[A_i B_i mod p] for lists of tensors, in one batched call. A_evals /
+    B_evals: optional lists of evaluate() results (or None entries)."""
     if len(As) != len(Bs):
         raise ValueError("As and Bs differ in length")
     if not As:
@@ -93,11 +110,15 @@ def mul_batched(p: int, As, Bs, outs=None, workspace: Workspace | None = None,
         outs = [torch.empty((2 * A.shape[0] - 1, A.shape[1], B.shape[2]), dtype=A.dtype,
                             device=A.device) for A, B in zip(As, Bs)]
     prods = []
-    for A, B, C in zip(As, Bs, outs):
+    A_evals = A_evals or [None] * len(As)
+    B_evals = B_evals or [None] * len(As)
+    for A, B, C, Ae, Be in zip(As, Bs, outs, A_evals, B_evals):
         d, m, n = A.shape
         if B.shape[0] != d or B.shape[1] != n or _elem_bytes(B) != eb or _elem_bytes(A) != eb:
             raise ValueError("inconsistent batch member")
-        prods.append((m, n, B.shape[2], d, A.data_ptr(), B.data_ptr(), C.data_ptr()))
+        prods.append((m, n, B.shape[2], d, A.data_ptr(), B.data_ptr(), C.data_ptr(),
+                      Ae.data_ptr() if Ae is not None else None,
+                      Be.data_ptr() if Be is not None else None))
     arr = _b.products_array(prods)
     need = _b.pm_batched_workspace_bytes(p, arr, len(prods), eb)
     ws = (workspace or _workspace(As[0].device)).get(need)

@@ -300,3 +300,58 @@ def test_config3_full_batch_sampled():
             assert np.array_equal(C[:, a, b].astype(np.uint64), ref[s])
         if d * (m * n + n * k + m * k) < 40_000_000:
             assert O.point_check(p, A, B, C, seed=int(i), points=1)
+
+
+def test_serving_results_same_alone_and_in_mix():
+    """Continuous batching over 4 streams with resident evaluations: sampled
+    requests are byte-identical to the same product computed alone (one
+    pm_mul call, no cached evaluations) and to the FIFO baseline; three
+    small ones also match the oracle."""
+    from paper_1905_04356_amd import serving as S
+    p = P30
+    dev = torch.device("cuda")
+    pool = S.make_pool(p, 21, 12, dev, with_evals=True, dims_cap=32)
+    arrivals, items = S.trace(21, 600.0, 0.5, len(pool))
+    keep = list(range(0, len(arrivals), max(1, len(arrivals) // 24)))
+    srv = S.Server(p, pool, 8 << 30, streams=4, keep=keep)
+    stats = srv.run(arrivals, items)
+    torch.cuda.synchronize()
+    say(f"[serving] {stats}")
+    assert stats["requests"] == len(arrivals) and stats["batches"] >= 1
+    fifo, kept_fifo = S.run_fifo(p, pool, arrivals, items, keep=keep)
+    torch.cuda.synchronize()
+    small = 0
+    for r in keep:
+        it = pool[items[r]]
+        alone = polymat.mul(p, it.A, it.B)
+        torch.cuda.synchronize()
+        assert torch.equal(srv.kept[r], alone), r
+        assert torch.equal(kept_fifo[r], alone), r
+        if small < 3 and it.m * it.n * it.k * it.d * it.d <= 1 << 28:
+            ref = O.polymatmul(p, it.A.cpu().numpy(), it.B.cpu().numpy())
+            assert np.array_equal(alone.cpu().numpy().astype(np.uint64), ref)
+            small += 1
+
+
+def test_eval_entry_points_match_plain_products():
+    """pm_eval_* evaluations fed to a batch give the same bytes as products
+    that transform their own operands (direct and CRT moduli)."""
+    for p, dt in ((P31, np.uint32), (I.seeded_prime_60(6), np.uint64)):
+        shapes = [(5, 8, 3, 100), (16, 32, 16, 2500), (1, 4, 2, 1)]
+        As, Bs, Ae, Be = [], [], [], []
+        for i, (m, n, k, d) in enumerate(shapes):
+            A, B = tensors(p, m, n, k, d, seed=22, product=i, dtype=dt)
+            As.append(torch.from_numpy(A).cuda())
+            Bs.append(torch.from_numpy(B).cuda())
+            Ae.append(polymat.evaluate(p, As[-1], 0))
+            Be.append(polymat.evaluate(p, Bs[-1], 1))
+        ref = polymat.mul_batched(p, As, Bs)
+        got = polymat.mul_batched(p, As, Bs, A_evals=Ae, B_evals=Be)
+        half = polymat.mul_batched(p, As, Bs, A_evals=Ae, B_evals=[None] * 3)
+        # two products: the direct (per-product launch) path of small batches
+        two = polymat.mul_batched(p, As[:2], Bs[:2], A_evals=[None, Ae[1]], B_evals=Be[:2])
+        torch.cuda.synchronize()
+        for r, g, h in zip(ref, got, half):
+            assert torch.equal(r, g) and torch.equal(r, h)
+        for r, t in zip(ref, two):
+            assert torch.equal(r, t)
