@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -507,38 +508,24 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
   }
 }
 
-int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
-              const BatchLayout& lay, const pm_product* prods, uint8_t* ws, hipStream_t s) {
+// Host side of a phase-launched batch: descriptors and segment tables (to be
+// copied to ws + lay.prod_off) and the launch groups.
+struct BatchGroup {
+  int phase;
+  uint64_t first_seg, nseg, tiles;
+  uint32_t lds;
+};
+struct BatchBuild {
+  std::vector<uint8_t> host;
+  std::vector<BatchGroup> groups;
+};
+
+int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
+                const BatchLayout& lay, const pm_product* prods, uint8_t* ws, BatchBuild* B) {
   const int count = (int)plans.size();
-  // Small batches: per-product launches with their parameters in kernel
-  // arguments (no descriptor upload, no phase tables).  Tuning knob
-  // PM_TUNE_BATCH_DIRECT_MAX (default 2) is the largest batch run this way.
-  static const int direct_max = [] {
-    const char* v = getenv("PM_TUNE_BATCH_DIRECT_MAX");
-    return v && *v ? atoi(v) : 2;
-  }();
-  if (count <= direct_max) {
-    for (int i = 0; i < count; ++i) {
-      const Plan& P = plans[i];
-      ProductLaunches L;
-      int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &L);
-      if (st != PM_OK) return st;
-      if (prods[i].A_eval) {
-        L.pw.ahat = (const uint32_t*)prods[i].A_eval;
-        L.pw.a_prime_stride = eval_prime_stride_bytes(P, P.m, P.n) / 4;
-      }
-      if (prods[i].B_eval) {
-        L.pw.bhat = (const uint32_t*)prods[i].B_eval;
-        L.pw.b_prime_stride = eval_prime_stride_bytes(P, P.n, P.k) / 4;
-      }
-      const bool skip[2] = {prods[i].A_eval != nullptr, prods[i].B_eval != nullptr};
-      st = launch_product(P, L, skip, s);
-      if (st != PM_OK) return st;
-    }
-    return PM_OK;
-  }
-  std::vector<uint8_t> host(lay.total - lay.prod_off, 0);
-  ProductLaunches* hp = (ProductLaunches*)host.data();
+  B->host.assign(lay.total - lay.prod_off, 0);
+  B->groups.clear();
+  ProductLaunches* hp = (ProductLaunches*)B->host.data();
   std::vector<HostSeg> ph[kBatchPhases];
   size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
@@ -559,9 +546,7 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
   }
   // Per phase and LDS class: largest tiles first, then prefix sums of tile
   // counts; one launch per non-empty (phase, class).
-  BatchSeg* hs = (BatchSeg*)(host.data() + (lay.seg_off - lay.prod_off));
-  struct Group { int phase; uint64_t first_seg, nseg, tiles; uint32_t lds; };
-  std::vector<Group> groups;
+  BatchSeg* hs = (BatchSeg*)(B->host.data() + (lay.seg_off - lay.prod_off));
   uint64_t seg_base = 0;
   for (int f = 0; f < kBatchPhases; ++f) {
     std::vector<HostSeg> cls[kLdsClasses];
@@ -570,7 +555,7 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
       if (cls[c].empty()) continue;
       std::stable_sort(cls[c].begin(), cls[c].end(),
                        [](const HostSeg& a, const HostSeg& b) { return a.cost > b.cost; });
-      Group G{f, seg_base, cls[c].size(), 0, 0};
+      BatchGroup G{f, seg_base, cls[c].size(), 0, 0};
       for (auto& h : cls[c]) {
         h.g.first = (uint32_t)G.tiles;
         G.tiles += h.count;
@@ -578,11 +563,16 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
         hs[seg_base++] = h.g;
       }
       if (G.tiles > 0x7fffffffull) return PM_ERANGE;
-      groups.push_back(G);
+      B->groups.push_back(G);
     }
   }
   if (seg_base > lay.nseg) return PM_EINVAL;
-  if (hipMemcpyAsync(ws + lay.prod_off, host.data(), host.size(), hipMemcpyHostToDevice, s) !=
+  return PM_OK;
+}
+
+int enqueue_batch(const BatchBuild& B, const void* host_src, const BatchLayout& lay, uint8_t* ws,
+                  hipStream_t s) {
+  if (hipMemcpyAsync(ws + lay.prod_off, host_src, B.host.size(), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return PM_EDEVICE;
   const ProductLaunches* dprods = (const ProductLaunches*)(ws + lay.prod_off);
@@ -590,13 +580,184 @@ int run_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
   static const int kind_of_phase[kBatchPhases] = {K_NTT_FWD, K_NTT_FWD, K_POINTWISE,
                                                   K_NTT_INV, K_NTT_INV, K_CRT};
   KernelTimer kt(K_BATCHED, s);
-  for (const Group& G : groups) {
+  for (const BatchGroup& G : B.groups) {
     KernelTimer kp(kind_of_phase[G.phase], s);
     if (launch_batch_phase(G.phase, dprods, dsegs + G.first_seg, (int)G.nseg,
                            (uint32_t)G.tiles, G.lds, s) != hipSuccess)
       return PM_EDEVICE;
   }
   return PM_OK;
+}
+
+// Small batches: per-product launches with their parameters in kernel
+// arguments (no descriptor upload, no phase tables).
+int run_direct(const std::vector<Plan>& plans, const std::vector<uint64_t>& offs,
+               const pm_product* prods, uint8_t* ws, hipStream_t s) {
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan& P = plans[i];
+    ProductLaunches L;
+    int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &L);
+    if (st != PM_OK) return st;
+    if (prods[i].A_eval) {
+      L.pw.ahat = (const uint32_t*)prods[i].A_eval;
+      L.pw.a_prime_stride = eval_prime_stride_bytes(P, P.m, P.n) / 4;
+    }
+    if (prods[i].B_eval) {
+      L.pw.bhat = (const uint32_t*)prods[i].B_eval;
+      L.pw.b_prime_stride = eval_prime_stride_bytes(P, P.n, P.k) / 4;
+    }
+    const bool skip[2] = {prods[i].A_eval != nullptr, prods[i].B_eval != nullptr};
+    st = launch_product(P, L, skip, s);
+    if (st != PM_OK) return st;
+  }
+  return PM_OK;
+}
+
+// ---- graph cache: a batch that repeats (same products, pointers, workspace)
+// is captured once into a HIP graph and replayed.  The first occurrence runs
+// eagerly, so tables and kernel attributes exist before any capture; the
+// second is captured; later ones replay.  Each entry owns the pinned host
+// copy of its descriptors that its memcpy node reads.
+struct GraphEntry {
+  std::vector<uint8_t> sig;
+  int seen = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* pinned = nullptr;
+  hipStream_t last = nullptr;
+  uint64_t tick = 0;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_tick = 0;
+constexpr size_t kGraphCacheMax = 16;
+
+void free_entry(GraphEntry& e) {
+  if (e.last) (void)hipStreamSynchronize(e.last);  // a replay may still read `pinned`
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  if (e.pinned) (void)hipHostFree(e.pinned);
+  e = GraphEntry();
+}
+
+// One non-blocking capture stream per device, default priority, kept for
+// the life of the process.
+hipStream_t capture_stream(int dev) {
+  static hipStream_t streams[64] = {};
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+std::vector<uint8_t> batch_signature(uint64_t p, int eb, const pm_product* prods, int count,
+                                     const void* ws, uint64_t ws_bytes, int dev) {
+  std::vector<uint8_t> sig(sizeof(uint64_t) * 3 + sizeof(int) * 2 + sizeof(pm_product) * count);
+  uint8_t* o = sig.data();
+  auto put = [&](const void* x, size_t n) { memcpy(o, x, n); o += n; };
+  const uint64_t w = (uint64_t)(uintptr_t)ws;
+  put(&p, 8); put(&w, 8); put(&ws_bytes, 8); put(&eb, sizeof eb); put(&dev, sizeof dev);
+  put(prods, sizeof(pm_product) * count);
+  return sig;
+}
+
+int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
+              const std::vector<uint64_t>& offs, const BatchLayout& lay, const pm_product* prods,
+              uint8_t* ws, uint64_t ws_bytes, hipStream_t s) {
+  const int count = (int)plans.size();
+  // Tuning knobs: PM_TUNE_BATCH_DIRECT_MAX (default 2) is the largest batch
+  // launched per product; PM_TUNE_BATCH_GRAPH=0 turns graph replay off.
+  static const int direct_max = [] {
+    const char* v = getenv("PM_TUNE_BATCH_DIRECT_MAX");
+    return v && *v ? atoi(v) : 2;
+  }();
+  static const bool use_graphs = [] {
+    const char* v = getenv("PM_TUNE_BATCH_GRAPH");
+    return !(v && *v == '0');
+  }();
+  if (count <= direct_max) return run_direct(plans, offs, prods, ws, s);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!use_graphs || hipStreamIsCapturing(s, &cs) != hipSuccess ||
+      cs != hipStreamCaptureStatusNone) {
+    BatchBuild B;
+    int st = build_batch(plans, offs, lay, prods, ws, &B);
+    if (st != PM_OK) return st;
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
+  std::vector<uint8_t> sig = batch_signature(p, eb, prods, count, ws, ws_bytes, dev);
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  GraphEntry* e = nullptr;
+  for (auto& g : g_graphs)
+    if (g.sig == sig) { e = &g; break; }
+  if (e && e->exec) {
+    e->tick = ++g_tick;
+    e->last = s;
+    KernelTimer kt(K_BATCHED, s);
+    return hipGraphLaunch(e->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+  }
+  BatchBuild B;
+  int st = build_batch(plans, offs, lay, prods, ws, &B);
+  if (st != PM_OK) return st;
+  if (!e) {
+    // first occurrence: remember the signature, run eagerly
+    if (g_graphs.size() >= kGraphCacheMax) {
+      auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                  [](const GraphEntry& a, const GraphEntry& b) {
+                                    return a.tick < b.tick;
+                                  });
+      free_entry(*lru);
+      g_graphs.erase(lru);
+    }
+    GraphEntry ne;
+    ne.sig = std::move(sig);
+    ne.seen = 1;
+    ne.tick = ++g_tick;
+    g_graphs.push_back(std::move(ne));
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  // second occurrence: capture on a library stream (the caller's may be the
+  // legacy default stream, which cannot be captured), instantiate, and
+  // launch the graph on the caller's stream.
+  hipStream_t cap = capture_stream(dev);
+  if (!cap || hipHostMalloc(&e->pinned, B.host.size(), hipHostMallocDefault) != hipSuccess) {
+    e->pinned = nullptr;
+    (void)hipGetLastError();
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  memcpy(e->pinned, B.host.data(), B.host.size());
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(e->pinned);
+    e->pinned = nullptr;
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  st = enqueue_batch(B, e->pinned, lay, ws, cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(cap, &graph);
+  if (st != PM_OK || ce != hipSuccess || !graph) {
+    // capture failed: nothing was run; clear the error and run eagerly
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    (void)hipHostFree(e->pinned);
+    e->pinned = nullptr;
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  e->graph = graph;
+  if (hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    e->exec = nullptr;
+    (void)hipGraphDestroy(graph);
+    e->graph = nullptr;
+    (void)hipHostFree(e->pinned);
+    e->pinned = nullptr;
+    return enqueue_batch(B, B.host.data(), lay, ws, s);
+  }
+  e->tick = ++g_tick;
+  e->last = s;
+  KernelTimer kt(K_BATCHED, s);
+  return hipGraphLaunch(e->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
 }  // namespace
@@ -635,7 +796,8 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
                          eb * P.d * P.n * P.k, prods[i].C, eb * (2ull * P.d - 1) * P.m * P.k);
     if (st != PM_OK) return (pm_status)st;
   }
-  return (pm_status)run_batch(plans, offs, lay, prods, (uint8_t*)ws, (hipStream_t)stream);
+  return (pm_status)run_batch(p, elem_bytes, plans, offs, lay, prods, (uint8_t*)ws, ws_bytes,
+                              (hipStream_t)stream);
 }
 
 pm_status pm_mul_batched_u32(uint32_t p, int32_t count, const pm_product* prods, void* workspace,

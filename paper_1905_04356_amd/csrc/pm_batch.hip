@@ -121,11 +121,13 @@ template <int PHASE, int NT>
 static int launch_phase_t(const ProductLaunches* prods, const BatchSeg* segs, int nseg,
                           uint32_t ntiles, size_t lds, hipStream_t s) {
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)batch_kernel<PHASE, NT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  // Raise the dynamic-LDS limit once, to the whole 160 KiB, on the first
+  // launch (which is never inside a graph capture: batches are captured on
+  // their second occurrence).
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void*)batch_kernel<PHASE, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      160 * 1024);
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL((batch_kernel<PHASE, NT>), dim3(ntiles), dim3(NT), lds, s, prods, segs,
                      nseg);
   return hipGetLastError();

@@ -27,6 +27,9 @@ bool profiling() { return g_on.load(std::memory_order_relaxed) != 0; }
 
 KernelTimer::KernelTimer(int kind, hipStream_t s) : kind_(kind), s_(s) {
   if (!profiling()) return;
+  // no timing inside a stream capture: the events would become graph nodes
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
     std::lock_guard<std::mutex> l(g_mu);
     g_failed = true;

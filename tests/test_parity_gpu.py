@@ -355,3 +355,31 @@ def test_eval_entry_points_match_plain_products():
             assert torch.equal(r, g) and torch.equal(r, h)
         for r, t in zip(ref, two):
             assert torch.equal(r, t)
+
+
+def test_batched_graph_replays_match_eager():
+    """A batch that repeats is run eagerly, then captured into a HIP graph,
+    then replayed: with eager work and synchronisations between calls and the
+    outputs cleared each time, every call must reproduce the single-call
+    results."""
+    p = P30
+    shapes = [(4, 8, 4, 100), (16, 16, 8, 3000), (8, 4, 8, 40), (32, 32, 32, 700),
+              (4, 4, 4, 1), (64, 32, 16, 2100)]
+    As, Bs, refs = [], [], []
+    for i, (m, n, k, d) in enumerate(shapes):
+        A, B = tensors(p, m, n, k, d, seed=23, product=i)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        refs.append(polymat.mul(p, As[-1], Bs[-1]).clone())
+    outs = [torch.empty_like(r) for r in refs]
+    ws = polymat.Workspace()
+    for call in range(5):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        polymat.mul_batched(p, As, Bs, outs, workspace=ws)
+        # unrelated eager work between calls
+        polymat.mul(p, As[0], Bs[0])
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, r), f"call {call} product {i}"
