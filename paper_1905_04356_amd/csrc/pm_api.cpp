@@ -145,7 +145,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   L->pw_staged = 4ull * ((uint64_t)m * n + (uint64_t)n * k) <= 128 * 1024;
 
   NttLaunch& fa = L->f[0];
-  fill_ntt_launch(&fa, P.logL, m * n, d);
+  fill_ntt_launch(&fa, P.logL, m * n, d, P.elem_bytes, false);
   for (int i = 0; i < P.r; ++i) fa.pc[i] = pc[i];
   fa.in = A;
   fa.out = ahat;
@@ -154,7 +154,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& fb = L->f[1];
   fb = fa;
-  fill_ntt_launch(&fb, P.logL, n * k, d);
+  fill_ntt_launch(&fb, P.logL, n * k, d, P.elem_bytes, false);
   fb.in = B;
   fb.out = bhat;
 
@@ -177,7 +177,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& ic = L->inv;
   ic = fa;
-  fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1);
+  fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1, P.mode == 1 ? 4 : P.elem_bytes, true);
   ic.in = chat;
   ic.in_prime_stride = pstride;
   const uint64_t nout = (2ull * d - 1) * m * k;
@@ -332,7 +332,7 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   }
   NttLaunch a;
   memset(&a, 0, sizeof a);
-  fill_ntt_launch(&a, P.logL, rows * cols, d);
+  fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false);
   for (int i = 0; i < P.r; ++i) a.pc[i] = pc[i];
   a.in = X;
   a.out = Xe;
@@ -456,10 +456,10 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
     const uint32_t neb = ((uint32_t)a.E + EB - 1) / EB;
     for (int q = 0; q < P.r; ++q) {
       if (a.split) {
-        const uint32_t items = (L_ >> a.split) * (uint32_t)a.E;
+        const uint32_t items = col_items(a);
         const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
         add(0, BK_COL_FWD, op, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
-                                              (1 << a.split), 0, 0);
+                                              a.col_vec * (1 << a.split), 0, 0);
         add(1, BK_BLOCK_FWD, op, q, neb, neb << a.split,
             (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
       } else {
@@ -493,10 +493,10 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
       if (a.split) {
         add(3, BK_BLOCK_INV, 0, q, neb, neb << a.split,
             (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
-        const uint32_t items = (L_ >> a.split) * (uint32_t)a.E;
+        const uint32_t items = col_items(a);
         const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
         add(4, BK_COL_INV, 0, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
-                                             (1 << a.split), 0, 0);
+                                             a.col_vec * (1 << a.split), 0, 0);
       } else {
         add(4, BK_INV_LDS, 0, q, neb, neb, (double)EB * L_ * (P.logL + 1), ntt_lds_bytes(a), 0);
       }

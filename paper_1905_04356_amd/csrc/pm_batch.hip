@@ -35,7 +35,7 @@ template <typename TIn, bool RED>
 __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, uint32_t x,
                                        uint32_t* lds) {
   if (g.kind == BK_COL_FWD) {
-    const uint32_t items = (1u << (a.logL - a.split)) * (uint32_t)a.E;
+    const uint32_t items = col_items(a);
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
     switch (a.split) {
@@ -62,7 +62,7 @@ template <typename TOut>
 __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, uint32_t x,
                                        uint32_t* lds) {
   if (g.kind == BK_COL_INV) {
-    const uint32_t items = (1u << (a.logL - a.split)) * (uint32_t)a.E;
+    const uint32_t items = col_items(a);
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
     switch (a.split) {

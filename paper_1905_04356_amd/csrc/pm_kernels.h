@@ -28,6 +28,7 @@ struct NttLaunch {
   int E;                     // entries per point
   int eb_log;                // log2(entries per workgroup) in the LDS kernel
   int vec;                   // residues per global load/store (1, 2, 4)
+  int col_vec;               // column pass: consecutive entries per item (1, 2, 4)
   int lds_stride;            // 32-bit words between entries in LDS
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers
@@ -80,6 +81,14 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
                           unsigned long long* counter, hipStream_t s);
 
 // Fill the launch descriptor of a transform for (logL, E, nin).
-void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin);
+// io_bytes: bytes per element of the coefficient-major side (the input of a
+// forward transform, the output of an inverse one).
+void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse);
+
+// Work items of the column pass: one per (j < L / 2^split, group of col_vec
+// consecutive entries).
+__host__ __device__ inline uint32_t col_items(const NttLaunch& a) {
+  return (1u << (a.logL - a.split)) * (uint32_t)(a.E / a.col_vec);
+}
 
 }  // namespace pm

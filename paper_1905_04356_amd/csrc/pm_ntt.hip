@@ -26,21 +26,19 @@ __global__ __launch_bounds__(kNT) void ntt_block_kernel(NttLaunch a) {
 
 template <typename TIn, bool REDUCE, int r>
 __global__ __launch_bounds__(kColNT) void ntt_col_fwd_kernel(NttLaunch a) {
-  const uint32_t items = (1u << (a.logL - r)) * (uint32_t)a.E;
-  col_fwd_tile<TIn, REDUCE, r>(a, blockIdx.y, blockIdx.x * kColNT + threadIdx.x, items,
+  col_fwd_tile<TIn, REDUCE, r>(a, blockIdx.y, blockIdx.x * kColNT + threadIdx.x, col_items(a),
                                gridDim.x * kColNT);
 }
 
 template <typename TOut, int r>
 __global__ __launch_bounds__(kColNT) void ntt_col_inv_kernel(NttLaunch a) {
-  const uint32_t items = (1u << (a.logL - r)) * (uint32_t)a.E;
-  col_inv_tile<TOut, r>(a, blockIdx.y, blockIdx.x * kColNT + threadIdx.x, items,
+  col_inv_tile<TOut, r>(a, blockIdx.y, blockIdx.x * kColNT + threadIdx.x, col_items(a),
                         gridDim.x * kColNT);
 }
 
 // ---- host side ---------------------------------------------------------------
 
-void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin) {
+void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse) {
   const PassPlan PP = make_pass_plan(logL);
   a->logL = logL;
   a->npass = PP.npass;
@@ -63,6 +61,11 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin) {
   int v = 4;
   while (v > 1 && ((E % v) != 0 || (1 << eb) % v != 0)) v >>= 1;
   a->vec = v;
+  // column items move at most 16 bytes per row access
+  int cv = inverse ? ntt_tune().colvec_inv : ntt_tune().colvec_fwd;
+  if (cv == 3) cv = 2;
+  while (cv > 1 && ((E % cv) != 0 || cv * io_bytes > 16)) cv >>= 1;
+  a->col_vec = cv;
   const int B = 1 << a->blk_log;
   a->lds_stride = B + (B >> 5) + 1;
 }
@@ -88,7 +91,7 @@ static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hi
 
 template <typename K>
 static int launch_col(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) {
-  const uint64_t items = ((uint64_t)1 << (a.logL - a.split)) * (uint64_t)a.E;
+  const uint64_t items = col_items(a);
   uint64_t blocks = (items + kColNT - 1) / kColNT;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(kernel, dim3((unsigned)blocks, nprimes), dim3(kColNT), 0, s, a);

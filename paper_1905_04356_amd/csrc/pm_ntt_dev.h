@@ -302,69 +302,104 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
 }
 
 // First forward pass of a split transform, r stages at stride S = L / 2^r,
-// items [it0, it1) with stride `step`: item (j, e) reads rows j + u S
-// (u < 2^(r-1); the upper half is zero padding since nin <= L/2) of the
-// coefficient-major input and writes all 2^r rows of the point-major buffer.
-template <typename TIn, bool REDUCE, int r>
-__device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint32_t it0,
-                                             uint32_t it1, uint32_t step) {
+// items [it0, it1) with stride `step`: item (j, g) reads, for the CV entries
+// e = g CV .. g CV + CV - 1, rows j + u S (u < 2^(r-1); the upper half is
+// zero padding since nin <= L/2) of the coefficient-major input and writes
+// all 2^r rows of the point-major buffer.  The entries share the twiddles.
+template <typename TIn, bool REDUCE, int r, int CV>
+__device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uint32_t it0,
+                                              uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
   const PrimeConst& P = a.pc[prime];
   const uint32_t q = P.q;
   const uint32_t S = 1u << (a.logL - r);
-  const uint32_t E = (uint32_t)a.E;
+  const uint32_t E = (uint32_t)a.E, G = E / CV;
   const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
   uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
   const Tw* tw = P.tw_fwd + a.tw_off[0];
   for (uint32_t it = it0; it < it1; it += step) {
-    const uint32_t j = it / E, e = it - j * E;
-    uint32_t x[R];
+    const uint32_t j = it / G, e = (it - j * G) * CV;
+    uint32_t x[CV][R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const uint32_t row = j + u * S;
-      x[u] = 0;
-      if (u < R / 2 && row < (uint32_t)a.nin) {
-        const TIn v = in[(size_t)row * E + e];
-        x[u] = REDUCE ? reduce_u64((uint64_t)v, q, P.mu) : (uint32_t)v;
-      }
+      Vec<TIn, CV> v;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v.v[c] = 0;
+      if (u < R / 2 && row < (uint32_t)a.nin) v = *(const Vec<TIn, CV>*)(in + (size_t)row * E + e);
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        x[c][u] = REDUCE ? reduce_u64((uint64_t)v.v[c], q, P.mu) : (uint32_t)v.v[c];
     }
     Tw t[R - 1];
 #pragma unroll
     for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
-    butterflies<r, true, true>(x, t, q);
 #pragma unroll
-    for (int u = 0; u < R; ++u) out[(size_t)(j + u * S) * E + e] = x[u];
+    for (int c = 0; c < CV; ++c) butterflies<r, true, true>(x[c], t, q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      Vec<uint32_t, CV> y;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) y.v[c] = x[c][u];
+      *(Vec<uint32_t, CV>*)(out + (size_t)(j + u * S) * E + e) = y;
+    }
   }
 }
 
-// Last inverse pass of a split transform: item (j, e) reads rows j + u S of
-// the point-major buffer and writes the rows below nin of the
-// coefficient-major output.
-template <typename TOut, int r>
-__device__ __forceinline__ void col_inv_tile(const NttLaunch& a, int prime, uint32_t it0,
+template <typename TIn, bool REDUCE, int r>
+__device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint32_t it0,
                                              uint32_t it1, uint32_t step) {
+  if (a.col_vec == 4) col_fwd_items<TIn, REDUCE, r, 4>(a, prime, it0, it1, step);
+  else if (a.col_vec == 2) col_fwd_items<TIn, REDUCE, r, 2>(a, prime, it0, it1, step);
+  else col_fwd_items<TIn, REDUCE, r, 1>(a, prime, it0, it1, step);
+}
+
+// Last inverse pass of a split transform: item (j, g) reads rows j + u S of
+// the point-major buffer for CV consecutive entries and writes the rows
+// below nin of the coefficient-major output.
+template <typename TOut, int r, int CV>
+__device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uint32_t it0,
+                                              uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
   const PrimeConst& P = a.pc[prime];
   const uint32_t S = 1u << (a.logL - r);
-  const uint32_t E = (uint32_t)a.E;
+  const uint32_t E = (uint32_t)a.E, G = E / CV;
   const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
   TOut* out = (TOut*)a.out + a.out_prime_stride * prime;
   const Tw* tw = P.tw_inv + a.tw_off[0];
   for (uint32_t it = it0; it < it1; it += step) {
-    const uint32_t j = it / E, e = it - j * E;
-    uint32_t x[R];
+    const uint32_t j = it / G, e = (it - j * G) * CV;
+    uint32_t x[CV][R];
 #pragma unroll
-    for (int u = 0; u < R; ++u) x[u] = in[(size_t)(j + u * S) * E + e];
+    for (int u = 0; u < R; ++u) {
+      const Vec<uint32_t, CV> v = *(const Vec<uint32_t, CV>*)(in + (size_t)(j + u * S) * E + e);
+#pragma unroll
+      for (int c = 0; c < CV; ++c) x[c][u] = v.v[c];
+    }
     Tw t[R - 1];
 #pragma unroll
     for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
-    butterflies<r, false, false>(x, t, P.q);
+#pragma unroll
+    for (int c = 0; c < CV; ++c) butterflies<r, false, false>(x[c], t, P.q);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const uint32_t row = j + u * S;
-      if (row < (uint32_t)a.nin) out[(size_t)row * E + e] = (TOut)x[u];
+      if (row < (uint32_t)a.nin) {
+        Vec<TOut, CV> y;
+#pragma unroll
+        for (int c = 0; c < CV; ++c) y.v[c] = (TOut)x[c][u];
+        *(Vec<TOut, CV>*)(out + (size_t)row * E + e) = y;
+      }
     }
   }
+}
+
+template <typename TOut, int r>
+__device__ __forceinline__ void col_inv_tile(const NttLaunch& a, int prime, uint32_t it0,
+                                             uint32_t it1, uint32_t step) {
+  if (a.col_vec == 4) col_inv_items<TOut, r, 4>(a, prime, it0, it1, step);
+  else if (a.col_vec == 2) col_inv_items<TOut, r, 2>(a, prime, it0, it1, step);
+  else col_inv_items<TOut, r, 1>(a, prime, it0, it1, step);
 }
 
 }  // namespace pm

@@ -110,7 +110,9 @@ const NttTune& ntt_tune() {
   static const NttTune T = {env_int("PM_TUNE_NTT_MAXR", 4, 2, 4),
                             env_int("PM_TUNE_NTT_LDS_LOG", 14, 11, 15),
                             env_int("PM_TUNE_NTT_SPLIT", 4, 0, 4),
-                            env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16)};
+                            env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16),
+                            env_int("PM_TUNE_NTT_COLVEC_FWD", 4, 1, 4),
+                            env_int("PM_TUNE_NTT_COLVEC_INV", 4, 1, 4)};
   return T;
 }
 

@@ -43,6 +43,7 @@ PassPlan make_pass_plan(int logL);
 // PM_TUNE_NTT_SPLIT_MINLOG (smallest log2 L that is split, default 11).
 struct NttTune {
   int maxr, lds_log, split_r1, split_min_log;
+  int colvec_fwd, colvec_inv;  // most entries per column-pass item
 };
 const NttTune& ntt_tune();
 int split_stages(int logL);
