@@ -461,7 +461,7 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
         add(0, BK_COL_FWD, op, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
                                               a.col_vec * (1 << a.split), 0, 0);
         add(1, BK_BLOCK_FWD, op, q, neb, neb << a.split,
-            (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
+            (double)EB * (1u << a.blk_log) * (a.logL - a.split), block_lds_bytes(a), 0);
       } else {
         add(0, BK_FWD_LDS, op, q, neb, neb, (double)EB * L_ * (P.logL + 1), ntt_lds_bytes(a), 0);
       }
@@ -492,7 +492,7 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
     for (int q = 0; q < P.r; ++q) {
       if (a.split) {
         add(3, BK_BLOCK_INV, 0, q, neb, neb << a.split,
-            (double)EB * (1u << a.blk_log) * (a.logL - a.split), ntt_lds_bytes(a), 0);
+            (double)EB * (1u << a.blk_log) * (a.logL - a.split), block_lds_bytes(a), 0);
         const uint32_t items = col_items(a);
         const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
         add(4, BK_COL_INV, 0, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *

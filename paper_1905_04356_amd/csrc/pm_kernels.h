@@ -29,6 +29,7 @@ struct NttLaunch {
   int eb_log;                // log2(entries per workgroup) in the LDS kernel
   int vec;                   // residues per global load/store (1, 2, 4)
   int col_vec;               // column pass: consecutive entries per item (1, 2, 4)
+  int blk_pitch;             // block step: LDS words per position (>= 2^eb_log, 4 | pitch)
   int lds_stride;            // 32-bit words between entries in LDS
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers
@@ -84,6 +85,11 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
 // io_bytes: bytes per element of the coefficient-major side (the input of a
 // forward transform, the output of an inverse one).
 void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse);
+
+// LDS bytes of one block-step tile (2^blk_log positions, position-major).
+__host__ __device__ inline size_t block_lds_bytes(const NttLaunch& a) {
+  return (4ull * (size_t)a.blk_pitch) << a.blk_log;
+}
 
 // Work items of the column pass: one per (j < L / 2^split, group of col_vec
 // consecutive entries).

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kNT) void ntt_inv_kernel(NttLaunch a) {
 }
 
 template <bool DIF, int V>
-__global__ __launch_bounds__(kNT) void ntt_block_kernel(NttLaunch a) {
+__global__ __launch_bounds__(kNT, 4) void ntt_block_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];
   block_tile<DIF, V>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
 }
@@ -68,6 +68,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   a->col_vec = cv;
   const int B = 1 << a->blk_log;
   a->lds_stride = B + (B >> 5) + 1;
+  a->blk_pitch = ((1 << eb) + 3) / 4 * 4 + ntt_tune().blk_pad;
 }
 
 static size_t lds_bytes(const NttLaunch& a) {
@@ -75,8 +76,8 @@ static size_t lds_bytes(const NttLaunch& a) {
 }
 
 template <typename K>
-static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hipStream_t s) {
-  const size_t lds = lds_bytes(a);
+static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hipStream_t s,
+                      size_t lds) {
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kernel,
@@ -119,9 +120,10 @@ static int launch_col_inv_r(const NttLaunch& a, int nprimes, hipStream_t s) {
 template <bool DIF>
 static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
   const int zb = 1 << a.split;
-  if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4>, a, nprimes, zb, s);
-  if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2>, a, nprimes, zb, s);
-  return launch_lds(ntt_block_kernel<DIF, 1>, a, nprimes, zb, s);
+  const size_t lds = block_lds_bytes(a);
+  if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4>, a, nprimes, zb, s, lds);
+  if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2>, a, nprimes, zb, s, lds);
+  return launch_lds(ntt_block_kernel<DIF, 1>, a, nprimes, zb, s, lds);
 }
 
 template <typename TIn, bool REDUCE>
@@ -133,8 +135,8 @@ static int launch_fwd_t(const NttLaunch& a, int nprimes, hipStream_t s) {
   }
   // 32-bit inputs move in 16-byte vectors when E allows, 64-bit ones in 16 bytes
   constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;
-  if (a.vec >= VW) return launch_lds(ntt_fwd_kernel<TIn, REDUCE, VW>, a, nprimes, 1, s);
-  return launch_lds(ntt_fwd_kernel<TIn, REDUCE, 1>, a, nprimes, 1, s);
+  if (a.vec >= VW) return launch_lds(ntt_fwd_kernel<TIn, REDUCE, VW>, a, nprimes, 1, s, lds_bytes(a));
+  return launch_lds(ntt_fwd_kernel<TIn, REDUCE, 1>, a, nprimes, 1, s, lds_bytes(a));
 }
 
 int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
@@ -157,8 +159,8 @@ static int launch_inv_t(const NttLaunch& a, int nprimes, hipStream_t s) {
     return launch_col_inv_r<TOut>(a, nprimes, s);
   }
   constexpr int VW = sizeof(TOut) == 4 ? 4 : 2;
-  if (a.vec >= VW) return launch_lds(ntt_inv_kernel<TOut, VW>, a, nprimes, 1, s);
-  return launch_lds(ntt_inv_kernel<TOut, 1>, a, nprimes, 1, s);
+  if (a.vec >= VW) return launch_lds(ntt_inv_kernel<TOut, VW>, a, nprimes, 1, s, lds_bytes(a));
+  return launch_lds(ntt_inv_kernel<TOut, 1>, a, nprimes, 1, s, lds_bytes(a));
 }
 
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s) {

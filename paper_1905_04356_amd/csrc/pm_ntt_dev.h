@@ -257,12 +257,87 @@ __device__ __forceinline__ void inv_lds_tile(const NttLaunch& a, int prime, int 
 // Split transforms, LDS part: block z of 2^blk_log consecutive positions of
 // the point-major buffer `out`, transformed in place by passes 1 .. npass-1
 // (forward, DIF) or npass-1 .. 1 (inverse, DIT).
+//
+// The tile sits in LDS position-major, as in HBM: position t, entry e at word
+// t * pitch + e.  Rows move between HBM and LDS as whole vectors, and a pass
+// item takes EPI adjacent entries at its 2^r positions pos0 + u S, one vector
+// access per position.  Consecutive lanes take consecutive entry groups of
+// the same position group, so they share the twiddles of that group and
+// their LDS addresses differ by a constant.
+template <int r, int EPI, bool DIF>
+__device__ __forceinline__ void block_pass(uint32_t* lds, int pitch, int blk_log, int eb_log,
+                                           int s, const Tw* __restrict__ tw, uint32_t q) {
+  constexpr int R = 1 << r;
+  constexpr int epi_log = EPI == 4 ? 2 : EPI == 2 ? 1 : 0;
+  const int S = 1 << s;
+  const int glog = eb_log - epi_log;  // log2 entry groups per position
+  const int items = 1 << (blk_log - r + glog);
+  const int ustep = S * pitch;
+  for (int it = threadIdx.x; it < items; it += kNT) {
+    const int g = it & ((1 << glog) - 1);
+    const int w = it >> glog;
+    const int blk = w >> s, j = w & (S - 1);
+    uint32_t* base = lds + ((blk << (s + r)) + j) * pitch + g * EPI;
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+    uint32_t x[EPI][R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const Vec<uint32_t, EPI> v = *(const Vec<uint32_t, EPI>*)(base + u * ustep);
+#pragma unroll
+      for (int c = 0; c < EPI; ++c) x[c][u] = v.v[c];
+    }
+#pragma unroll
+    for (int c = 0; c < EPI; ++c) butterflies<r, DIF, false>(x[c], t, q);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      Vec<uint32_t, EPI> v;
+#pragma unroll
+      for (int c = 0; c < EPI; ++c) v.v[c] = x[c][u];
+      *(Vec<uint32_t, EPI>*)(base + u * ustep) = v;
+    }
+  }
+}
+
+// Entries per pass item: the widest vector (<= 4, <= the entries of the
+// tile) that still gives every thread of the workgroup an item.
+__device__ __forceinline__ int block_epi_log(int blk_log, int eb_log, int r) {
+  int e = eb_log < 2 ? eb_log : 2;
+  while (e > 0 && blk_log - r + eb_log - e < 9) --e;  // 2^9 = kNT
+  return e;
+}
+
+template <int r, bool DIF>
+__device__ __forceinline__ void block_pass_r(const NttLaunch& a, uint32_t* lds, const Tw* tw,
+                                             int ps, uint32_t q) {
+  const int s = a.stride_log[ps];
+  // (16 residues x 4 entries would not fit the register budget of 4 waves/SIMD)
+  switch (block_epi_log(a.blk_log, a.eb_log, r)) {
+    case 2: block_pass<r, r < 4 ? 4 : 2, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
+    case 1: block_pass<r, 2, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
+    default: block_pass<r, 1, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
+  }
+}
+
+template <bool DIF>
+__device__ __forceinline__ void block_run_pass(const NttLaunch& a, uint32_t* lds, const Tw* tw,
+                                               int ps, uint32_t q) {
+  switch (a.stages[ps]) {
+    case 1: block_pass_r<1, DIF>(a, lds, tw, ps, q); break;
+    case 2: block_pass_r<2, DIF>(a, lds, tw, ps, q); break;
+    case 3: block_pass_r<3, DIF>(a, lds, tw, ps, q); break;
+    default: block_pass_r<4, DIF>(a, lds, tw, ps, q); break;
+  }
+}
+
 template <bool DIF, int V>
 __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb, int z,
                                            uint32_t* lds) {
   const PrimeConst& P = a.pc[prime];
   const int EB = 1 << a.eb_log;
   const int e0 = eb * EB;
+  const int pitch = a.blk_pitch;
   uint32_t* buf = (uint32_t*)a.out + a.out_prime_stride * prime + ((size_t)z << a.blk_log) * a.E;
   const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
   const int total = 1 << (a.blk_log + glog);
@@ -275,29 +350,25 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
 #pragma unroll
       for (int v = 0; v < V; ++v) x.v[v] = 0;
     }
-#pragma unroll
-    for (int v = 0; v < V; ++v) lds[(e + v) * a.lds_stride + lds_pos(t)] = x.v[v];
+    *(Vec<uint32_t, V>*)(lds + t * pitch + e) = x;
   }
   __syncthreads();
   if (DIF) {
     for (int ps = 1; ps < a.npass; ++ps) {
-      run_pass<true, false>(a, lds, P.tw_fwd + a.tw_off[ps], a.blk_log, ps, P.q);
+      block_run_pass<true>(a, lds, P.tw_fwd + a.tw_off[ps], ps, P.q);
       __syncthreads();
     }
   } else {
     for (int ps = a.npass - 1; ps >= 1; --ps) {
-      run_pass<false, false>(a, lds, P.tw_inv + a.tw_off[ps], a.blk_log, ps, P.q);
+      block_run_pass<false>(a, lds, P.tw_inv + a.tw_off[ps], ps, P.q);
       __syncthreads();
     }
   }
   for (int idx = threadIdx.x; idx < total; idx += kNT) {
     const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
-    if (e0 + e < a.E) {
-      Vec<uint32_t, V> y;
-#pragma unroll
-      for (int v = 0; v < V; ++v) y.v[v] = lds[(e + v) * a.lds_stride + lds_pos(t)];
-      *(Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e) = y;
-    }
+    if (e0 + e < a.E)
+      *(Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e) =
+          *(const Vec<uint32_t, V>*)(lds + t * pitch + e);
   }
 }
 

@@ -44,6 +44,7 @@ PassPlan make_pass_plan(int logL);
 struct NttTune {
   int maxr, lds_log, split_r1, split_min_log;
   int colvec_fwd, colvec_inv;  // most entries per column-pass item
+  int blk_pad;                 // block step: LDS words of padding per position
 };
 const NttTune& ntt_tune();
 int split_stages(int logL);
