@@ -29,9 +29,14 @@ __device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t q) 
   return reduce_once(a + b, q);
 }
 
-// (a - b) mod q for a, b in [0, q).
+// (a - b) mod q for a, b in [0, q): min(a - b, a - b + q) in unsigned
+// arithmetic.  If a >= b the first is in [0, q) and the second is larger;
+// otherwise the first wraps to at least 2^32 - q > q and the second is the
+// residue in [1, q).
 __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t q) {
-  return reduce_once(a + (q - b), q);
+  const uint32_t d = a - b;
+  const uint32_t e = d + q;
+  return e < d ? e : d;
 }
 
 // a*w mod q in [0, 2q) for any a < 2^32, w < q, wp = floor(w*2^32/q).
@@ -45,6 +50,23 @@ __device__ __forceinline__ uint32_t mul_shoup_lazy(uint32_t a, uint32_t w, uint3
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp,
                                               uint32_t q) {
   return reduce_once(mul_shoup_lazy(a, w, wp, q), q);
+}
+
+// 2^32 - q, hidden from the optimizer (see mul_shoup_nq).
+__device__ __forceinline__ uint32_t opaque_neg(uint32_t q) {
+  uint32_t nq = 0u - q;
+  asm("" : "+v"(nq));
+  return nq;
+}
+
+// mul_shoup with nq = 2^32 - q: a*w - qt*q mod 2^32 is the low word of
+// qt*nq + (a*w mod 2^32), one v_mad_u64_u32 in place of a multiply and a
+// subtraction.  (With nq visible as 0 - q the compiler folds the product
+// back into the multiply-and-subtract form.)
+__device__ __forceinline__ uint32_t mul_shoup_nq(uint32_t a, uint32_t w, uint32_t wp,
+                                                 uint32_t q, uint32_t nq) {
+  const uint32_t qt = __umulhi(a, wp);
+  return reduce_once((uint32_t)((uint64_t)qt * nq + (uint64_t)(a * w)), q);
 }
 
 // x mod q for any 64-bit x; mu = floor((2^64-1)/q).

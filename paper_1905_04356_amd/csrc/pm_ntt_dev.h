@@ -62,6 +62,7 @@ struct alignas(sizeof(T) * V) Vec {
 template <int r, bool DIF, bool ZHI>
 __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q) {
   constexpr int R = 1 << r;
+  const uint32_t nq = opaque_neg(q);
   if (DIF) {
 #pragma unroll
     for (int v = r - 1; v >= 0; --v) {
@@ -71,11 +72,11 @@ __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q
         const int u2 = u | (1 << v);
         const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
         if (ZHI && v == r - 1) {
-          x[u2] = mul_shoup(x[u], tt.w, tt.wp, q);
+          x[u2] = mul_shoup_nq(x[u], tt.w, tt.wp, q, nq);
         } else {
           const uint32_t a0 = x[u], b0 = x[u2];
           x[u] = add_mod(a0, b0, q);
-          x[u2] = mul_shoup(a0 + (q - b0), tt.w, tt.wp, q);
+          x[u2] = mul_shoup_nq(a0 + (q - b0), tt.w, tt.wp, q, nq);
         }
       }
     }
@@ -88,7 +89,7 @@ __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q
         const int u2 = u | (1 << v);
         const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
         const uint32_t a0 = x[u];
-        const uint32_t b0 = mul_shoup(x[u2], tt.w, tt.wp, q);
+        const uint32_t b0 = mul_shoup_nq(x[u2], tt.w, tt.wp, q, nq);
         x[u] = add_mod(a0, b0, q);
         x[u2] = sub_mod(a0, b0, q);
       }

@@ -113,7 +113,7 @@ const NttTune& ntt_tune() {
                             env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16),
                             env_int("PM_TUNE_NTT_COLVEC_FWD", 4, 1, 4),
                             env_int("PM_TUNE_NTT_COLVEC_INV", 4, 1, 4),
-                            env_int("PM_TUNE_NTT_BLK_PAD", 4, 0, 64) & ~3};
+                            env_int("PM_TUNE_NTT_BLK_PAD", 0, 0, 64) & ~3};
   return T;
 }
 
