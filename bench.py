@@ -31,11 +31,16 @@ INT8_MFMA_PEAK_TOPS = 5000.0          # dense int8, 5.0 POP/s
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
 VALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # 39.3 T 32-bit lane-ops/s
 
-# 32-bit VALU operations of one radix-2 butterfly with canonical residues and
-# Shoup multiplication: modular add (add, sub, min), modular difference
-# (sub, add), product by the twiddle (mul_hi, mul_lo, mul_lo, sub) and its
-# final correction (sub, min).
-OPS_PER_BUTTERFLY = 11
+# 32-bit VALU operations of one radix-2 butterfly with canonical residues
+# (q may exceed 2^30, so no lazy reduction) and Shoup multiplication, whose
+# product a*w - floor(a*w'/2^32)*q mod 2^32 takes mul_hi, mul_lo and one
+# v_mad_u64_u32 (with 2^32 - q), plus the final correction (sub, min):
+#   forward (DIF): modular add (add, sub, min), difference plus q (sub, add),
+#     product (3) and correction (2): 10;
+#   inverse (DIT): product (3), correction (2), modular add (3), modular
+#     difference (sub, add, min): 11.
+OPS_FWD_BUTTERFLY = 10
+OPS_INV_BUTTERFLY = 11
 
 WORKLOADS = {
     # name: (p, m, n, k, d, elem dtype)
@@ -62,13 +67,13 @@ def kernel_work(kind, plan, p, m, n, k, d, eb):
     if kind == "ntt_fwd":
         E = m * n + n * k
         byts = eb * d * E + 4 * L * E * r
-        ops = OPS_PER_BUTTERFLY * (L // 2) * logL * E * r
+        ops = OPS_FWD_BUTTERFLY * (L // 2) * logL * E * r
         return byts, ops
     if kind == "ntt_inv":
         E = m * k
         out_b = eb if plan.mode == 0 else 4
         byts = 4 * L * E * r + out_b * (2 * d - 1) * E * r
-        ops = OPS_PER_BUTTERFLY * (L // 2) * logL * E * r
+        ops = OPS_INV_BUTTERFLY * (L // 2) * logL * E * r
         return byts, ops
     if kind == "pointwise":
         byts = 4 * L * (m * n + n * k + m * k) * r
@@ -103,6 +108,25 @@ def roofline_for(kind, byts, ops, seconds, plan):
     achieved = byts / seconds / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kind}
+
+
+def path_roofline(kernels, plan, device_ms):
+    """Roofline of the whole path: the sum over kernel kinds of the larger of
+    (algorithmic bytes at peak HBM bandwidth) and (algorithmic operations at
+    the peak of the unit that executes them), against the measured device
+    time of one product."""
+    floor_s = 0.0
+    for kind, kk in kernels.items():
+        t_hbm = kk["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
+        if kind in ("ntt_fwd", "ntt_inv"):
+            t_ops = kk["ops"] / (VALU_PEAK_TOPS * 1e12)
+        elif kind == "pointwise" and plan.pointwise == 1:
+            t_ops = 32.0 * kk["ops"] / (INT8_MFMA_PEAK_TOPS * 1e12)
+        else:
+            t_ops = 0.0
+        floor_s += max(t_hbm, t_ops)
+    return {"floor_us": floor_s * 1e6, "measured_us": device_ms * 1e3,
+            "frac": floor_s * 1e6 / (device_ms * 1e3)}
 
 
 def cpu_baseline(p, A, B, m, n, k, d, target_s):
@@ -256,7 +280,8 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
         if kind_of(name) and wscale:
             traffic[kind_of(name)] += v * wscale / steps_pmc
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
-              f"python3 bench.py --steps {steps_stats} --warmup 2 --no-cpu-baseline --no-batched")
+              f"python3 bench.py --steps {steps_stats} --warmup 2 --no-cpu-baseline --no-batched "
+              "--serving-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           "| kernel | calls | avg us | total ms | kind |", "|---|---|---|---|---|"]
@@ -271,7 +296,7 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
-                  "--no-cpu-baseline --no-batched")
+                  "--no-cpu-baseline --no-batched --serving-seconds 0")
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
@@ -433,6 +458,7 @@ def main():
         kernels[kind]["roofline"]["traffic"] = traffic.get(kind) if traffic else None
     dominant = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
     roof = dict(kernels[dominant]["roofline"])
+    roof["path"] = path_roofline(kernels, plan, ev0.elapsed_time(ev1) / args.steps)
 
     out = {
         "metric": "polymatrix mul mod p: m*n*k*d coefficient-MACs/s",

@@ -125,7 +125,7 @@ namespace pm {
 // All launch descriptors of one product; A, B, C device pointers, ws the
 // product's workspace (laid out by make_plan).
 int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                          ProductLaunches* L) {
+                          ProductLaunches* L, bool batched) {
   memset(L, 0, sizeof *L);
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
@@ -145,7 +145,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   L->pw_staged = 4ull * ((uint64_t)m * n + (uint64_t)n * k) <= 128 * 1024;
 
   NttLaunch& fa = L->f[0];
-  fill_ntt_launch(&fa, P.logL, m * n, d, P.elem_bytes, false);
+  fill_ntt_launch(&fa, P.logL, m * n, d, P.elem_bytes, false, batched);
   for (int i = 0; i < P.r; ++i) fa.pc[i] = pc[i];
   fa.in = A;
   fa.out = ahat;
@@ -154,7 +154,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& fb = L->f[1];
   fb = fa;
-  fill_ntt_launch(&fb, P.logL, n * k, d, P.elem_bytes, false);
+  fill_ntt_launch(&fb, P.logL, n * k, d, P.elem_bytes, false, batched);
   fb.in = B;
   fb.out = bhat;
 
@@ -177,7 +177,8 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& ic = L->inv;
   ic = fa;
-  fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1, P.mode == 1 ? 4 : P.elem_bytes, true);
+  fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1, P.mode == 1 ? 4 : P.elem_bytes, true,
+                  batched);
   ic.in = chat;
   ic.in_prime_stride = pstride;
   const uint64_t nout = (2ull * d - 1) * m * k;
@@ -332,7 +333,7 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   }
   NttLaunch a;
   memset(&a, 0, sizeof a);
-  fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false);
+  fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false, false);
   for (int i = 0; i < P.r; ++i) a.pc[i] = pc[i];
   a.in = X;
   a.out = Xe;
@@ -530,8 +531,11 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
   size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
     const Plan& P = plans[i];
-    int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i]);
+    int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i],
+                                   true);
     if (st != PM_OK) return st;
+    // the phase kernels run column items of one entry (register budget)
+    hp[i].f[0].col_vec = hp[i].f[1].col_vec = hp[i].inv.col_vec = 1;
     // given evaluations replace the forward transforms of that operand
     if (prods[i].A_eval) {
       hp[i].pw.ahat = (const uint32_t*)prods[i].A_eval;

@@ -26,8 +26,9 @@ struct ProductLaunches {
   int32_t pad[2];
 };
 
+// batched: launch parameters for the batched phase kernels.
 int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                          ProductLaunches* out);
+                          ProductLaunches* out, bool batched = false);
 
 // Tile kinds, grouped into phases that must run in order.
 enum BatchKind : uint16_t {

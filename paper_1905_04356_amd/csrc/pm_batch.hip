@@ -39,9 +39,9 @@ __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, ui
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
     switch (a.split) {
-      case 2: col_fwd_tile<TIn, RED, 2>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      case 3: col_fwd_tile<TIn, RED, 3>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      default: col_fwd_tile<TIn, RED, 4>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 2: col_fwd_items<TIn, RED, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 3: col_fwd_items<TIn, RED, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      default: col_fwd_items<TIn, RED, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
     }
   } else {
     constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;
@@ -53,9 +53,9 @@ __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, ui
 template <bool DIF>
 __device__ __forceinline__ void block_v(const NttLaunch& a, int prime, int x, int z,
                                         uint32_t* lds) {
-  if (a.vec == 4) block_tile<DIF, 4>(a, prime, x, z, lds);
-  else if (a.vec == 2) block_tile<DIF, 2>(a, prime, x, z, lds);
-  else block_tile<DIF, 1>(a, prime, x, z, lds);
+  if (a.vec == 4) block_tile<DIF, 4, kBatchNT, 2>(a, prime, x, z, lds);
+  else if (a.vec == 2) block_tile<DIF, 2, kBatchNT, 2>(a, prime, x, z, lds);
+  else block_tile<DIF, 1, kBatchNT, 2>(a, prime, x, z, lds);
 }
 
 template <typename TOut>
@@ -66,9 +66,9 @@ __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, ui
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
     switch (a.split) {
-      case 2: col_inv_tile<TOut, 2>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      case 3: col_inv_tile<TOut, 3>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      default: col_inv_tile<TOut, 4>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 2: col_inv_items<TOut, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 3: col_inv_items<TOut, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      default: col_inv_items<TOut, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
     }
   } else {
     constexpr int VW = sizeof(TOut) == 4 ? 4 : 2;
@@ -77,8 +77,10 @@ __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, ui
   }
 }
 
+// The block phases (1, 3) are held to 4 waves per SIMD so that two
+// 512-thread workgroups share a CU.
 template <int PHASE, int NT>
-__global__ __launch_bounds__(NT) void batch_kernel(const ProductLaunches* prods,
+__global__ __launch_bounds__(NT, (PHASE == 1 || PHASE == 3) ? 4 : 1) void batch_kernel(const ProductLaunches* prods,
                                                    const BatchSeg* segs, int nseg) {
   extern __shared__ uint32_t lds[];
   const uint32_t b = blockIdx.x;

@@ -84,7 +84,9 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
 // Fill the launch descriptor of a transform for (logL, E, nin).
 // io_bytes: bytes per element of the coefficient-major side (the input of a
 // forward transform, the output of an inverse one).
-void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse);
+// batched: parameters for the batched phase kernels (512-thread block tiles).
+void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse,
+                     bool batched);
 
 // LDS bytes of one block-step tile (2^blk_log positions, position-major).
 __host__ __device__ inline size_t block_lds_bytes(const NttLaunch& a) {

@@ -18,10 +18,10 @@ __global__ __launch_bounds__(kNT) void ntt_inv_kernel(NttLaunch a) {
   inv_lds_tile<TOut, V>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
-template <bool DIF, int V>
-__global__ __launch_bounds__(kNT, 4) void ntt_block_kernel(NttLaunch a) {
+template <bool DIF, int V, int NT>
+__global__ __launch_bounds__(NT, 4) void ntt_block_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];
-  block_tile<DIF, V>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
+  block_tile<DIF, V, NT>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
 }
 
 template <typename TIn, bool REDUCE, int r>
@@ -38,7 +38,8 @@ __global__ __launch_bounds__(kColNT) void ntt_col_inv_kernel(NttLaunch a) {
 
 // ---- host side ---------------------------------------------------------------
 
-void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse) {
+void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse,
+                     bool batched) {
   const PassPlan PP = make_pass_plan(logL);
   a->logL = logL;
   a->npass = PP.npass;
@@ -53,7 +54,8 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   a->E = E;
   // about 2^lds_log residues of LDS per workgroup, at least one entry, no
   // more slots than entries
-  int eb = ntt_tune().lds_log - a->blk_log;
+  const NttTune& T = ntt_tune();
+  int eb = (PP.split ? (batched ? T.batch_tile_log : T.blk_tile_log) : T.lds_log) - a->blk_log;
   if (eb < 0) eb = 0;
   while (eb > 0 && (1 << (eb - 1)) >= E) --eb;
   a->eb_log = eb;
@@ -77,7 +79,7 @@ static size_t lds_bytes(const NttLaunch& a) {
 
 template <typename K>
 static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hipStream_t s,
-                      size_t lds) {
+                      size_t lds, int nt = kNT) {
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kernel,
@@ -86,7 +88,7 @@ static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hi
   }
   const int EB = 1 << a.eb_log;
   dim3 grid((a.E + EB - 1) / EB, nprimes, zblocks);
-  hipLaunchKernelGGL(kernel, grid, dim3(kNT), lds, s, a);
+  hipLaunchKernelGGL(kernel, grid, dim3(nt), lds, s, a);
   return hipGetLastError();
 }
 
@@ -121,9 +123,14 @@ template <bool DIF>
 static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
   const int zb = 1 << a.split;
   const size_t lds = block_lds_bytes(a);
-  if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4>, a, nprimes, zb, s, lds);
-  if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2>, a, nprimes, zb, s, lds);
-  return launch_lds(ntt_block_kernel<DIF, 1>, a, nprimes, zb, s, lds);
+  if (ntt_tune().blk_nt == 256) {
+    if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4, 256>, a, nprimes, zb, s, lds, 256);
+    if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2, 256>, a, nprimes, zb, s, lds, 256);
+    return launch_lds(ntt_block_kernel<DIF, 1, 256>, a, nprimes, zb, s, lds, 256);
+  }
+  if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4, kNT>, a, nprimes, zb, s, lds);
+  if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2, kNT>, a, nprimes, zb, s, lds);
+  return launch_lds(ntt_block_kernel<DIF, 1, kNT>, a, nprimes, zb, s, lds);
 }
 
 template <typename TIn, bool REDUCE>

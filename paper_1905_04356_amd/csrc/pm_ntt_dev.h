@@ -265,7 +265,7 @@ __device__ __forceinline__ void inv_lds_tile(const NttLaunch& a, int prime, int 
 // access per position.  Consecutive lanes take consecutive entry groups of
 // the same position group, so they share the twiddles of that group and
 // their LDS addresses differ by a constant.
-template <int r, int EPI, bool DIF>
+template <int r, int EPI, bool DIF, int NT>
 __device__ __forceinline__ void block_pass(uint32_t* lds, int pitch, int blk_log, int eb_log,
                                            int s, const Tw* __restrict__ tw, uint32_t q) {
   constexpr int R = 1 << r;
@@ -274,7 +274,7 @@ __device__ __forceinline__ void block_pass(uint32_t* lds, int pitch, int blk_log
   const int glog = eb_log - epi_log;  // log2 entry groups per position
   const int items = 1 << (blk_log - r + glog);
   const int ustep = S * pitch;
-  for (int it = threadIdx.x; it < items; it += kNT) {
+  for (int it = threadIdx.x; it < items; it += NT) {
     const int g = it & ((1 << glog) - 1);
     const int w = it >> glog;
     const int blk = w >> s, j = w & (S - 1);
@@ -302,37 +302,46 @@ __device__ __forceinline__ void block_pass(uint32_t* lds, int pitch, int blk_log
 }
 
 // Entries per pass item: the widest vector (<= 4, <= the entries of the
-// tile) that still gives every thread of the workgroup an item.
-__device__ __forceinline__ int block_epi_log(int blk_log, int eb_log, int r) {
+// tile) that still gives every one of the 2^nt_log threads an item.
+__device__ __forceinline__ int block_epi_log(int blk_log, int eb_log, int r, int nt_log) {
   int e = eb_log < 2 ? eb_log : 2;
-  while (e > 0 && blk_log - r + eb_log - e < 9) --e;  // 2^9 = kNT
+  while (e > 0 && blk_log - r + eb_log - e < nt_log) --e;
   return e;
 }
 
-template <int r, bool DIF>
+template <int r, bool DIF, int NT, int MAXEPI>
 __device__ __forceinline__ void block_pass_r(const NttLaunch& a, uint32_t* lds, const Tw* tw,
                                              int ps, uint32_t q) {
   const int s = a.stride_log[ps];
-  // (16 residues x 4 entries would not fit the register budget of 4 waves/SIMD)
-  switch (block_epi_log(a.blk_log, a.eb_log, r)) {
-    case 2: block_pass<r, r < 4 ? 4 : 2, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
-    case 1: block_pass<r, 2, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
-    default: block_pass<r, 1, DIF>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
+  // (16 residues x 4 entries would not fit the register budget of 4 waves
+  // per SIMD; with MAXEPI < 4 radix-16 items take a single entry)
+  constexpr int EPI2 = (r == 4 && MAXEPI < 4) ? 1 : 2;
+  switch (block_epi_log(a.blk_log, a.eb_log, r, NT == 256 ? 8 : 9)) {
+    case 2:
+      block_pass<r, (r < 4 && MAXEPI >= 4) ? 4 : EPI2, DIF, NT>(lds, a.blk_pitch, a.blk_log,
+                                                                a.eb_log, s, tw, q);
+      break;
+    case 1: block_pass<r, EPI2, DIF, NT>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
+    default: block_pass<r, 1, DIF, NT>(lds, a.blk_pitch, a.blk_log, a.eb_log, s, tw, q); break;
   }
 }
 
-template <bool DIF>
+template <bool DIF, int NT, int MAXEPI>
 __device__ __forceinline__ void block_run_pass(const NttLaunch& a, uint32_t* lds, const Tw* tw,
                                                int ps, uint32_t q) {
   switch (a.stages[ps]) {
-    case 1: block_pass_r<1, DIF>(a, lds, tw, ps, q); break;
-    case 2: block_pass_r<2, DIF>(a, lds, tw, ps, q); break;
-    case 3: block_pass_r<3, DIF>(a, lds, tw, ps, q); break;
-    default: block_pass_r<4, DIF>(a, lds, tw, ps, q); break;
+    case 1: block_pass_r<1, DIF, NT, MAXEPI>(a, lds, tw, ps, q); break;
+    case 2: block_pass_r<2, DIF, NT, MAXEPI>(a, lds, tw, ps, q); break;
+    case 3: block_pass_r<3, DIF, NT, MAXEPI>(a, lds, tw, ps, q); break;
+    default: block_pass_r<4, DIF, NT, MAXEPI>(a, lds, tw, ps, q); break;
   }
 }
 
-template <bool DIF, int V>
+// One tile with NT threads (512 in the batched phase kernels; the
+// single-product kernel may use 256 so that more tiles share a CU) and at
+// most MAXEPI entries per pass item (the batched kernels use 2, and 1 for
+// radix-16 passes, to stay within their register budget).
+template <bool DIF, int V, int NT = kNT, int MAXEPI = 4>
 __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb, int z,
                                            uint32_t* lds) {
   const PrimeConst& P = a.pc[prime];
@@ -342,7 +351,7 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
   uint32_t* buf = (uint32_t*)a.out + a.out_prime_stride * prime + ((size_t)z << a.blk_log) * a.E;
   const int glog = a.eb_log - (V == 4 ? 2 : V == 2 ? 1 : 0);
   const int total = 1 << (a.blk_log + glog);
-  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
     const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     Vec<uint32_t, V> x;
     if (e0 + e < a.E) {
@@ -356,16 +365,16 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
   __syncthreads();
   if (DIF) {
     for (int ps = 1; ps < a.npass; ++ps) {
-      block_run_pass<true>(a, lds, P.tw_fwd + a.tw_off[ps], ps, P.q);
+      block_run_pass<true, NT, MAXEPI>(a, lds, P.tw_fwd + a.tw_off[ps], ps, P.q);
       __syncthreads();
     }
   } else {
     for (int ps = a.npass - 1; ps >= 1; --ps) {
-      block_run_pass<false>(a, lds, P.tw_inv + a.tw_off[ps], ps, P.q);
+      block_run_pass<false, NT, MAXEPI>(a, lds, P.tw_inv + a.tw_off[ps], ps, P.q);
       __syncthreads();
     }
   }
-  for (int idx = threadIdx.x; idx < total; idx += kNT) {
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
     const int t = idx >> glog, e = (idx & ((1 << glog) - 1)) * V;
     if (e0 + e < a.E)
       *(Vec<uint32_t, V>*)(buf + (size_t)t * a.E + e0 + e) =

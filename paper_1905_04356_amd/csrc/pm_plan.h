@@ -45,6 +45,9 @@ struct NttTune {
   int maxr, lds_log, split_r1, split_min_log;
   int colvec_fwd, colvec_inv;  // most entries per column-pass item
   int blk_pad;                 // block step: LDS words of padding per position
+  int blk_nt;                  // block step: threads per workgroup (256 or 512)
+  int blk_tile_log;            // block step: log2 residues per tile
+  int batch_tile_log;          // ... in the batched phase kernels
 };
 const NttTune& ntt_tune();
 int split_stages(int logL);
