@@ -7,6 +7,11 @@ checker built from the definitions in Section 2 of Hyun, Neiger, Schost
 * `polymatmul`       -- the full product C = A B over F_p, coefficient-major.
 * `polymatmul_entries` -- selected whole output entries C_ij (all 2d-1
                         coefficients), for sizes where the full product is slow.
+* `middle_product`, `middle_entries` -- coefficients lo .. lo+len-1 of A B
+                        for operands of different lengths: the whole product,
+                        then the slice (Section 2, "Polynomial
+                        multiplication": the direct approach to the middle
+                        product).
 * `point_check`      -- C(r) == A(r) B(r) at seeded points r of F_p: the
                         evaluation map at r is a ring homomorphism, which is
                         what evaluation/interpolation schemes rest on.
@@ -25,8 +30,8 @@ import os
 import numpy as np
 
 __all__ = ["lib", "is_prime", "powmod", "polymatmul", "polymatmul_entries",
-           "eval_at", "matmul", "polymul", "point_check", "freivalds_check",
-           "host_threads"]
+           "middle_product", "middle_entries", "eval_at", "matmul", "polymul",
+           "point_check", "freivalds_check", "host_threads"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -131,6 +136,44 @@ def polymatmul_entries(p: int, A, B, pairs, threads: int | None = None,
     if rc != 0:
         raise ValueError("oracle rejected arguments")
     return out
+
+
+def _pad_to(X: np.ndarray, d: int) -> np.ndarray:
+    """X with zero coefficients appended up to d (the polynomial is unchanged)."""
+    if X.shape[0] == d:
+        return X
+    out = np.zeros((d,) + X.shape[1:], dtype=np.uint64)
+    out[:X.shape[0]] = X
+    return out
+
+
+def _check_window(da: int, db: int, lo: int, length: int) -> None:
+    if lo < 0 or length < 1 or lo + length > da + db - 1:
+        raise ValueError("window outside the product's coefficients")
+
+
+def middle_product(p: int, A, B, lo: int, length: int, threads: int | None = None,
+                   L=None) -> np.ndarray:
+    """Coefficients lo .. lo+length-1 of A B mod p, A: (da, m, n),
+    B: (db, n, k) -> (length, m, k).  The paper's MiddleProduct(F, G, c, d)
+    is middle_product(p, F, G, c, d) with F of c and G of c+d coefficients."""
+    A, B = _u64(A), _u64(B)
+    da, db = A.shape[0], B.shape[0]
+    _check_window(da, db, lo, length)
+    d = max(da, db)
+    C = polymatmul(p, _pad_to(A, d), _pad_to(B, d), threads=threads, L=L)
+    return np.ascontiguousarray(C[lo:lo + length])
+
+
+def middle_entries(p: int, A, B, lo: int, length: int, pairs,
+                   threads: int | None = None, L=None) -> np.ndarray:
+    """Rows out[s, c] = (A B)[lo + c, i_s, j_s] for the (i, j) pairs given."""
+    A, B = _u64(A), _u64(B)
+    da, db = A.shape[0], B.shape[0]
+    _check_window(da, db, lo, length)
+    d = max(da, db)
+    rows = polymatmul_entries(p, _pad_to(A, d), _pad_to(B, d), pairs, threads=threads, L=L)
+    return np.ascontiguousarray(rows[:, lo:lo + length])
 
 
 def eval_at(p: int, X, r: int, L=None) -> np.ndarray:
