@@ -112,6 +112,34 @@ pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                      const uint64_t* A, const uint64_t* B, uint64_t* C,
                      void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* Middle product, and in general a window of coefficients of a product
+ * (Section 2, "Polynomial multiplication": MiddleProduct(F, G, c, d) returns
+ * the coefficients of degrees c .. c+d-1 of F G for F in K[x]_c and G in
+ * K[x]_{c+d}; Section 3, Algorithm PM-Basis, uses its matrix version for the
+ * residual).  Here A is an (m x n) matrix with da coefficients (degree < da),
+ * B an (n x k) matrix with db coefficients, both coefficient-major as for
+ * pm_mul_*, and C receives coefficients lo .. lo+len-1 of A B mod p
+ * (len*m*k elements, row c of C = coefficient lo + c).  The paper's
+ * MiddleProduct is da = c, db = c + d, lo = c, len = d.  The transform length
+ * is the least power of two >= max(da + db - 1 - lo, lo + len): a
+ * coefficient of degree >= L that wraps around lands below lo, so the window
+ * is exact, and the middle product with c = d costs about half the points of
+ * the whole product.  Requires lo >= 0, len >= 1 and lo + len <= da + db - 1
+ * (else PM_EINVAL).  Pointer, alignment, overlap and workspace rules and the
+ * other status codes are those of pm_mul_*; pm_middle_plan reports the plan
+ * and workspace size.  Asynchronous on `stream`. */
+pm_status pm_middle_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
+                         int32_t db, int32_t lo, int32_t len, int32_t elem_bytes,
+                         pm_plan_info* out);
+pm_status pm_middle_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t da,
+                        int32_t db, int32_t lo, int32_t len, const uint32_t* A,
+                        const uint32_t* B, uint32_t* C, void* workspace,
+                        uint64_t workspace_bytes, void* stream);
+pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
+                        int32_t db, int32_t lo, int32_t len, const uint64_t* A,
+                        const uint64_t* B, uint64_t* C, void* workspace,
+                        uint64_t workspace_bytes, void* stream);
+
 /* One product of a batch; the pointers follow the pm_mul_* layout rules.
  * A_eval / B_eval: optional evaluations of A / B made by pm_eval_* (NULL:
  * the batch transforms the operand itself).  Given evaluations are used in

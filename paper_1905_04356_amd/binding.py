@@ -26,7 +26,7 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
            "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_eval_bytes", "pm_eval_u32",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
-           "pm_sync")
+           "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
@@ -84,12 +84,17 @@ def lib():
     L.pm_eval_bytes.argtypes = [u64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)]
     L.pm_eval_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, u64, vp]
     L.pm_eval_u64.argtypes = [u64, i32, i32, i32, i32, vp, vp, u64, vp]
+    L.pm_middle_plan.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, i32,
+                                 ctypes.POINTER(pm_plan_info)]
+    L.pm_middle_u32.argtypes = [u32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
+    L.pm_middle_u64.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
-                 "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64"):
+                 "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
+                 "pm_middle_u32", "pm_middle_u64"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -191,3 +196,19 @@ def pm_eval_u32(p, role, rows, cols, d, X, X_eval, eval_bytes, stream) -> int:
 
 def pm_eval_u64(p, role, rows, cols, d, X, X_eval, eval_bytes, stream) -> int:
     return lib().pm_eval_u64(p, role, rows, cols, d, X, X_eval, eval_bytes, stream)
+
+
+def pm_middle_plan(p: int, m: int, n: int, k: int, da: int, db: int, lo: int, length: int,
+                   elem_bytes: int) -> pm_plan_info:
+    info = pm_plan_info()
+    _check(lib().pm_middle_plan(p, m, n, k, da, db, lo, length, elem_bytes,
+                                ctypes.byref(info)), "pm_middle_plan")
+    return info
+
+
+def pm_middle_u32(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_middle_u32(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream)
+
+
+def pm_middle_u64(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_middle_u64(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream)

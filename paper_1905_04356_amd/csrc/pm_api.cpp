@@ -25,6 +25,16 @@
 
 using namespace pm;
 
+static void fill_plan_info(const Plan& P, pm_plan_info* out) {
+  memset(out, 0, sizeof *out);
+  out->mode = P.mode;
+  out->log2_len = P.logL;
+  out->num_primes = P.r;
+  out->pointwise = P.pointwise;
+  for (int i = 0; i < P.r; ++i) out->primes[i] = P.q[i];
+  out->workspace_bytes = P.ws_bytes;
+}
+
 extern "C" {
 
 const char* pm_status_str(int status) {
@@ -49,13 +59,7 @@ pm_status pm_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int32_
   Plan P;
   int st = make_plan(p, m, n, k, d, elem_bytes, &P);
   if (st != PM_OK) return (pm_status)st;
-  memset(out, 0, sizeof *out);
-  out->mode = P.mode;
-  out->log2_len = P.logL;
-  out->num_primes = P.r;
-  out->pointwise = P.pointwise;
-  for (int i = 0; i < P.r; ++i) out->primes[i] = P.q[i];
-  out->workspace_bytes = P.ws_bytes;
+  fill_plan_info(P, out);
   return PM_OK;
 }
 
@@ -83,8 +87,8 @@ int check_operands(const Plan& P, const void* A, const void* B, void* C) {
   if (!A || !B || !C) return PM_EINVAL;
   if (((uintptr_t)A | (uintptr_t)B | (uintptr_t)C) & 15) return PM_EINVAL;
   const uint64_t eb = (uint64_t)P.elem_bytes;
-  const uint64_t na = eb * P.d * P.m * P.n, nb = eb * P.d * P.n * P.k;
-  const uint64_t nc = eb * (2ull * P.d - 1) * P.m * P.k;
+  const uint64_t na = eb * P.da * P.m * P.n, nb = eb * P.db * P.n * P.k;
+  const uint64_t nc = eb * (uint64_t)P.nout * P.m * P.k;
   if (overlap(C, nc, A, na) || overlap(C, nc, B, nb)) return PM_EINVAL;
   return PM_OK;
 }
@@ -132,7 +136,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
     int st = get_prime_const(P.q[i], P.logL, &pc[i]);
     if (st != PM_OK) return st;
   }
-  const int m = P.m, n = P.n, k = P.k, d = P.d;
+  const int m = P.m, n = P.n, k = P.k;
   const uint64_t pstride = P.prime_stride / 4;  // in u32 elements
   uint32_t* ahat = (uint32_t*)(ws + P.off_ahat);
   uint32_t* bhat = (uint32_t*)(ws + P.off_bhat);
@@ -145,7 +149,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   L->pw_staged = 4ull * ((uint64_t)m * n + (uint64_t)n * k) <= 128 * 1024;
 
   NttLaunch& fa = L->f[0];
-  fill_ntt_launch(&fa, P.logL, m * n, d, P.elem_bytes, false, batched);
+  fill_ntt_launch(&fa, P.logL, m * n, P.da, P.elem_bytes, false, batched);
   for (int i = 0; i < P.r; ++i) fa.pc[i] = pc[i];
   fa.in = A;
   fa.out = ahat;
@@ -154,7 +158,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& fb = L->f[1];
   fb = fa;
-  fill_ntt_launch(&fb, P.logL, n * k, d, P.elem_bytes, false, batched);
+  fill_ntt_launch(&fb, P.logL, n * k, P.db, P.elem_bytes, false, batched);
   fb.in = B;
   fb.out = bhat;
 
@@ -177,11 +181,12 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& ic = L->inv;
   ic = fa;
-  fill_ntt_launch(&ic, P.logL, m * k, 2 * d - 1, P.mode == 1 ? 4 : P.elem_bytes, true,
+  fill_ntt_launch(&ic, P.logL, m * k, P.nout, P.mode == 1 ? 4 : P.elem_bytes, true,
                   batched);
+  ic.out_lo = P.lo;
   ic.in = chat;
   ic.in_prime_stride = pstride;
-  const uint64_t nout = (2ull * d - 1) * m * k;
+  const uint64_t nout = (uint64_t)P.nout * m * k;
   if (P.mode == 0) {
     ic.out = C;
     ic.out_prime_stride = 0;
@@ -258,6 +263,21 @@ pm_status mul_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int
   return (pm_status)run_product(P, A, B, C, (uint8_t*)ws, (hipStream_t)stream);
 }
 
+pm_status middle_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
+                        int32_t lo, int32_t len, int elem_bytes, const void* A, const void* B,
+                        void* C, void* ws, uint64_t ws_bytes, void* stream) {
+  Plan P;
+  int st = make_slice_plan(p, m, n, k, da, db, lo, len, elem_bytes, &P);
+  if (st != PM_OK) return (pm_status)st;
+  st = check_operands(P, A, B, C);
+  if (st != PM_OK) return (pm_status)st;
+  const uint64_t eb = (uint64_t)elem_bytes;
+  st = check_workspace(ws, ws_bytes, P.ws_bytes, A, eb * da * m * n, B, eb * db * n * k, C,
+                       eb * (uint64_t)len * m * k);
+  if (st != PM_OK) return (pm_status)st;
+  return (pm_status)run_product(P, A, B, C, (uint8_t*)ws, (hipStream_t)stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,6 +292,30 @@ pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, con
                      const uint64_t* B, uint64_t* C, void* workspace, uint64_t workspace_bytes,
                      void* stream) {
   return mul_common(p, m, n, k, d, 8, A, B, C, workspace, workspace_bytes, stream);
+}
+
+pm_status pm_middle_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
+                         int32_t lo, int32_t len, int32_t elem_bytes, pm_plan_info* out) {
+  if (!out) return PM_EINVAL;
+  Plan P;
+  int st = make_slice_plan(p, m, n, k, da, db, lo, len, elem_bytes, &P);
+  if (st != PM_OK) return (pm_status)st;
+  fill_plan_info(P, out);
+  return PM_OK;
+}
+
+pm_status pm_middle_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
+                        int32_t lo, int32_t len, const uint32_t* A, const uint32_t* B,
+                        uint32_t* C, void* workspace, uint64_t workspace_bytes, void* stream) {
+  return middle_common(p, m, n, k, da, db, lo, len, 4, A, B, C, workspace, workspace_bytes,
+                       stream);
+}
+
+pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
+                        int32_t lo, int32_t len, const uint64_t* A, const uint64_t* B,
+                        uint64_t* C, void* workspace, uint64_t workspace_bytes, void* stream) {
+  return middle_common(p, m, n, k, da, db, lo, len, 8, A, B, C, workspace, workspace_bytes,
+                       stream);
 }
 
 pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count, int32_t elem_bytes,
@@ -796,8 +840,8 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
     if (((uintptr_t)prods[i].A_eval | (uintptr_t)prods[i].B_eval) & 255) return PM_EINVAL;
     const uint64_t eb = (uint64_t)elem_bytes;
     const Plan& P = plans[i];
-    st = check_workspace(ws, ws_bytes, lay.total, prods[i].A, eb * P.d * P.m * P.n, prods[i].B,
-                         eb * P.d * P.n * P.k, prods[i].C, eb * (2ull * P.d - 1) * P.m * P.k);
+    st = check_workspace(ws, ws_bytes, lay.total, prods[i].A, eb * P.da * P.m * P.n, prods[i].B,
+                         eb * P.db * P.n * P.k, prods[i].C, eb * (uint64_t)P.nout * P.m * P.k);
     if (st != PM_OK) return (pm_status)st;
   }
   return (pm_status)run_batch(p, elem_bytes, plans, offs, lay, prods, (uint8_t*)ws, ws_bytes,

@@ -25,6 +25,7 @@ struct NttLaunch {
   int stride_log[kMaxPasses];
   uint32_t tw_off[kMaxPasses];
   int nin;                   // forward: coefficients read; inverse: written
+  int out_lo;                // inverse: first coefficient written (to row 0)
   int E;                     // entries per point
   int eb_log;                // log2(entries per workgroup) in the LDS kernel
   int vec;                   // residues per global load/store (1, 2, 4)

@@ -51,6 +51,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
     a->tw_off[i] = i < PP.npass ? PP.tw_off[i] : 0;
   }
   a->nin = nin;
+  a->out_lo = 0;
   a->E = E;
   // about 2^lds_log residues of LDS per workgroup, at least one entry, no
   // more slots than entries
@@ -66,6 +67,8 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   // column items move at most 16 bytes per row access
   int cv = inverse ? ntt_tune().colvec_inv : ntt_tune().colvec_fwd;
   if (cv == 3) cv = 2;
+  // inputs longer than L/2 take the one-entry full-load column pass
+  if (!inverse && 2 * nin > (1 << logL)) cv = 1;
   while (cv > 1 && ((E % cv) != 0 || cv * io_bytes > 16)) cv >>= 1;
   a->col_vec = cv;
   const int B = 1 << a->blk_log;

@@ -215,7 +215,7 @@ __device__ __forceinline__ void fwd_lds_tile(const NttLaunch& a, int prime, int 
 }
 
 // Unsplit inverse transform: point-major input to coefficient-major output
-// (rows < nin).
+// (coefficients out_lo .. out_lo + nin - 1 to rows 0 .. nin - 1).
 template <typename TOut, int V>
 __device__ __forceinline__ void inv_lds_tile(const NttLaunch& a, int prime, int eb,
                                              uint32_t* lds) {
@@ -249,7 +249,8 @@ __device__ __forceinline__ void inv_lds_tile(const NttLaunch& a, int prime, int 
     if (e0 + e < a.E) {
       Vec<TOut, V> y;
 #pragma unroll
-      for (int v = 0; v < V; ++v) y.v[v] = (TOut)lds[(e + v) * a.lds_stride + lds_pos(c)];
+      for (int v = 0; v < V; ++v)
+        y.v[v] = (TOut)lds[(e + v) * a.lds_stride + lds_pos(c + a.out_lo)];
       *(Vec<TOut, V>*)(out + (size_t)c * a.E + e0 + e) = y;
     }
   }
@@ -384,10 +385,12 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
 
 // First forward pass of a split transform, r stages at stride S = L / 2^r,
 // items [it0, it1) with stride `step`: item (j, g) reads, for the CV entries
-// e = g CV .. g CV + CV - 1, rows j + u S (u < 2^(r-1); the upper half is
-// zero padding since nin <= L/2) of the coefficient-major input and writes
-// all 2^r rows of the point-major buffer.  The entries share the twiddles.
-template <typename TIn, bool REDUCE, int r, int CV>
+// e = g CV .. g CV + CV - 1, the rows j + u S below nin of the
+// coefficient-major input and writes all 2^r rows of the point-major buffer.
+// ZHI (nin <= L/2): rows u >= 2^(r-1) are zero padding, not read, and the
+// first stage reduces to products by the twiddles.  The entries share the
+// twiddles.
+template <typename TIn, bool REDUCE, int r, int CV, bool ZHI = true>
 __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uint32_t it0,
                                               uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
@@ -407,7 +410,8 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
       Vec<TIn, CV> v;
 #pragma unroll
       for (int c = 0; c < CV; ++c) v.v[c] = 0;
-      if (u < R / 2 && row < (uint32_t)a.nin) v = *(const Vec<TIn, CV>*)(in + (size_t)row * E + e);
+      if ((!ZHI || u < R / 2) && row < (uint32_t)a.nin)
+        v = *(const Vec<TIn, CV>*)(in + (size_t)row * E + e);
 #pragma unroll
       for (int c = 0; c < CV; ++c)
         x[c][u] = REDUCE ? reduce_u64((uint64_t)v.v[c], q, P.mu) : (uint32_t)v.v[c];
@@ -416,7 +420,7 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
 #pragma unroll
     for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
 #pragma unroll
-    for (int c = 0; c < CV; ++c) butterflies<r, true, true>(x[c], t, q);
+    for (int c = 0; c < CV; ++c) butterflies<r, true, ZHI>(x[c], t, q);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       Vec<uint32_t, CV> y;
@@ -430,14 +434,19 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
 template <typename TIn, bool REDUCE, int r>
 __device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint32_t it0,
                                              uint32_t it1, uint32_t step) {
+  if (2 * a.nin > (1 << a.logL)) {  // inputs longer than L/2 (coefficient windows)
+    col_fwd_items<TIn, REDUCE, r, 1, false>(a, prime, it0, it1, step);
+    return;
+  }
   if (a.col_vec == 4) col_fwd_items<TIn, REDUCE, r, 4>(a, prime, it0, it1, step);
   else if (a.col_vec == 2) col_fwd_items<TIn, REDUCE, r, 2>(a, prime, it0, it1, step);
   else col_fwd_items<TIn, REDUCE, r, 1>(a, prime, it0, it1, step);
 }
 
 // Last inverse pass of a split transform: item (j, g) reads rows j + u S of
-// the point-major buffer for CV consecutive entries and writes the rows
-// below nin of the coefficient-major output.
+// the point-major buffer for CV consecutive entries and writes coefficients
+// out_lo .. out_lo + nin - 1 to rows 0 .. nin - 1 of the coefficient-major
+// output.
 template <typename TOut, int r, int CV>
 __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uint32_t it0,
                                               uint32_t it1, uint32_t step) {
@@ -464,7 +473,7 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
     for (int c = 0; c < CV; ++c) butterflies<r, false, false>(x[c], t, P.q);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const uint32_t row = j + u * S;
+      const uint32_t row = j + u * S - (uint32_t)a.out_lo;  // wraps above nin below out_lo
       if (row < (uint32_t)a.nin) {
         Vec<TOut, CV> y;
 #pragma unroll

@@ -13,6 +13,7 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -202,32 +203,39 @@ static int choose_pointwise(int m, int n, int k) {
   return mfma_ok ? 1 : 0;
 }
 
-int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out) {
+int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
+                    int elem_bytes, Plan* out) {
   if (!out) return PM_EINVAL;
   if (elem_bytes != 4 && elem_bytes != 8) return PM_EINVAL;
-  if (m < 1 || n < 1 || k < 1 || d < 1) return PM_EINVAL;
+  if (m < 1 || n < 1 || k < 1 || da < 1 || db < 1 || lo < 0 || nout < 1) return PM_EINVAL;
   if (p < 2) return PM_EINVAL;
+  // the window must lie inside the product's da + db - 1 coefficients
+  if ((uint64_t)lo + (uint64_t)nout > (uint64_t)da + (uint64_t)db - 1) return PM_EINVAL;
   if (elem_bytes == 4 && p > 0xFFFFFFFFull) return PM_ERANGE;
   if (elem_bytes == 8 && p >= (1ull << 62)) return PM_ERANGE;
-  const int logL = ceil_log2(2ull * (uint64_t)d - 1);
+  const uint64_t need = std::max<uint64_t>((uint64_t)da + db - 1 - lo, (uint64_t)lo + nout);
+  const int logL = ceil_log2(need);
   if (logL > kMaxLogLen) return PM_EUNSUPPORTED;
   const uint64_t L = 1ull << logL;
   const uint64_t lim = 1ull << 32;
   const uint64_t mn = (uint64_t)m * n, nk = (uint64_t)n * k, mk = (uint64_t)m * k;
-  if ((uint64_t)d * mn >= lim || (uint64_t)d * nk >= lim || (2ull * d - 1) * mk >= lim ||
+  if ((uint64_t)da * mn >= lim || (uint64_t)db * nk >= lim || (uint64_t)nout * mk >= lim ||
       L * mn >= lim || L * nk >= lim || L * mk >= lim)
     return PM_ERANGE;
 
   Plan P{};
-  P.p = p; P.m = m; P.n = n; P.k = k; P.d = d; P.elem_bytes = elem_bytes;
+  P.p = p; P.m = m; P.n = n; P.k = k; P.elem_bytes = elem_bytes;
+  P.d = std::max(da, db);
+  P.da = da; P.db = db; P.lo = lo; P.nout = nout;
   P.logL = logL;
   if (p >= 3 && p < (1ull << 31) && is_prime_u64(p) && v2_u64(p - 1) >= logL) {
     P.mode = 0;
     P.r = 1;
     P.q[0] = (uint32_t)p;
   } else {
-    // Integer coefficients of the lifted product lie in [0, n*d*(p-1)^2].
-    Big bound = big_mul(big_mul(big_from(p - 1), p - 1), (uint64_t)n * d);
+    // Integer coefficients of the lifted product lie in
+    // [0, n * min(da, db) * (p-1)^2].
+    Big bound = big_mul(big_mul(big_from(p - 1), p - 1), (uint64_t)n * std::min(da, db));
     Big prod = big_from(1);
     P.mode = 1;
     P.r = 0;
@@ -248,9 +256,14 @@ int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out)
   P.prime_stride = off;
   P.off_cq = P.prime_stride * (uint64_t)P.r;
   P.ws_bytes = P.off_cq;
-  if (P.mode == 1) P.ws_bytes = align_up(P.off_cq + 4ull * P.r * (2ull * d - 1) * mk, 256);
+  if (P.mode == 1) P.ws_bytes = align_up(P.off_cq + 4ull * P.r * (uint64_t)nout * mk, 256);
   *out = P;
   return PM_OK;
+}
+
+int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out) {
+  if (d < 1) return PM_EINVAL;
+  return make_slice_plan(p, m, n, k, d, d, 0, 2 * d - 1, elem_bytes, out);
 }
 
 // ---- device tables --------------------------------------------------------

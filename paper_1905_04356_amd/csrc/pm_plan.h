@@ -69,17 +69,28 @@ struct Plan {
   uint32_t q[kMaxPrimes];
   int pointwise;         // 0 VALU, 1 MFMA
   int m, n, k, d;
+  // coefficient counts of A and B, and the window [lo, lo + nout) of the
+  // product's coefficients that is computed (full product: d, d, 0, 2d-1)
+  int da, db, lo, nout;
   uint64_t p;
   int elem_bytes;
   // workspace layout (bytes, from the workspace base)
   uint64_t off_ahat, off_bhat, off_chat;  // per-prime stride below
   uint64_t prime_stride;                  // bytes between primes' eval sets
-  uint64_t off_cq;                        // CRT residues: r x (2d-1) x m x k u32
+  uint64_t off_cq;                        // CRT residues: r x nout x m x k u32
   uint64_t ws_bytes;
 };
 
 // Status codes mirror pm_status in pm.h.
 int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out);
+
+// Plan of coefficients lo .. lo + nout - 1 of A B, deg A < da, deg B < db:
+// the transform length L only has to exceed both da + db - 2 - lo (so that
+// no coefficient of degree >= L wraps onto the window) and lo + nout - 1.
+// The middle product of the paper is the case da = c, db = c + d, lo = c,
+// nout = d.
+int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
+                    int elem_bytes, Plan* out);
 
 // Host number theory (the library's own; the test oracle has separate code).
 bool is_prime_u64(uint64_t n);

@@ -81,6 +81,37 @@ def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = Non
     return out
 
 
+def middle(p: int, A: torch.Tensor, B: torch.Tensor, lo: int, length: int,
+           out: torch.Tensor | None = None, workspace: Workspace | None = None,
+           stream=None) -> torch.Tensor:
+    """Coefficients lo .. lo+length-1 of A B mod p (A: (da, m, n), B: (db, n, k));
+    the middle product of F in K[x]_c and G in K[x]_{c+d} is
+    middle(p, F, G, c, d)."""
+    if A.dim() != 3 or B.dim() != 3:
+        raise ValueError("A and B must be (coefficients, rows, cols)")
+    da, m, n = A.shape
+    db, n2, k = B.shape
+    if n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    eb = _elem_bytes(A)
+    if B.dtype != A.dtype:
+        raise TypeError("A and B must have the same dtype")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be GPU tensors")
+    A = A.contiguous()
+    B = B.contiguous()
+    if out is None:
+        out = torch.empty((length, m, k), dtype=A.dtype, device=A.device)
+    need = _b.pm_middle_plan(p, m, n, k, da, db, lo, length, eb).workspace_bytes
+    ws = (workspace or _workspace(A.device)).get(need)
+    fn = _b.pm_middle_u32 if eb == 4 else _b.pm_middle_u64
+    st = fn(p, m, n, k, da, db, lo, length, A.data_ptr(), B.data_ptr(), out.data_ptr(),
+            ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_middle")
+    return out
+
+
 def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
     """Evaluations of one operand (role 0: left factor A, 1: right factor B)
     as a device byte tensor, reusable by every product with the same p,
