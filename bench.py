@@ -151,6 +151,61 @@ def cpu_baseline(p, A, B, m, n, k, d, target_s):
             "seconds": dt}
 
 
+def bench_middle(steps=10, warmup=2, seed=6, p=2013265921, m=64, n=64, k=32, c=4096,
+                 dd=4096):
+    """Residual of Algorithm PM-Basis at order c + dd: an m x m basis of degree
+    <= c times the m x n series truncated at order c + dd, coefficients
+    c .. c + dd - 1 (the paper's MiddleProduct).  pm_middle against the whole
+    product of the same operands (both padded to c + dd coefficients) and a
+    slice, on the same stream; outputs compared."""
+    import torch
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream()
+    P1 = I.polymat_torch(seed, 0, I.TENSOR_A, p, c + 1, m, n, dev)
+    F = I.polymat_torch(seed, 0, I.TENSOR_B, p, c + dd, n, k, dev)
+    P1pad = torch.zeros((c + dd, m, n), dtype=P1.dtype, device=dev)
+    P1pad[:c + 1] = P1
+    ws = polymat.Workspace(dev)
+    out = torch.empty((dd, m, k), dtype=P1.dtype, device=dev)
+    full = torch.empty((2 * (c + dd) - 1, m, k), dtype=P1.dtype, device=dev)
+
+    def run_mid():
+        polymat.middle(p, P1, F, c, dd, out=out, workspace=ws, stream=stream)
+
+    def run_full():
+        polymat.mul(p, P1pad, F, out=full, workspace=ws, stream=stream)
+        return full[c:c + dd]
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_mid = timed(run_mid)
+    t_full = timed(run_full)
+    same = bool(torch.equal(out, run_full()))
+    torch.cuda.synchronize()
+    plan_mid = Bd.pm_middle_plan(p, m, n, k, c + 1, c + dd, c, dd, 4)
+    plan_full = Bd.pm_plan(p, m, n, k, c + dd, 4)
+    del P1, F, P1pad, out, full, ws
+    return {"workload": f"PM-Basis residual: {m}x{n} basis of degree <= {c} times {n}x{k} "
+                        f"series of order {c + dd}, coefficients {c}..{c + dd - 1}, mod {p}",
+            "middle_ms": t_mid, "whole_product_then_slice_ms": t_full,
+            "speedup": t_full / t_mid, "middle_L": 1 << plan_mid.log2_len,
+            "whole_L": 1 << plan_full.log2_len, "outputs_equal": same}
+
+
 def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
@@ -384,6 +439,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-middle", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the serving trace (0: skip)")
@@ -486,6 +542,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_steps, 1)
+        torch.cuda.empty_cache()
+    if not args.no_middle:
+        out["middle"] = bench_middle()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
         out["serving"] = bench_serving(args.serving_seconds)
