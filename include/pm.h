@@ -140,6 +140,21 @@ pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
                         const uint64_t* B, uint64_t* C, void* workspace,
                         uint64_t workspace_bytes, void* stream);
 
+/* Algorithm M-Basis (Section 3, "Approximant bases": sigma rounds of
+ * residual, M-Basis-1 returning the s'-Popov basis at order 1, P := Q P and
+ * s' := rdeg_s(P)) on the host, for the leaves of PM-Basis, whose polynomial
+ * products run through pm_middle_*.  F: host memory, sigma*m*n residues mod
+ * p, coefficient-major (coefficient c of entry (i, j) at (c*m + i)*n + j);
+ * shift: m host integers.  Output P: host memory of (sigma+1)*m*m residues,
+ * coefficient-major, an s-ordered weak Popov approximant basis of (F, sigma)
+ * (coefficients above its degree are zero); rdeg_out: m host integers,
+ * rdeg_shift(P).  p must be a prime, 2 <= p < 2^62 (PM_EINVAL if not prime,
+ * PM_ERANGE if too large); PM_EINVAL on sizes < 1 or NULL pointers.
+ * Synchronous; touches no device. */
+pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
+                         const uint64_t* F, const int64_t* shift, uint64_t* P,
+                         int64_t* rdeg_out);
+
 /* One product of a batch; the pointers follow the pm_mul_* layout rules.
  * A_eval / B_eval: optional evaluations of A / B made by pm_eval_* (NULL:
  * the batch transforms the operand itself).  Given evaluations are used in

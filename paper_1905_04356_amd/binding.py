@@ -26,7 +26,7 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
            "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_eval_bytes", "pm_eval_u32",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
-           "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64")
+           "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
@@ -88,13 +88,14 @@ def lib():
                                  ctypes.POINTER(pm_plan_info)]
     L.pm_middle_u32.argtypes = [u32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_middle_u64.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
+    L.pm_mbasis_host.argtypes = [u64, i32, i32, i32, vp, vp, vp, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
                  "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
-                 "pm_middle_u32", "pm_middle_u64"):
+                 "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -212,3 +213,17 @@ def pm_middle_u32(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream)
 
 def pm_middle_u64(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream) -> int:
     return lib().pm_middle_u64(p, m, n, k, da, db, lo, length, A, B, C, ws, ws_bytes, stream)
+
+
+def pm_mbasis_host(p: int, F, sigma: int, shift):
+    """M-Basis on the host: F a (>= sigma, m, n) integer array of residues,
+    shift m integers -> (P as a (sigma+1, m, m) uint64 array, rdeg list)."""
+    import numpy as np
+    F = np.ascontiguousarray(np.asarray(F)[:sigma], dtype=np.uint64)
+    _, m, n = F.shape
+    sh = np.ascontiguousarray(shift, dtype=np.int64)
+    P = np.zeros((sigma + 1, m, m), dtype=np.uint64)
+    rd = np.zeros(m, dtype=np.int64)
+    _check(lib().pm_mbasis_host(p, m, n, sigma, F.ctypes.data, sh.ctypes.data, P.ctypes.data,
+                                rd.ctypes.data), "pm_mbasis_host")
+    return P, [int(x) for x in rd]

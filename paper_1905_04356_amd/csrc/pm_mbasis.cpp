@@ -1,0 +1,147 @@
+// pm_mbasis.cpp -- Algorithm M-Basis on the host: the leaves of PM-Basis.
+//
+// Hyun, Neiger, Schost (ISSAC 2019), Section 3, "Approximant bases": for F in
+// K[x]^{m x n} and order sigma, M-Basis runs sigma rounds; round k takes the
+// residual R (coefficient k of P F), the s'-Popov approximant basis Q of R at
+// order 1 (M-Basis-1), and sets P := Q P, s' := rdeg_s(P).
+//
+// M-Basis-1 on a constant R: rows are taken by increasing shift (ties by
+// index); a row that reduces to zero against the earlier independent rows
+// gives the constant basis row e_i - sum c_j e_j (its combination), an
+// independent row gives x e_i.  That matrix is the s-Popov basis at order 1.
+//
+// Instead of forming P F at every round, G = P F (the residual series) is
+// updated with the same row operations as P; its coefficient k is R.  These
+// leaves are small sequential eliminations (orders up to a few dozen); the
+// polynomial products of PM-Basis above them run on the GPU.
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "pm_plan.h"
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct Field {
+  uint64_t p;
+  uint64_t add(uint64_t a, uint64_t b) const { uint64_t s = a + b; return s >= p ? s - p : s; }
+  uint64_t sub(uint64_t a, uint64_t b) const { return a >= b ? a - b : a + p - b; }
+  uint64_t mul(uint64_t a, uint64_t b) const { return (uint64_t)((u128)a * b % p); }
+  uint64_t inv(uint64_t a) const { return pm::powmod_u64(a, p - 2, p); }
+};
+
+const int64_t kNoDeg = INT64_MIN / 4;
+
+// rdeg_s(P)_i = max_j deg(P_ij) + s_j over nonzero entries; P is (D, m, m).
+void row_degrees(const std::vector<uint64_t>& P, int D, int m, const int64_t* s,
+                 int64_t* out) {
+  for (int i = 0; i < m; ++i) {
+    int64_t best = kNoDeg;
+    for (int j = 0; j < m; ++j) {
+      for (int c = D - 1; c >= 0; --c) {
+        if (P[((size_t)c * m + i) * m + j]) {
+          best = std::max(best, (int64_t)c + s[j]);
+          break;
+        }
+      }
+    }
+    out[i] = best;
+  }
+}
+
+}  // namespace
+
+extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
+                                    const uint64_t* F, const int64_t* shift, uint64_t* Pout,
+                                    int64_t* rdeg_out) {
+  if (!F || !shift || !Pout || !rdeg_out) return PM_EINVAL;
+  if (m < 1 || n < 1 || sigma < 1) return PM_EINVAL;
+  if (p >= (1ull << 62)) return PM_ERANGE;
+  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+  const Field K{p};
+  const int D = sigma + 1;                       // coefficients of P (degree <= sigma)
+  std::vector<uint64_t> P((size_t)D * m * m, 0), G((size_t)sigma * m * n, 0);
+  for (int i = 0; i < m; ++i) P[(size_t)i * m + i] = 1;
+  for (size_t e = 0; e < G.size(); ++e) G[e] = F[e] % p;
+  std::vector<int64_t> sc(shift, shift + m);
+  std::vector<int> order(m);
+  std::vector<uint64_t> v(n), comb(m), newP((size_t)D * m), newG((size_t)sigma * n);
+  struct Pivot { int col; std::vector<uint64_t> w, cw; };
+  for (int k = 0; k < sigma; ++k) {
+    // M-Basis-1 on R = coefficient k of G, shift sc
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sc[a] < sc[b]; });
+    std::vector<Pivot> piv;
+    std::vector<int> indep;                       // rows multiplied by x
+    std::vector<std::pair<int, std::vector<uint64_t>>> dep;  // (row, combination)
+    for (int i : order) {
+      for (int c = 0; c < n; ++c) v[c] = G[((size_t)k * m + i) * n + c];
+      std::fill(comb.begin(), comb.end(), 0);
+      comb[i] = 1;
+      for (const Pivot& q : piv) {
+        const uint64_t f = v[q.col];
+        if (!f) continue;
+        for (int c = 0; c < n; ++c) v[c] = K.sub(v[c], K.mul(f, q.w[c]));
+        for (int j = 0; j < m; ++j) comb[j] = K.sub(comb[j], K.mul(f, q.cw[j]));
+      }
+      int col = -1;
+      for (int c = 0; c < n && col < 0; ++c)
+        if (v[c]) col = c;
+      if (col < 0) {
+        dep.emplace_back(i, comb);
+      } else {
+        const uint64_t iv = K.inv(v[col]);
+        Pivot q{col, std::vector<uint64_t>(n), std::vector<uint64_t>(m)};
+        for (int c = 0; c < n; ++c) q.w[c] = K.mul(v[c], iv);
+        for (int j = 0; j < m; ++j) q.cw[j] = K.mul(comb[j], iv);
+        piv.push_back(std::move(q));
+        indep.push_back(i);
+      }
+    }
+    // P := Q P and G := Q G.  Constant rows combine the old rows (their
+    // support is on the row itself and independent rows, which are updated
+    // after); independent rows are multiplied by x.
+    for (auto& dc : dep) {
+      const int i = dc.first;
+      const std::vector<uint64_t>& cm = dc.second;
+      std::fill(newP.begin(), newP.end(), 0);
+      std::fill(newG.begin(), newG.end(), 0);
+      for (int j = 0; j < m; ++j) {
+        const uint64_t f = cm[j];
+        if (!f) continue;
+        for (int c = 0; c < D; ++c)
+          for (int t = 0; t < m; ++t)
+            newP[(size_t)c * m + t] =
+                K.add(newP[(size_t)c * m + t], K.mul(f, P[((size_t)c * m + j) * m + t]));
+        for (int c = k; c < sigma; ++c)
+          for (int t = 0; t < n; ++t)
+            newG[(size_t)c * n + t] =
+                K.add(newG[(size_t)c * n + t], K.mul(f, G[((size_t)c * m + j) * n + t]));
+      }
+      for (int c = 0; c < D; ++c)
+        for (int t = 0; t < m; ++t) P[((size_t)c * m + i) * m + t] = newP[(size_t)c * m + t];
+      for (int c = k; c < sigma; ++c)
+        for (int t = 0; t < n; ++t) G[((size_t)c * m + i) * n + t] = newG[(size_t)c * n + t];
+    }
+    for (int i : indep) {
+      for (int c = D - 1; c >= 1; --c)
+        for (int t = 0; t < m; ++t)
+          P[((size_t)c * m + i) * m + t] = P[((size_t)(c - 1) * m + i) * m + t];
+      for (int t = 0; t < m; ++t) P[(size_t)i * m + t] = 0;
+      for (int c = sigma - 1; c >= 1; --c)
+        for (int t = 0; t < n; ++t)
+          G[((size_t)c * m + i) * n + t] = G[((size_t)(c - 1) * m + i) * n + t];
+      for (int t = 0; t < n; ++t) G[(size_t)i * n + t] = 0;
+    }
+    row_degrees(P, D, m, shift, sc.data());
+  }
+  memcpy(Pout, P.data(), sizeof(uint64_t) * P.size());
+  memcpy(rdeg_out, sc.data(), sizeof(int64_t) * m);
+  return PM_OK;
+}

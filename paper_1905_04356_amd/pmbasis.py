@@ -1,0 +1,93 @@
+"""Algorithm PM-Basis (Section 3, "Approximant bases") with its polynomial
+products on the GPU.
+
+PM-Basis(F, sigma, s): below the threshold T it is M-Basis (pm_mbasis_host,
+host code: a short sequential elimination per order); above it,
+    P1 = PM-Basis(F mod x^c, c, s)            c = ceil(sigma / 2)
+    R  = MiddleProduct(P1, F, c, sigma - c)   coefficients c .. sigma-1 of P1 F
+    P2 = PM-Basis(R, sigma - c, rdeg_s(P1))
+    return P2 P1
+The residual and the product run through pm_middle (the residual on a
+transform of about sigma points instead of 1.5 sigma). Bases stay on the
+device between levels; only the leaves' inputs and outputs cross to the host.
+The shifts follow the predictable-degree property: the row degrees
+rdeg_s(P2 P1) equal rdeg_{rdeg_s(P1)}(P2), so deg(P) <= max rdeg - min s
+bounds the coefficients kept.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as _b
+from . import polymat
+
+
+def _trim_host(P: np.ndarray) -> np.ndarray:
+    D = P.shape[0]
+    while D > 1 and not P[D - 1].any():
+        D -= 1
+    return P[:D]
+
+
+class PMBasis:
+    """One PM-Basis computation mod a prime p (residues as torch.uint32 for
+    p < 2^32, torch.uint64 otherwise)."""
+
+    def __init__(self, p: int, threshold: int = 16, stream=None):
+        if threshold < 1:
+            raise ValueError("threshold must be >= 1")
+        self.p = p
+        self.T = threshold
+        self.stream = stream
+        self.ws = None
+        self.leaves = 0
+        self.products = 0
+
+    def _leaf(self, F: torch.Tensor, sigma: int, s: list[int]):
+        Fh = F[:sigma].to("cpu").numpy().astype(np.uint64)
+        P, rd = _b.pm_mbasis_host(self.p, Fh, sigma, s)
+        P = _trim_host(P)
+        self.leaves += 1
+        return torch.from_numpy(P.astype(np.uint64 if F.dtype == torch.uint64 else np.uint32)
+                                ).to(F.device), rd
+
+    def _bound(self, P: torch.Tensor, rd: list[int], s: list[int]) -> torch.Tensor:
+        keep = max(rd) - min(s) + 1
+        return P[:max(1, min(P.shape[0], keep))]
+
+    def _run(self, F: torch.Tensor, sigma: int, s: list[int]):
+        if sigma <= self.T:
+            return self._leaf(F, sigma, s)
+        c = (sigma + 1) // 2
+        d = sigma - c
+        P1, s1 = self._run(F[:c], c, s)
+        if self.ws is None:
+            self.ws = polymat.Workspace(F.device)
+        R = polymat.middle(self.p, P1, F[:sigma], c, d, workspace=self.ws, stream=self.stream)
+        P2, s2 = self._run(R, d, s1)
+        P = polymat.middle(self.p, P2, P1, 0, P2.shape[0] + P1.shape[0] - 1,
+                           workspace=self.ws, stream=self.stream)
+        self.products += 2
+        return self._bound(P, s2, s), s2
+
+    def __call__(self, F: torch.Tensor, sigma: int, shift) -> tuple[torch.Tensor, list[int]]:
+        """F: (>= sigma, m, n) residues on the GPU; shift: m integers.
+        Returns (P, rdeg): P (deg+1, m, m) on the GPU, an s-ordered weak Popov
+        approximant basis of (F, sigma), and rdeg_s(P)."""
+        if F.dim() != 3 or F.shape[0] < sigma or sigma < 1:
+            raise ValueError("F must be (>= sigma, m, n) with sigma >= 1")
+        s = [int(x) for x in shift]
+        if len(s) != F.shape[1]:
+            raise ValueError("one shift per row of F")
+        P, rd = self._run(F.contiguous(), sigma, s)
+        # exact trim of trailing zero coefficients (one reduction on the device)
+        signed = torch.int64 if P.dtype == torch.uint64 else torch.int32
+        nz = torch.nonzero(P.reshape(P.shape[0], -1).view(signed).ne(0).any(dim=1))
+        D = int(nz.max().item()) + 1 if nz.numel() else 1
+        return P[:D].contiguous(), rd
+
+
+def pmbasis(p: int, F: torch.Tensor, sigma: int, shift, threshold: int = 16, stream=None):
+    """PM-Basis(F, sigma, shift) mod p; see PMBasis."""
+    return PMBasis(p, threshold, stream)(F, sigma, shift)
