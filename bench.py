@@ -206,6 +206,32 @@ def bench_middle(steps=10, warmup=2, seed=6, p=2013265921, m=64, n=64, k=32, c=4
             "whole_L": 1 << plan_full.log2_len, "outputs_equal": same}
 
 
+def bench_pmbasis(p=786433, seed=7):
+    """Algorithm PM-Basis (approximant bases) driven through the GPU middle
+    products, on the two table sizes of the paper that fit transforms of at
+    most 2^15 points, mod a 20-bit FFT prime (786433 = 3 2^18 + 1), zero
+    shift, F seeded uniform; one warm-up run, then one timed run each."""
+    import torch
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import pmbasis as PB
+    dev = torch.device("cuda")
+    rows = []
+    for (m, n, sigma, T) in [(32, 16, 8192, 8), (128, 64, 2048, 1)]:
+        F = I.polymat_torch(seed, 0, I.TENSOR_A, p, sigma, m, n, dev)
+        PB.PMBasis(p, T)(F[:64], 64, [0] * m)
+        pm = PB.PMBasis(p, T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, rd = pm(F, sigma, [0] * m)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows.append({"m": m, "n": n, "order": sigma, "threshold": T, "seconds": dt,
+                     "leaf_seconds": pm.leaf_seconds, "leaves": pm.leaves,
+                     "basis_degree": int(P.shape[0]) - 1})
+        del F, P
+    return {"workload": f"PM-Basis, F m x n of order sigma, mod {p}, zero shift", "runs": rows}
+
+
 def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
@@ -336,7 +362,7 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
             traffic[kind_of(name)] += v * wscale / steps_pmc
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup 2 --no-cpu-baseline --no-batched "
-              "--serving-seconds 0")
+              "--no-middle --no-pmbasis --serving-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           "| kernel | calls | avg us | total ms | kind |", "|---|---|---|---|---|"]
@@ -351,7 +377,7 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
-                  "--no-cpu-baseline --no-batched --serving-seconds 0")
+                  "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --serving-seconds 0")
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
@@ -440,6 +466,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-middle", action="store_true")
+    ap.add_argument("--no-pmbasis", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the serving trace (0: skip)")
@@ -545,6 +572,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_middle:
         out["middle"] = bench_middle()
+        torch.cuda.empty_cache()
+    if not args.no_pmbasis:
+        out["pmbasis"] = bench_pmbasis()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
         out["serving"] = bench_serving(args.serving_seconds)

@@ -28,11 +28,32 @@ namespace {
 
 typedef unsigned __int128 u128;
 
+// Arithmetic mod p.  For p < 2^32 products fit 64 bits and are reduced with
+// Barrett's method (mu = floor((2^64-1)/p)); sums of products are kept in
+// 128 bits and reduced once.
 struct Field {
   uint64_t p;
+  bool small;          // p < 2^32
+  uint64_t mu;         // floor((2^64 - 1) / p)
+  uint64_t r64;        // 2^64 mod p
+  explicit Field(uint64_t q)
+      : p(q), small(q < (1ull << 32)), mu(~0ull / q), r64((uint64_t)(((u128)1 << 64) % q)) {}
+  uint64_t red64(uint64_t x) const {  // x mod p, p < 2^32
+    const uint64_t qt = (uint64_t)(((u128)x * mu) >> 64);
+    uint64_t r = x - qt * p;
+    while (r >= p) r -= p;
+    return r;
+  }
+  uint64_t red128(u128 x) const {
+    if (!small) return (uint64_t)(x % p);
+    const uint64_t hi = red64((uint64_t)(x >> 64)), lo = red64((uint64_t)x);
+    return add(red64(hi * r64), lo);
+  }
   uint64_t add(uint64_t a, uint64_t b) const { uint64_t s = a + b; return s >= p ? s - p : s; }
   uint64_t sub(uint64_t a, uint64_t b) const { return a >= b ? a - b : a + p - b; }
-  uint64_t mul(uint64_t a, uint64_t b) const { return (uint64_t)((u128)a * b % p); }
+  uint64_t mul(uint64_t a, uint64_t b) const {
+    return small ? red64(a * b) : (uint64_t)((u128)a * b % p);
+  }
   uint64_t inv(uint64_t a) const { return pm::powmod_u64(a, p - 2, p); }
 };
 
@@ -64,7 +85,7 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
   if (m < 1 || n < 1 || sigma < 1) return PM_EINVAL;
   if (p >= (1ull << 62)) return PM_ERANGE;
   if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
-  const Field K{p};
+  const Field K(p);
   const int D = sigma + 1;                       // coefficients of P (degree <= sigma)
   std::vector<uint64_t> P((size_t)D * m * m, 0), G((size_t)sigma * m * n, 0);
   for (int i = 0; i < m; ++i) P[(size_t)i * m + i] = 1;
@@ -107,30 +128,37 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
     // P := Q P and G := Q G.  Constant rows combine the old rows (their
     // support is on the row itself and independent rows, which are updated
     // after); independent rows are multiplied by x.
+    // P has degree <= k before this round, so coefficients above k are zero
+    const int dk = std::min(D, k + 1);
+    std::vector<int> sup;
+    std::vector<uint64_t> cf;
     for (auto& dc : dep) {
       const int i = dc.first;
       const std::vector<uint64_t>& cm = dc.second;
-      std::fill(newP.begin(), newP.end(), 0);
-      std::fill(newG.begin(), newG.end(), 0);
-      for (int j = 0; j < m; ++j) {
-        const uint64_t f = cm[j];
-        if (!f) continue;
-        for (int c = 0; c < D; ++c)
-          for (int t = 0; t < m; ++t)
-            newP[(size_t)c * m + t] =
-                K.add(newP[(size_t)c * m + t], K.mul(f, P[((size_t)c * m + j) * m + t]));
-        for (int c = k; c < sigma; ++c)
-          for (int t = 0; t < n; ++t)
-            newG[(size_t)c * n + t] =
-                K.add(newG[(size_t)c * n + t], K.mul(f, G[((size_t)c * m + j) * n + t]));
-      }
-      for (int c = 0; c < D; ++c)
+      sup.clear();
+      cf.clear();
+      for (int j = 0; j < m; ++j)
+        if (cm[j]) { sup.push_back(j); cf.push_back(cm[j]); }
+      const size_t ns = sup.size();
+      for (int c = 0; c < dk; ++c)
+        for (int t = 0; t < m; ++t) {
+          u128 acc = 0;
+          for (size_t u = 0; u < ns; ++u) acc += (u128)cf[u] * P[((size_t)c * m + sup[u]) * m + t];
+          newP[(size_t)c * m + t] = K.red128(acc);
+        }
+      for (int c = k; c < sigma; ++c)
+        for (int t = 0; t < n; ++t) {
+          u128 acc = 0;
+          for (size_t u = 0; u < ns; ++u) acc += (u128)cf[u] * G[((size_t)c * m + sup[u]) * n + t];
+          newG[(size_t)c * n + t] = K.red128(acc);
+        }
+      for (int c = 0; c < dk; ++c)
         for (int t = 0; t < m; ++t) P[((size_t)c * m + i) * m + t] = newP[(size_t)c * m + t];
       for (int c = k; c < sigma; ++c)
         for (int t = 0; t < n; ++t) G[((size_t)c * m + i) * n + t] = newG[(size_t)c * n + t];
     }
     for (int i : indep) {
-      for (int c = D - 1; c >= 1; --c)
+      for (int c = std::min(D - 1, dk); c >= 1; --c)
         for (int t = 0; t < m; ++t)
           P[((size_t)c * m + i) * m + t] = P[((size_t)(c - 1) * m + i) * m + t];
       for (int t = 0; t < m; ++t) P[(size_t)i * m + t] = 0;
@@ -139,7 +167,7 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
           G[((size_t)c * m + i) * n + t] = G[((size_t)(c - 1) * m + i) * n + t];
       for (int t = 0; t < n; ++t) G[(size_t)i * n + t] = 0;
     }
-    row_degrees(P, D, m, shift, sc.data());
+    row_degrees(P, std::min(D, k + 2), m, shift, sc.data());
   }
   memcpy(Pout, P.data(), sizeof(uint64_t) * P.size());
   memcpy(rdeg_out, sc.data(), sizeof(int64_t) * m);

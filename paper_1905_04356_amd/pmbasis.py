@@ -16,6 +16,8 @@ bounds the coefficients kept.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import torch
 
@@ -43,14 +45,18 @@ class PMBasis:
         self.ws = None
         self.leaves = 0
         self.products = 0
+        self.leaf_seconds = 0.0   # host time in the leaves (copies included)
 
     def _leaf(self, F: torch.Tensor, sigma: int, s: list[int]):
+        t0 = time.perf_counter()
         Fh = F[:sigma].to("cpu").numpy().astype(np.uint64)
         P, rd = _b.pm_mbasis_host(self.p, Fh, sigma, s)
         P = _trim_host(P)
         self.leaves += 1
-        return torch.from_numpy(P.astype(np.uint64 if F.dtype == torch.uint64 else np.uint32)
-                                ).to(F.device), rd
+        out = torch.from_numpy(P.astype(np.uint64 if F.dtype == torch.uint64 else np.uint32)
+                               ).to(F.device)
+        self.leaf_seconds += time.perf_counter() - t0
+        return out, rd
 
     def _bound(self, P: torch.Tensor, rd: list[int], s: list[int]) -> torch.Tensor:
         keep = max(rd) - min(s) + 1
