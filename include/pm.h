@@ -155,6 +155,14 @@ pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
                          const uint64_t* F, const int64_t* shift, uint64_t* P,
                          int64_t* rdeg_out);
 
+/* Inverse of an n x n matrix mod a prime p < 2^62 on the host (Gauss-Jordan
+ * elimination): the constant term A(0)^{-1} that starts Newton iteration for
+ * the truncated inverse A^{-1} mod x^N (Section 4, "Lifting techniques").
+ * M, Minv: host arrays of n*n residues, row-major.  PM_EINVAL if M is
+ * singular mod p, p is not prime, n < 1 or a pointer is NULL; PM_ERANGE if
+ * p >= 2^62.  Synchronous; touches no device. */
+pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv);
+
 /* One product of a batch; the pointers follow the pm_mul_* layout rules.
  * A_eval / B_eval: optional evaluations of A / B made by pm_eval_* (NULL:
  * the batch transforms the operand itself).  Given evaluations are used in

@@ -26,7 +26,8 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_u32", "pm_mul_u64", "pm_batched_workspace_bytes",
            "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_eval_bytes", "pm_eval_u32",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
-           "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host")
+           "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
+           "pm_matinv_host")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
@@ -89,13 +90,14 @@ def lib():
     L.pm_middle_u32.argtypes = [u32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_middle_u64.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_mbasis_host.argtypes = [u64, i32, i32, i32, vp, vp, vp, vp]
+    L.pm_matinv_host.argtypes = [u64, i32, vp, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
                  "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
-                 "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host"):
+                 "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -227,3 +229,13 @@ def pm_mbasis_host(p: int, F, sigma: int, shift):
     _check(lib().pm_mbasis_host(p, m, n, sigma, F.ctypes.data, sh.ctypes.data, P.ctypes.data,
                                 rd.ctypes.data), "pm_mbasis_host")
     return P, [int(x) for x in rd]
+
+
+def pm_matinv_host(p: int, M):
+    """Inverse of a square matrix mod a prime p (host), as a uint64 array."""
+    import numpy as np
+    M = np.ascontiguousarray(np.asarray(M), dtype=np.uint64)
+    n = M.shape[0]
+    out = np.zeros((n, n), dtype=np.uint64)
+    _check(lib().pm_matinv_host(p, n, M.ctypes.data, out.ctypes.data), "pm_matinv_host")
+    return out

@@ -173,3 +173,37 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
   memcpy(rdeg_out, sc.data(), sizeof(int64_t) * m);
   return PM_OK;
 }
+
+// Inverse of an n x n matrix mod a prime p by Gauss-Jordan elimination with
+// row pivoting: the constant term A(0)^{-1} with which Newton iteration for
+// truncated inverses starts.
+extern "C" pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv) {
+  if (!M || !Minv || n < 1) return PM_EINVAL;
+  if (p >= (1ull << 62)) return PM_ERANGE;
+  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+  const Field K(p);
+  const size_t w = 2 * (size_t)n;
+  std::vector<uint64_t> a((size_t)n * w, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) a[i * w + j] = M[(size_t)i * n + j] % p;
+    a[i * w + n + i] = 1;
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = -1;
+    for (int r = col; r < n && piv < 0; ++r)
+      if (a[r * w + col]) piv = r;
+    if (piv < 0) return PM_EINVAL;  // singular
+    if (piv != col)
+      for (size_t j = 0; j < w; ++j) std::swap(a[piv * w + j], a[col * w + j]);
+    const uint64_t iv = K.inv(a[col * w + col]);
+    for (size_t j = 0; j < w; ++j) a[col * w + j] = K.mul(a[col * w + j], iv);
+    for (int r = 0; r < n; ++r) {
+      const uint64_t f = a[r * w + col];
+      if (r == col || !f) continue;
+      for (size_t j = 0; j < w; ++j) a[r * w + j] = K.sub(a[r * w + j], K.mul(f, a[col * w + j]));
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Minv[(size_t)i * n + j] = a[i * w + n + j];
+  return PM_OK;
+}

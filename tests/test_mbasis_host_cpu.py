@@ -40,3 +40,26 @@ def test_host_mbasis_rejects_bad_arguments():
     assert e.value.status == B.PM_ERANGE
     L = B.lib()
     assert L.pm_mbasis_host(97, 2, 1, 0, F.ctypes.data, None, None, None) == B.PM_EINVAL
+
+
+@pytest.mark.parametrize("p,n,seed", [(97, 4, 1), (998244353, 9, 2), ((1 << 61) - 1, 5, 3),
+                                      (2, 6, 4)])
+def test_host_matinv_equals_oracle(p, n, seed):
+    from oracle import series as S
+    rng = np.random.default_rng(seed)
+    while True:
+        M = np.array([[int(rng.integers(0, 1 << 62)) % p for _ in range(n)] for _ in range(n)],
+                     dtype=object)
+        try:
+            ref = S.matinv(M, p)
+            break
+        except ValueError:
+            continue
+    got = B.pm_matinv_host(p, M.astype(np.uint64)).astype(object)
+    assert np.array_equal(got, ref)
+
+
+def test_host_matinv_rejects_singular():
+    with pytest.raises(B.PmError) as e:
+        B.pm_matinv_host(97, np.array([[1, 2], [2, 4]], dtype=np.uint64))
+    assert e.value.status == B.PM_EINVAL
