@@ -232,6 +232,47 @@ def bench_pmbasis(p=786433, seed=7):
     return {"workload": f"PM-Basis, F m x n of order sigma, mod {p}, zero shift", "runs": rows}
 
 
+def bench_newton(p=2013265921, n=32, da=2049, N=4096, rhs=64, seed=8):
+    """Truncated inverse S = A^{-1} mod x^N by Newton iteration (GPU middle
+    products), then S as a multiplier class: `rhs` products S b_i
+    (b_i: n x 1, N coefficients) in one batched call with S's evaluations
+    computed once, against the same batch transforming S every time."""
+    import torch
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import newton
+    from paper_1905_04356_amd import polymat
+    dev = torch.device("cuda")
+    A = I.polymat_torch(seed, 0, I.TENSOR_A, p, da, n, n, dev)
+    newton.truncated_inverse(p, A[:8], 64)               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Sx = newton.truncated_inverse(p, A, N)
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    Bs = [I.polymat_torch(seed, 1 + i, I.TENSOR_B, p, N, n, 1, dev) for i in range(rhs)]
+    ws = polymat.Workspace(dev)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    t_eval = timed(lambda: newton.evaluations(p, Sx), reps=1)
+    Se = newton.evaluations(p, Sx)
+    t_reuse = timed(lambda: polymat.mul_batched(p, [Sx] * rhs, Bs, workspace=ws,
+                                                A_evals=[Se] * rhs))
+    t_plain = timed(lambda: polymat.mul_batched(p, [Sx] * rhs, Bs, workspace=ws))
+    del A, Sx, Bs, Se, ws
+    return {"workload": f"truncated inverse of a {n}x{n} matrix of degree < {da} mod x^{N}, "
+                        f"mod {p}; then {rhs} products by it ({n}x1 right sides)",
+            "newton_s": t_inv, "eval_once_ms": t_eval, "products_reusing_evals_ms": t_reuse,
+            "products_transforming_S_ms": t_plain, "reuse_speedup": t_plain / t_reuse}
+
+
 def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
@@ -575,6 +616,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_pmbasis:
         out["pmbasis"] = bench_pmbasis()
+        torch.cuda.empty_cache()
+        out["newton"] = bench_newton()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
         out["serving"] = bench_serving(args.serving_seconds)
