@@ -170,13 +170,18 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
   for (int i = 0; i < P.r; ++i) {
     pw.pc[i] = pc[i];
-    // weights of the limb accumulators: 256^s L^{-1} mod q
-    uint64_t w = pc[i].linv;
+    // weights of the limb accumulators in Montgomery form:
+    // 256^s L^{-1} 2^32 mod q
+    uint64_t w = ((uint64_t)pc[i].linv << 32) % P.q[i];
     for (int t = 0; t < 7; ++t) {
       pw.cs[i][t] = (uint32_t)w;
       w = (w << 8) % P.q[i];
     }
-    pw.bias[i] = ((1ull << 62) + P.q[i] - 1) / P.q[i] * P.q[i];
+    // |sum_s c_s acc_s| < 7 q max|acc_s| <= 7 q n 2^16 (|acc_s| <= 4 n 2^14)
+    pw.bias[i] = (uint64_t)P.q[i] * 7ull * (uint64_t)n * 65536ull;
+    uint32_t inv = 1;  // q^{-1} mod 2^32 by Newton's iteration (q odd)
+    for (int it = 0; it < 5; ++it) inv *= 2u - P.q[i] * inv;
+    pw.qninv[i] = 0u - inv;
   }
 
   NttLaunch& ic = L->inv;

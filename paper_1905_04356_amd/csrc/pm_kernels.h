@@ -50,8 +50,9 @@ struct PointwiseLaunch {
   const uint32_t* bhat;
   uint32_t* chat;
   PrimeConst pc[kMaxPrimes];
-  uint32_t cs[kMaxPrimes][8];  // MFMA variant: 256^s L^{-1} mod q, s < 7
-  uint64_t bias[kMaxPrimes];   // MFMA variant: a multiple of q in [2^62, 2^62 + q)
+  uint32_t cs[kMaxPrimes][8];  // MFMA variant: 256^s L^{-1} 2^32 mod q, s < 7
+  uint64_t bias[kMaxPrimes];   // MFMA variant: q * 7 n 2^16, above every |sum|
+  uint32_t qninv[kMaxPrimes];  // MFMA variant: -q^{-1} mod 2^32
 };
 
 // Chinese remaindering of r residue arrays (u32, `count` each, stride

@@ -142,12 +142,16 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
   const int tiles_m = mp >> 4, tiles = tiles_m * (kp >> 4);
   const int lr = lane & 15, lk = (lane >> 4) * 16;
   // c_s < q < 2^31, so each weight is a non-negative int32 and each term a
-  // single signed 32x32->64 multiply-add; the bias (a multiple of q, at least
-  // 2^62) makes the sum non-negative for the unsigned Barrett reduction.
+  // single signed 32x32->64 multiply-add.  The bias, a multiple of q above
+  // every |sum|, makes the sum T non-negative and T < 14 q n 2^16 <= q 2^32
+  // (n < 4096), so Montgomery's reduction (P. Montgomery, Math. Comp. 1985)
+  // t = (T + (T mu' mod 2^32) q) / 2^32 lies in [0, 2q) and equals
+  // T 2^{-32} mod q; the weights carry the factor 2^32.
   int32_t cs[7];
 #pragma unroll
   for (int s = 0; s < 7; ++s) cs[s] = (int32_t)a.cs[prime][s];
   const uint64_t bias = a.bias[prime];
+  const uint32_t qninv = a.qninv[prime];
   for (int tile = wave; tile < tiles; tile += nwaves) {
     const int ti = tile % tiles_m, tj = tile / tiles_m;
     v4i acc[7];
@@ -173,7 +177,8 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
       int64_t S = (int64_t)bias;
 #pragma unroll
       for (int s = 0; s < 7; ++s) S += (int64_t)cs[s] * (int64_t)acc[s][r];
-      const uint32_t v = reduce_u64((uint64_t)S, q, P.mu);
+      const uint32_t mm = (uint32_t)S * qninv;
+      const uint32_t v = reduce_once((uint32_t)(((uint64_t)mm * q + (uint64_t)S) >> 32), q);
       if (i < m && j < k) C[i * k + j] = v;
     }
   }
