@@ -86,9 +86,52 @@ __device__ __forceinline__ void transpose4x4(const uint32_t in[4], uint32_t out[
   out[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
 }
 
+// Four balanced base-256 digits (each in [-128, 127]) of x as bytes: the sum
+// x + 0x80808080 carries exactly as the balanced representation needs, and
+// the xor recentres each byte.  Exact for x in [-0x80808080, 0x7F7F7F7F] as a
+// two's-complement word.  Residues below q <= 0x7F7F7F7F (all NTT primes
+// used here) need no centring; larger q are centred first.
+template <bool CENTER>
 __device__ __forceinline__ uint32_t limbs_of(uint32_t x, uint32_t q, uint32_t half_q) {
-  const uint32_t c = x > half_q ? x - q : x;  // centred, as a two's-complement word
+  const uint32_t c = CENTER && x > half_q ? x - q : x;
   return (c + 0x80808080u) ^ 0x80808080u;
+}
+
+// A (row-major m x n) and B (n x k, stored transposed) into LDS digit planes.
+template <bool CENTER>
+__device__ __forceinline__ void stage_limbs(const uint32_t* A, const uint32_t* B, uint8_t* As,
+                                            uint8_t* Bs, int m, int n, int k, int mp, int kp,
+                                            int ng, int rs, uint32_t q, uint32_t half_q) {
+  const int l16 = threadIdx.x & 15, r16 = threadIdx.x >> 4, nr = blockDim.x >> 4;
+  // A: row i, 4 consecutive l per item; 16 lanes cover 64 consecutive l.
+  for (int i = r16; i < mp; i += nr) {
+    for (int g = l16; g < ng; g += 16) {
+      const int l0 = g * 4;
+      uint32_t in[4] = {0, 0, 0, 0}, out[4];
+      if (i < m && l0 < n) {
+        const uint4 v = *(const uint4*)(A + i * n + l0);
+        in[0] = limbs_of<CENTER>(v.x, q, half_q); in[1] = limbs_of<CENTER>(v.y, q, half_q);
+        in[2] = limbs_of<CENTER>(v.z, q, half_q); in[3] = limbs_of<CENTER>(v.w, q, half_q);
+      }
+      transpose4x4(in, out);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * rs + l0) = out[pl];
+    }
+  }
+  // B transposed: column j, 4 consecutive l; 16 lanes cover 16 consecutive j.
+  for (int g = r16; g < ng; g += nr) {
+    const int l0 = g * 4;
+    for (int j = l16; j < kp; j += 16) {
+      uint32_t in[4] = {0, 0, 0, 0}, out[4];
+      if (j < k && l0 < n) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) in[c] = limbs_of<CENTER>(B[(l0 + c) * k + j], q, half_q);
+      }
+      transpose4x4(in, out);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * rs + l0) = out[pl];
+    }
+  }
 }
 
 __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, int t, int prime,
@@ -105,37 +148,10 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
   uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * ((size_t)m * k);
   const int nt = blockDim.x;
   const int ng = np >> 2;                   // groups of 4 contraction indices (multiple of 16)
-  const int l16 = threadIdx.x & 15, r16 = threadIdx.x >> 4, nr = nt >> 4;
-
-  // A: row i, 4 consecutive l per item; 16 lanes cover 64 consecutive l.
-  for (int i = r16; i < mp; i += nr) {
-    for (int g = l16; g < ng; g += 16) {
-      const int l0 = g * 4;
-      uint32_t in[4] = {0, 0, 0, 0}, out[4];
-      if (i < m && l0 < n) {
-        const uint4 v = *(const uint4*)(A + i * n + l0);
-        in[0] = limbs_of(v.x, q, half_q); in[1] = limbs_of(v.y, q, half_q);
-        in[2] = limbs_of(v.z, q, half_q); in[3] = limbs_of(v.w, q, half_q);
-      }
-      transpose4x4(in, out);
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * rs + l0) = out[pl];
-    }
-  }
-  // B transposed: column j, 4 consecutive l; 16 lanes cover 16 consecutive j.
-  for (int g = r16; g < ng; g += nr) {
-    const int l0 = g * 4;
-    for (int j = l16; j < kp; j += 16) {
-      uint32_t in[4] = {0, 0, 0, 0}, out[4];
-      if (j < k && l0 < n) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) in[c] = limbs_of(B[(l0 + c) * k + j], q, half_q);
-      }
-      transpose4x4(in, out);
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * rs + l0) = out[pl];
-    }
-  }
+  if (q <= 0x7F7F7F7Fu)
+    stage_limbs<false>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
+  else
+    stage_limbs<true>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = nt >> 6;

@@ -383,3 +383,19 @@ def test_batched_graph_replays_match_eager():
         torch.cuda.synchronize()
         for i, (o, r) in enumerate(zip(outs, refs)):
             assert torch.equal(o, r), f"call {call} product {i}"
+
+
+@pytest.mark.parametrize("fill", ["max", "random"])
+def test_mfma_centred_limbs_for_primes_above_0x7f7f7f7f(fill):
+    """A direct-mode prime above 0x7F7F7F7F (2^31 - 1 at d = 1, one point)
+    takes the MFMA kernel's centred digit path; all-(p-1) and random inputs."""
+    p, m, n, k, d = (1 << 31) - 1, 8, 64, 8, 1
+    info = Bd.pm_plan(p, m, n, k, d, 4)
+    assert info.mode == 0 and info.pointwise == 1
+    if fill == "max":
+        A = np.full((d, m, n), p - 1, dtype=np.uint32)
+        B = np.full((d, n, k), p - 1, dtype=np.uint32)
+    else:
+        A, B = tensors(p, m, n, k, d, seed=13)
+    C = gpu_mul(p, A, B)
+    assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
