@@ -140,6 +140,29 @@ pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
                         const uint64_t* B, uint64_t* C, void* workspace,
                         uint64_t workspace_bytes, void* stream);
 
+/* A batch of coefficient windows (pm_middle_* products): each product follows
+ * the pm_middle_* rules for its own (m, n, k, da, db, lo, len) and pointers. */
+typedef struct pm_window_product {
+  int32_t m, n, k, da, db, lo, len, pad;
+  const void* A;
+  const void* B;
+  void* C;
+} pm_window_product;
+
+/* Workspace bytes for pm_middle_batched_* over `count` windows (host array). */
+pm_status pm_middle_batched_workspace_bytes(uint64_t p, int32_t count,
+                                            const pm_window_product* wins,
+                                            int32_t elem_bytes, uint64_t* out);
+
+/* All `count` windows in the phase launches of pm_mul_batched_* (as when
+ * several independent PM-Basis computations issue their residuals and basis
+ * products level by level).  Outputs are identical, byte for byte, to one
+ * pm_middle_* call per product.  Asynchronous on `stream`. */
+pm_status pm_middle_batched_u32(uint32_t p, int32_t count, const pm_window_product* wins,
+                                void* workspace, uint64_t workspace_bytes, void* stream);
+pm_status pm_middle_batched_u64(uint64_t p, int32_t count, const pm_window_product* wins,
+                                void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* Algorithm M-Basis (Section 3, "Approximant bases": sigma rounds of
  * residual, M-Basis-1 returning the s'-Popov basis at order 1, P := Q P and
  * s' := rdeg_s(P)) on the host, for the leaves of PM-Basis, whose polynomial

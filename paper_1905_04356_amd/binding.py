@@ -27,7 +27,8 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_mul_batched_u32", "pm_mul_batched_u64", "pm_eval_bytes", "pm_eval_u32",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
            "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
-           "pm_matinv_host")
+           "pm_matinv_host", "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
+           "pm_middle_batched_u64")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
 
@@ -53,6 +54,13 @@ class pm_product(ctypes.Structure):
                 ("d", ctypes.c_int32), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
                 ("C", ctypes.c_void_p), ("A_eval", ctypes.c_void_p),
                 ("B_eval", ctypes.c_void_p)]
+
+
+class pm_window_product(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("da", ctypes.c_int32), ("db", ctypes.c_int32), ("lo", ctypes.c_int32),
+                ("len", ctypes.c_int32), ("pad", ctypes.c_int32), ("A", ctypes.c_void_p),
+                ("B", ctypes.c_void_p), ("C", ctypes.c_void_p)]
 
 
 _lib = None
@@ -91,13 +99,19 @@ def lib():
     L.pm_middle_u64.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_mbasis_host.argtypes = [u64, i32, i32, i32, vp, vp, vp, vp]
     L.pm_matinv_host.argtypes = [u64, i32, vp, vp]
+    L.pm_middle_batched_workspace_bytes.argtypes = [u64, i32, ctypes.POINTER(pm_window_product),
+                                                    i32, ctypes.POINTER(u64)]
+    L.pm_middle_batched_u32.argtypes = [u32, i32, ctypes.POINTER(pm_window_product), vp, u64, vp]
+    L.pm_middle_batched_u64.argtypes = [u64, i32, ctypes.POINTER(pm_window_product), vp, u64, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
                  "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
-                 "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host"):
+                 "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host",
+                 "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
+                 "pm_middle_batched_u64"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -239,3 +253,26 @@ def pm_matinv_host(p: int, M):
     out = np.zeros((n, n), dtype=np.uint64)
     _check(lib().pm_matinv_host(p, n, M.ctypes.data, out.ctypes.data), "pm_matinv_host")
     return out
+
+
+def windows_array(wins) -> ctypes.Array:
+    """(m, n, k, da, db, lo, len, A_ptr, B_ptr, C_ptr) tuples -> pm_window_product[count]."""
+    arr = (pm_window_product * max(1, len(wins)))()
+    for i, (m, n, k, da, db, lo, ln, a, b, c) in enumerate(wins):
+        arr[i] = pm_window_product(m, n, k, da, db, lo, ln, 0, a, b, c)
+    return arr
+
+
+def pm_middle_batched_workspace_bytes(p: int, arr, count: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_middle_batched_workspace_bytes(p, count, arr, elem_bytes, ctypes.byref(out)),
+           "pm_middle_batched_workspace_bytes")
+    return out.value
+
+
+def pm_middle_batched_u32(p, count, arr, ws, ws_bytes, stream) -> int:
+    return lib().pm_middle_batched_u32(p, count, arr, ws, ws_bytes, stream)
+
+
+def pm_middle_batched_u64(p, count, arr, ws, ws_bytes, stream) -> int:
+    return lib().pm_middle_batched_u64(p, count, arr, ws, ws_bytes, stream)

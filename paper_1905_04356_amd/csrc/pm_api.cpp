@@ -442,15 +442,13 @@ struct BatchLayout {
   uint64_t nseg;
 };
 
-int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_bytes,
-               std::vector<Plan>& plans, std::vector<uint64_t>& offs, BatchLayout* lay) {
-  plans.resize(count);
+// Workspace layout of a batch whose plans are made: per-product workspaces,
+// then the product descriptors and the segment table.
+void layout_batch(const std::vector<Plan>& plans, std::vector<uint64_t>& offs, BatchLayout* lay) {
+  const int count = (int)plans.size();
   offs.resize(count);
   uint64_t off = 0, nseg = 0;
   for (int32_t i = 0; i < count; ++i) {
-    const pm_product& pr = prods[i];
-    int st = make_plan(p, pr.m, pr.n, pr.k, pr.d, elem_bytes, &plans[i]);
-    if (st != PM_OK) return st;
     offs[i] = off;
     off = align_up(off + plans[i].ws_bytes, 256);
     nseg += count_segments(plans[i]);
@@ -461,6 +459,35 @@ int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_
   off = align_up(off + sizeof(BatchSeg) * nseg, 256);
   lay->total = off;
   lay->nseg = nseg;
+}
+
+int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_bytes,
+               std::vector<Plan>& plans, std::vector<uint64_t>& offs, BatchLayout* lay) {
+  plans.resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const pm_product& pr = prods[i];
+    int st = make_plan(p, pr.m, pr.n, pr.k, pr.d, elem_bytes, &plans[i]);
+    if (st != PM_OK) return st;
+  }
+  layout_batch(plans, offs, lay);
+  return PM_OK;
+}
+
+// Plans of a batch of coefficient windows (pm_window_product), with the
+// products re-expressed as pm_product (no precomputed evaluations) for the
+// shared launch code.
+int plan_window_batch(uint64_t p, int32_t count, const pm_window_product* wins,
+                      int32_t elem_bytes, std::vector<Plan>& plans, std::vector<uint64_t>& offs,
+                      BatchLayout* lay, std::vector<pm_product>* prods) {
+  plans.resize(count);
+  if (prods) prods->resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const pm_window_product& w = wins[i];
+    int st = make_slice_plan(p, w.m, w.n, w.k, w.da, w.db, w.lo, w.len, elem_bytes, &plans[i]);
+    if (st != PM_OK) return st;
+    if (prods) (*prods)[i] = pm_product{w.m, w.n, w.k, 0, w.A, w.B, w.C, nullptr, nullptr};
+  }
+  layout_batch(plans, offs, lay);
   return PM_OK;
 }
 
@@ -703,14 +730,21 @@ hipStream_t capture_stream(int dev) {
   return streams[dev];
 }
 
-std::vector<uint8_t> batch_signature(uint64_t p, int eb, const pm_product* prods, int count,
-                                     const void* ws, uint64_t ws_bytes, int dev) {
-  std::vector<uint8_t> sig(sizeof(uint64_t) * 3 + sizeof(int) * 2 + sizeof(pm_product) * count);
+std::vector<uint8_t> batch_signature(uint64_t p, int eb, const pm_product* prods,
+                                     const std::vector<Plan>& plans, const void* ws,
+                                     uint64_t ws_bytes, int dev) {
+  const int count = (int)plans.size();
+  std::vector<uint8_t> sig(sizeof(uint64_t) * 3 + sizeof(int) * 2 +
+                           (sizeof(pm_product) + 4 * sizeof(int)) * count);
   uint8_t* o = sig.data();
   auto put = [&](const void* x, size_t n) { memcpy(o, x, n); o += n; };
   const uint64_t w = (uint64_t)(uintptr_t)ws;
   put(&p, 8); put(&w, 8); put(&ws_bytes, 8); put(&eb, sizeof eb); put(&dev, sizeof dev);
   put(prods, sizeof(pm_product) * count);
+  for (const Plan& P : plans) {  // coefficient windows (whole products: d, d, 0, 2d-1)
+    const int win[4] = {P.da, P.db, P.lo, P.nout};
+    put(win, sizeof win);
+  }
   return sig;
 }
 
@@ -739,7 +773,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
-  std::vector<uint8_t> sig = batch_signature(p, eb, prods, count, ws, ws_bytes, dev);
+  std::vector<uint8_t> sig = batch_signature(p, eb, prods, plans, ws, ws_bytes, dev);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   GraphEntry* e = nullptr;
   for (auto& g : g_graphs)
@@ -851,6 +885,54 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
   }
   return (pm_status)run_batch(p, elem_bytes, plans, offs, lay, prods, (uint8_t*)ws, ws_bytes,
                               (hipStream_t)stream);
+}
+
+static pm_status window_batched_common(uint64_t p, int32_t count,
+                                       const pm_window_product* wins, int elem_bytes, void* ws,
+                                       uint64_t ws_bytes, void* stream) {
+  if (count < 0 || (count > 0 && !wins)) return PM_EINVAL;
+  if (count == 0) return PM_OK;
+  std::vector<Plan> plans;
+  std::vector<uint64_t> offs;
+  std::vector<pm_product> prods;
+  BatchLayout lay;
+  int st = plan_window_batch(p, count, wins, elem_bytes, plans, offs, &lay, &prods);
+  if (st != PM_OK) return (pm_status)st;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < lay.total) return PM_EWORKSPACE;
+  const uint64_t eb = (uint64_t)elem_bytes;
+  for (int32_t i = 0; i < count; ++i) {
+    const Plan& P = plans[i];
+    st = check_operands(P, prods[i].A, prods[i].B, prods[i].C);
+    if (st != PM_OK) return (pm_status)st;
+    st = check_workspace(ws, ws_bytes, lay.total, prods[i].A, eb * P.da * P.m * P.n, prods[i].B,
+                         eb * P.db * P.n * P.k, prods[i].C, eb * (uint64_t)P.nout * P.m * P.k);
+    if (st != PM_OK) return (pm_status)st;
+  }
+  return (pm_status)run_batch(p, elem_bytes, plans, offs, lay, prods.data(), (uint8_t*)ws,
+                              ws_bytes, (hipStream_t)stream);
+}
+
+pm_status pm_middle_batched_workspace_bytes(uint64_t p, int32_t count,
+                                            const pm_window_product* wins, int32_t elem_bytes,
+                                            uint64_t* out) {
+  if (!out || count < 0 || (count > 0 && !wins)) return PM_EINVAL;
+  std::vector<Plan> plans;
+  std::vector<uint64_t> offs;
+  BatchLayout lay;
+  int st = plan_window_batch(p, count, wins, elem_bytes, plans, offs, &lay, nullptr);
+  if (st != PM_OK) return (pm_status)st;
+  *out = count ? lay.total : 0;
+  return PM_OK;
+}
+
+pm_status pm_middle_batched_u32(uint32_t p, int32_t count, const pm_window_product* wins,
+                                void* workspace, uint64_t workspace_bytes, void* stream) {
+  return window_batched_common(p, count, wins, 4, workspace, workspace_bytes, stream);
+}
+
+pm_status pm_middle_batched_u64(uint64_t p, int32_t count, const pm_window_product* wins,
+                                void* workspace, uint64_t workspace_bytes, void* stream) {
+  return window_batched_common(p, count, wins, 8, workspace, workspace_bytes, stream);
 }
 
 pm_status pm_mul_batched_u32(uint32_t p, int32_t count, const pm_product* prods, void* workspace,

@@ -38,11 +38,21 @@ __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, ui
     const uint32_t items = col_items(a);
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
-    // (batched products are whole products: nin = d <= L/2)
+    // whole products have nin = d <= L/2; coefficient windows may not
+    const bool zhi = 2 * a.nin <= (1 << a.logL);
     switch (a.split) {
-      case 2: col_fwd_items<TIn, RED, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      case 3: col_fwd_items<TIn, RED, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      default: col_fwd_items<TIn, RED, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 2:
+        if (zhi) col_fwd_items<TIn, RED, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        else col_fwd_items<TIn, RED, 2, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        break;
+      case 3:
+        if (zhi) col_fwd_items<TIn, RED, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        else col_fwd_items<TIn, RED, 3, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        break;
+      default:
+        if (zhi) col_fwd_items<TIn, RED, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        else col_fwd_items<TIn, RED, 4, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
+        break;
     }
   } else {
     constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;

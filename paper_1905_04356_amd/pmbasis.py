@@ -97,3 +97,47 @@ class PMBasis:
 def pmbasis(p: int, F: torch.Tensor, sigma: int, shift, threshold: int = 16, stream=None):
     """PM-Basis(F, sigma, shift) mod p; see PMBasis."""
     return PMBasis(p, threshold, stream)(F, sigma, shift)
+
+
+class PMBasisMany(PMBasis):
+    """Several independent PM-Basis computations of the same order, run in
+    lockstep: at every node of the recursion the residuals of all instances
+    are one pm_middle_batched call, and so are their basis products, so the
+    batched phase kernels carry the whole family (shapes and degrees may
+    differ between instances)."""
+
+    def _run_many(self, Fs, sigma: int, ss):
+        if sigma <= self.T:
+            outs = [self._leaf(F, sigma, s) for F, s in zip(Fs, ss)]
+            return [o[0] for o in outs], [o[1] for o in outs]
+        c = (sigma + 1) // 2
+        d = sigma - c
+        P1s, s1s = self._run_many([F[:c] for F in Fs], c, ss)
+        if self.ws is None:
+            self.ws = polymat.Workspace(Fs[0].device)
+        Rs = polymat.middle_batched(self.p, P1s, [F[:sigma] for F in Fs], [(c, d)] * len(Fs),
+                                    workspace=self.ws, stream=self.stream)
+        P2s, s2s = self._run_many(Rs, d, s1s)
+        Ps = polymat.middle_batched(self.p, P2s, P1s,
+                                    [(0, a.shape[0] + b.shape[0] - 1) for a, b in zip(P2s, P1s)],
+                                    workspace=self.ws, stream=self.stream)
+        self.products += 2 * len(Fs)
+        return [self._bound(P, s2, s) for P, s2, s in zip(Ps, s2s, ss)], s2s
+
+    def __call__(self, Fs, sigma: int, shifts):
+        """Fs: list of (>= sigma, m_i, n_i) GPU tensors; shifts: one list per
+        instance.  Returns a list of (P, rdeg), as PMBasis does for each."""
+        if not Fs or len(Fs) != len(shifts):
+            raise ValueError("one shift list per series")
+        ss = [[int(x) for x in s] for s in shifts]
+        for F, s in zip(Fs, ss):
+            if F.dim() != 3 or F.shape[0] < sigma or len(s) != F.shape[1]:
+                raise ValueError("each F must be (>= sigma, m, n) with m shifts")
+        Ps, rds = self._run_many([F.contiguous() for F in Fs], sigma, ss)
+        out = []
+        for P, rd in zip(Ps, rds):
+            signed = torch.int64 if P.dtype == torch.uint64 else torch.int32
+            nz = torch.nonzero(P.reshape(P.shape[0], -1).view(signed).ne(0).any(dim=1))
+            D = int(nz.max().item()) + 1 if nz.numel() else 1
+            out.append((P[:D].contiguous(), rd))
+        return out

@@ -112,6 +112,37 @@ def middle(p: int, A: torch.Tensor, B: torch.Tensor, lo: int, length: int,
     return out
 
 
+def middle_batched(p: int, As, Bs, windows, outs=None, workspace: Workspace | None = None,
+                   stream=None):
+    """[coefficients lo_i .. lo_i+len_i-1 of A_i B_i mod p] in one batched call;
+    windows: list of (lo, len)."""
+    if not (len(As) == len(Bs) == len(windows)):
+        raise ValueError("As, Bs and windows differ in length")
+    if not As:
+        return []
+    eb = _elem_bytes(As[0])
+    if outs is None:
+        outs = [torch.empty((ln, A.shape[1], B.shape[2]), dtype=A.dtype, device=A.device)
+                for A, B, (lo, ln) in zip(As, Bs, windows)]
+    wins = []
+    As = [A.contiguous() for A in As]
+    Bs = [B.contiguous() for B in Bs]
+    for A, B, C, (lo, ln) in zip(As, Bs, outs, windows):
+        da, m, n = A.shape
+        db, n2, k = B.shape
+        if n2 != n or _elem_bytes(A) != eb or _elem_bytes(B) != eb:
+            raise ValueError("inconsistent batch member")
+        wins.append((m, n, k, da, db, lo, ln, A.data_ptr(), B.data_ptr(), C.data_ptr()))
+    arr = _b.windows_array(wins)
+    need = _b.pm_middle_batched_workspace_bytes(p, arr, len(wins), eb)
+    ws = (workspace or _workspace(As[0].device)).get(need)
+    fn = _b.pm_middle_batched_u32 if eb == 4 else _b.pm_middle_batched_u64
+    st = fn(p, len(wins), arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_middle_batched")
+    return outs
+
+
 def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
     """Evaluations of one operand (role 0: left factor A, 1: right factor B)
     as a device byte tensor, reusable by every product with the same p,

@@ -85,3 +85,40 @@ def test_pmbasis_certified(p, sigma, m, n, T):
     assert X._rank_mod(F0, p) == n          # F(0) of full column rank
     assert X.pivot_degree_sum(P) == n * sigma
     assert rd == X.rdeg(P, s)
+
+
+def test_pmbasis_many_equals_single_runs():
+    """Instances in lockstep (batched residuals and products) give the same
+    bases as one run each; the small instance also equals the oracle."""
+    p, sigma, T = P30, 300, 8
+    cases = [(4, 2, [0, 0, 0, 0]), (6, 3, [1, 0, 2, 0, 0, 1]), (5, 1, [0, 0, 0, 0, 0]),
+             (3, 2, [0, 2, 1])]
+    Fs = [torch.from_numpy(series(p, sigma, m, n, seed=20 + i)).cuda()
+          for i, (m, n, _) in enumerate(cases)]
+    many = PB.PMBasisMany(p, T)(Fs, sigma, [s for _, _, s in cases])
+    for F, (m, n, s), (P, rd) in zip(Fs, cases, many):
+        P1, rd1 = PB.pmbasis(p, F, sigma, s, threshold=T)
+        assert P.shape == P1.shape and torch.equal(P, P1) and rd == rd1
+    torch.cuda.synchronize()
+    small = series(p, 40, 3, 2, seed=31)
+    (P, rd), = PB.PMBasisMany(p, 4)([torch.from_numpy(small).cuda()], 40, [[0, 1, 0]])
+    ref = X.pmbasis(small.astype(object), 40, [0, 1, 0], p, 4)
+    assert np.array_equal(P.cpu().numpy().astype(object), ref)
+
+
+def test_middle_batched_equals_single_windows():
+    from paper_1905_04356_amd import polymat
+    p = P31
+    specs = [(3, 4, 2, 10, 25, 10, 15), (8, 8, 4, 1025, 2048, 1024, 1024),
+             (2, 2, 2, 700, 3000, 650, 2300), (4, 4, 4, 33, 64, 0, 96), (1, 1, 1, 1, 1, 0, 1),
+             (16, 8, 8, 513, 1024, 512, 512)]
+    As, Bs, wins = [], [], []
+    for i, (m, n, k, da, db, lo, ln) in enumerate(specs):
+        As.append(torch.from_numpy(I.polymat(40, i, I.TENSOR_A, p, da, m, n)).cuda())
+        Bs.append(torch.from_numpy(I.polymat(40, i, I.TENSOR_B, p, db, n, k)).cuda())
+        wins.append((lo, ln))
+    for rep in range(3):        # repeats: the third replays a captured graph
+        got = polymat.middle_batched(p, As, Bs, wins)
+        for A, B, (lo, ln), g in zip(As, Bs, wins, got):
+            assert torch.equal(g, polymat.middle(p, A, B, lo, ln)), (rep, lo, ln)
+        torch.cuda.synchronize()
