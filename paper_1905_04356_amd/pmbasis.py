@@ -16,6 +16,8 @@ bounds the coefficients kept.
 """
 from __future__ import annotations
 
+import concurrent.futures
+import os
 import time
 
 import numpy as np
@@ -106,10 +108,29 @@ class PMBasisMany(PMBasis):
     batched phase kernels carry the whole family (shapes and degrees may
     differ between instances)."""
 
+    def __init__(self, p: int, threshold: int = 16, stream=None, workers: int | None = None):
+        super().__init__(p, threshold, stream)
+        self.workers = workers or min(16, os.cpu_count() or 1)
+        self.pool = None
+
+    def _leaves(self, Fs, sigma: int, ss):
+        """The instances' leaves are independent: their host eliminations run
+        on a thread pool (the C calls release the interpreter lock)."""
+        t0 = time.perf_counter()
+        hosts = [F[:sigma].to("cpu").numpy().astype(np.uint64) for F in Fs]
+        if self.pool is None:
+            self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.workers)
+        res = list(self.pool.map(lambda a: _b.pm_mbasis_host(self.p, a[0], sigma, a[1]),
+                                 zip(hosts, ss)))
+        npdt = np.uint64 if Fs[0].dtype == torch.uint64 else np.uint32
+        Ps = [torch.from_numpy(_trim_host(P).astype(npdt)).to(Fs[0].device) for P, _ in res]
+        self.leaves += len(Fs)
+        self.leaf_seconds += time.perf_counter() - t0
+        return Ps, [rd for _, rd in res]
+
     def _run_many(self, Fs, sigma: int, ss):
         if sigma <= self.T:
-            outs = [self._leaf(F, sigma, s) for F, s in zip(Fs, ss)]
-            return [o[0] for o in outs], [o[1] for o in outs]
+            return self._leaves(Fs, sigma, ss)
         c = (sigma + 1) // 2
         d = sigma - c
         P1s, s1s = self._run_many([F[:c] for F in Fs], c, ss)
