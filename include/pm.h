@@ -172,8 +172,8 @@ pm_status pm_middle_batched_u64(uint64_t p, int32_t count, const pm_window_produ
  * coefficient-major, an s-ordered weak Popov approximant basis of (F, sigma)
  * (coefficients above its degree are zero); rdeg_out: m host integers,
  * rdeg_shift(P).  p must be a prime, 2 <= p < 2^62 (PM_EINVAL if not prime,
- * PM_ERANGE if too large); PM_EINVAL on sizes < 1 or NULL pointers.
- * Synchronous; touches no device. */
+ * PM_ERANGE if too large); PM_EINVAL on sizes < 1 or NULL pointers;
+ * PM_ENOMEM if host memory runs out.  Synchronous; touches no device. */
 pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
                          const uint64_t* F, const int64_t* shift, uint64_t* P,
                          int64_t* rdeg_out);
@@ -183,7 +183,8 @@ pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
  * the truncated inverse A^{-1} mod x^N (Section 4, "Lifting techniques").
  * M, Minv: host arrays of n*n residues, row-major.  PM_EINVAL if M is
  * singular mod p, p is not prime, n < 1 or a pointer is NULL; PM_ERANGE if
- * p >= 2^62.  Synchronous; touches no device. */
+ * p >= 2^62; PM_ENOMEM if host memory runs out.  Synchronous; touches no
+ * device. */
 pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv);
 
 /* One product of a batch; the pointers follow the pm_mul_* layout rules.

@@ -854,17 +854,34 @@ extern "C" {
 pm_status pm_batched_workspace_bytes(uint64_t p, int32_t count, const pm_product* prods,
                                      int32_t elem_bytes, uint64_t* out) {
   if (!out || count < 0 || (count > 0 && !prods)) return PM_EINVAL;
-  std::vector<Plan> plans;
-  std::vector<uint64_t> offs;
-  BatchLayout lay;
-  int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
-  if (st != PM_OK) return (pm_status)st;
-  *out = lay.total;
-  return PM_OK;
+  try {
+    std::vector<Plan> plans;
+    std::vector<uint64_t> offs;
+    BatchLayout lay;
+    int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
+    if (st != PM_OK) return (pm_status)st;
+    *out = lay.total;
+    return PM_OK;
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
 }
 
+static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods,
+                              int elem_bytes, void* ws, uint64_t ws_bytes, void* stream);
+
+// Host allocation failures of the batch bookkeeping become PM_ENOMEM.
 static pm_status batched_common(uint64_t p, int32_t count, const pm_product* prods,
                                 int elem_bytes, void* ws, uint64_t ws_bytes, void* stream) {
+  try {
+    return batched_impl(p, count, prods, elem_bytes, ws, ws_bytes, stream);
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
+}
+
+static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods,
+                              int elem_bytes, void* ws, uint64_t ws_bytes, void* stream) {
   if (count < 0 || (count > 0 && !prods)) return PM_EINVAL;
   if (count == 0) return PM_OK;
   std::vector<Plan> plans;
@@ -887,9 +904,23 @@ static pm_status batched_common(uint64_t p, int32_t count, const pm_product* pro
                               (hipStream_t)stream);
 }
 
+static pm_status window_batched_impl(uint64_t p, int32_t count,
+                                     const pm_window_product* wins, int elem_bytes, void* ws,
+                                     uint64_t ws_bytes, void* stream);
+
 static pm_status window_batched_common(uint64_t p, int32_t count,
                                        const pm_window_product* wins, int elem_bytes, void* ws,
                                        uint64_t ws_bytes, void* stream) {
+  try {
+    return window_batched_impl(p, count, wins, elem_bytes, ws, ws_bytes, stream);
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
+}
+
+static pm_status window_batched_impl(uint64_t p, int32_t count,
+                                     const pm_window_product* wins, int elem_bytes, void* ws,
+                                     uint64_t ws_bytes, void* stream) {
   if (count < 0 || (count > 0 && !wins)) return PM_EINVAL;
   if (count == 0) return PM_OK;
   std::vector<Plan> plans;
@@ -916,13 +947,17 @@ pm_status pm_middle_batched_workspace_bytes(uint64_t p, int32_t count,
                                             const pm_window_product* wins, int32_t elem_bytes,
                                             uint64_t* out) {
   if (!out || count < 0 || (count > 0 && !wins)) return PM_EINVAL;
-  std::vector<Plan> plans;
-  std::vector<uint64_t> offs;
-  BatchLayout lay;
-  int st = plan_window_batch(p, count, wins, elem_bytes, plans, offs, &lay, nullptr);
-  if (st != PM_OK) return (pm_status)st;
-  *out = count ? lay.total : 0;
-  return PM_OK;
+  try {
+    std::vector<Plan> plans;
+    std::vector<uint64_t> offs;
+    BatchLayout lay;
+    int st = plan_window_batch(p, count, wins, elem_bytes, plans, offs, &lay, nullptr);
+    if (st != PM_OK) return (pm_status)st;
+    *out = count ? lay.total : 0;
+    return PM_OK;
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
 }
 
 pm_status pm_middle_batched_u32(uint32_t p, int32_t count, const pm_window_product* wins,

@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <numeric>
 #include <vector>
 
@@ -78,13 +79,8 @@ void row_degrees(const std::vector<uint64_t>& P, int D, int m, const int64_t* s,
 
 }  // namespace
 
-extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
-                                    const uint64_t* F, const int64_t* shift, uint64_t* Pout,
-                                    int64_t* rdeg_out) {
-  if (!F || !shift || !Pout || !rdeg_out) return PM_EINVAL;
-  if (m < 1 || n < 1 || sigma < 1) return PM_EINVAL;
-  if (p >= (1ull << 62)) return PM_ERANGE;
-  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+static pm_status mbasis_impl(uint64_t p, int32_t m, int32_t n, int32_t sigma, const uint64_t* F,
+                             const int64_t* shift, uint64_t* Pout, int64_t* rdeg_out) {
   const Field K(p);
   const int D = sigma + 1;                       // coefficients of P (degree <= sigma)
   std::vector<uint64_t> P((size_t)D * m * m, 0), G((size_t)sigma * m * n, 0);
@@ -174,13 +170,24 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
   return PM_OK;
 }
 
+extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t sigma,
+                                    const uint64_t* F, const int64_t* shift, uint64_t* Pout,
+                                    int64_t* rdeg_out) {
+  if (!F || !shift || !Pout || !rdeg_out) return PM_EINVAL;
+  if (m < 1 || n < 1 || sigma < 1) return PM_EINVAL;
+  if (p >= (1ull << 62)) return PM_ERANGE;
+  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+  try {
+    return mbasis_impl(p, m, n, sigma, F, shift, Pout, rdeg_out);
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
+}
+
 // Inverse of an n x n matrix mod a prime p by Gauss-Jordan elimination with
 // row pivoting: the constant term A(0)^{-1} with which Newton iteration for
 // truncated inverses starts.
-extern "C" pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv) {
-  if (!M || !Minv || n < 1) return PM_EINVAL;
-  if (p >= (1ull << 62)) return PM_ERANGE;
-  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+static pm_status matinv_impl(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv) {
   const Field K(p);
   const size_t w = 2 * (size_t)n;
   std::vector<uint64_t> a((size_t)n * w, 0);
@@ -206,4 +213,15 @@ extern "C" pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, ui
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) Minv[(size_t)i * n + j] = a[i * w + n + j];
   return PM_OK;
+}
+
+extern "C" pm_status pm_matinv_host(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv) {
+  if (!M || !Minv || n < 1) return PM_EINVAL;
+  if (p >= (1ull << 62)) return PM_ERANGE;
+  if (p < 2 || !pm::is_prime_u64(p)) return PM_EINVAL;
+  try {
+    return matinv_impl(p, n, M, Minv);
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
 }
