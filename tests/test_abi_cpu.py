@@ -138,3 +138,52 @@ def test_check_residues_rejects_bad_arguments():
     out = ctypes.c_uint64(0)
     assert L.pm_check_residues(97, 0, 10, 4, ctypes.byref(out), 1 << 20, None) == B.PM_EINVAL
     assert L.pm_check_residues(97, 1 << 20, 10, 3, ctypes.byref(out), 1 << 20, None) == B.PM_EINVAL
+
+
+@pytest.mark.parametrize("da,db,lo,length", [(1, 1, 0, 1), (5, 9, 5, 4), (4097, 8192, 4096, 4096),
+                                             (100, 100, 0, 199), (3, 3000, 0, 3000),
+                                             (2048, 4096, 2048, 2048), (7, 7, 12, 1)])
+def test_middle_plan_length_is_the_least_that_keeps_the_window_exact(da, db, lo, length):
+    info = B.pm_middle_plan(998244353, 2, 3, 2, da, db, lo, length, 4)
+    need = max(da + db - 1 - lo, lo + length)
+    L = 1 << info.log2_len
+    assert L >= need and (L // 2 < need or L == 1)
+    # the paper's MiddleProduct with c = d uses half the points of the whole product
+    if (da, db, lo, length) == (2048, 4096, 2048, 2048):
+        full = B.pm_plan(998244353, 2, 3, 2, 4096, 4)
+        assert info.log2_len == full.log2_len - 1
+
+
+def test_middle_plan_crt_bound_uses_the_shorter_operand():
+    p = 4294967291                     # not NTT-friendly: CRT mode
+    a = B.pm_middle_plan(p, 4, 64, 4, 10, 4000, 10, 3990, 4)
+    b = B.pm_plan(p, 4, 64, 4, 4000, 4)
+    assert a.mode == b.mode == 1
+    qs = [a.primes[i] for i in range(a.num_primes)]
+    assert math.prod(qs) > 64 * 10 * (p - 1) ** 2
+    assert a.num_primes <= b.num_primes
+
+
+@pytest.mark.parametrize("args", [(3, 3, -1, 2), (3, 3, 0, 0), (3, 3, 4, 2), (0, 3, 0, 1),
+                                  (3, 0, 0, 1)])
+def test_middle_plan_rejects_bad_windows(args):
+    da, db, lo, length = args
+    with pytest.raises(B.PmError) as e:
+        B.pm_middle_plan(97, 2, 2, 2, da, db, lo, length, 4)
+    assert e.value.status == B.PM_EINVAL
+
+
+def test_middle_batched_workspace_and_checks():
+    A, Bp, C = 1 << 20, 2 << 20, 3 << 20
+    arr = B.windows_array([(4, 4, 4, 16, 32, 16, 16, A, Bp, C),
+                           (2, 3, 2, 5, 9, 5, 4, A, Bp, C + (1 << 16))])
+    need = B.pm_middle_batched_workspace_bytes(998244353, arr, 2, 4)
+    one = B.pm_middle_plan(998244353, 4, 4, 4, 16, 32, 16, 16, 4).workspace_bytes
+    assert need >= one
+    L = B.lib()
+    assert L.pm_middle_batched_u32(998244353, 2, arr, 64 << 20, need - 1, None) == B.PM_EWORKSPACE
+    assert L.pm_middle_batched_u32(998244353, -1, arr, 64 << 20, need, None) == B.PM_EINVAL
+    assert L.pm_middle_batched_u32(998244353, 0, arr, 64 << 20, need, None) == B.PM_OK
+    bad = B.windows_array([(4, 4, 4, 16, 32, 40, 16, A, Bp, C)])   # window past the product
+    with pytest.raises(B.PmError):
+        B.pm_middle_batched_workspace_bytes(998244353, bad, 1, 4)
