@@ -140,6 +140,24 @@ pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
                         const uint64_t* B, uint64_t* C, void* workspace,
                         uint64_t workspace_bytes, void* stream);
 
+/* C = A B mod p by evaluation at the points 0, 1, ..., 2d-2 and interpolation
+ * back, both as matrix products over F_p with (inverse) Vandermonde matrices
+ * on the int8 matrix cores (Section 2, "Polynomial matrix multiplication":
+ * the adaptation of Doliskani, Giorgi, Lebreton and Schost, which replaces
+ * evaluation/interpolation by plain multiplication with Vandermonde
+ * matrices, worthwhile for moderate d; and "3-primes" multiplication is not
+ * needed for moduli without roots of unity).  Same operands, layout, pointer
+ * and workspace rules and result as pm_mul_u32 (workspace size from
+ * pm_vdm_workspace_bytes).  Requires p prime, 3 <= p < 2^31, 2d - 1 <= p,
+ * 2d - 1 < 4096 and n < 4096 (PM_ERANGE / PM_EINVAL / PM_EUNSUPPORTED
+ * otherwise).  The Vandermonde matrices are built on the host and kept on
+ * the device per (p, d) on first use.  Asynchronous on `stream`. */
+pm_status pm_vdm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                                 uint64_t* out);
+pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         const uint32_t* A, const uint32_t* B, uint32_t* C,
+                         void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* A batch of coefficient windows (pm_middle_* products): each product follows
  * the pm_middle_* rules for its own (m, n, k, da, db, lo, len) and pointers. */
 typedef struct pm_window_product {
@@ -247,7 +265,8 @@ pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count,
  * pm_profile_end waits for those events and returns, per kernel kind, the
  * summed device time and the launch count.  Kinds (index into the arrays):
  * 0 forward transform, 1 pointwise products, 2 inverse transform,
- * 3 Chinese remaindering, 4 batched persistent kernel.  Returns PM_EDEVICE if
+ * 3 Chinese remaindering, 4 batched persistent kernel, 5 evaluation and
+ * 6 interpolation by Vandermonde products.  Returns PM_EDEVICE if
  * an event could not be created or read; PM_EINVAL if out is NULL. */
 #define PM_KERNEL_KINDS 8
 typedef struct pm_kernel_stats {

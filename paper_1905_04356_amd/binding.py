@@ -28,9 +28,9 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
            "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
            "pm_matinv_host", "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
-           "pm_middle_batched_u64")
+           "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32")
 
-KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched")
+KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
 
 class PmError(RuntimeError):
@@ -103,6 +103,8 @@ def lib():
                                                     i32, ctypes.POINTER(u64)]
     L.pm_middle_batched_u32.argtypes = [u32, i32, ctypes.POINTER(pm_window_product), vp, u64, vp]
     L.pm_middle_batched_u64.argtypes = [u64, i32, ctypes.POINTER(pm_window_product), vp, u64, vp]
+    L.pm_vdm_workspace_bytes.argtypes = [u64, i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_mul_vdm_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
@@ -111,7 +113,7 @@ def lib():
                  "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
                  "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host",
                  "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
-                 "pm_middle_batched_u64"):
+                 "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -276,3 +278,14 @@ def pm_middle_batched_u32(p, count, arr, ws, ws_bytes, stream) -> int:
 
 def pm_middle_batched_u64(p, count, arr, ws, ws_bytes, stream) -> int:
     return lib().pm_middle_batched_u64(p, count, arr, ws, ws_bytes, stream)
+
+
+def pm_vdm_workspace_bytes(p: int, m: int, n: int, k: int, d: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_vdm_workspace_bytes(p, m, n, k, d, ctypes.byref(out)),
+           "pm_vdm_workspace_bytes")
+    return out.value
+
+
+def pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)

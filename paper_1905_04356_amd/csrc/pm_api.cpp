@@ -22,8 +22,18 @@
 #include "pm_kernels.h"
 #include "pm_plan.h"
 #include "pm_profile.h"
+#include "pm_vdm.h"
 
 using namespace pm;
+
+static int vdm_check(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d);
+static uint64_t vdm_ws_bytes(int m, int n, int k, int d);
+
+// Whether pm_mul_vdm_u32 takes this product (p prime below 2^31, odd,
+// 2d - 1 <= min(p, 4095), n < 4096).
+static bool vdm_eligible(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d) {
+  return p > 2 && vdm_check(p, m, n, k, d) == PM_OK;
+}
 
 static void fill_plan_info(const Plan& P, pm_plan_info* out) {
   memset(out, 0, sizeof *out);
@@ -253,12 +263,27 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   return launch_product(P, L, none, s);
 }
 
+// Largest d for which products mod a prime without the needed roots of unity
+// go through Vandermonde evaluation on the matrix cores instead of CRT
+// (PM_TUNE_VDM_MAXD, default 64: measured faster up to there).
+int vdm_max_d() {
+  static const int v = [] {
+    const char* e = getenv("PM_TUNE_VDM_MAXD");
+    return e ? atoi(e) : 64;
+  }();
+  return v;
+}
+
 pm_status mul_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int elem_bytes,
                      const void* A, const void* B, void* C, void* ws, uint64_t ws_bytes,
                      void* stream) {
   Plan P;
   int st = make_plan(p, m, n, k, d, elem_bytes, &P);
   if (st != PM_OK) return (pm_status)st;
+  if (P.mode == 1 && elem_bytes == 4 && d <= vdm_max_d() && vdm_eligible(p, m, n, k, d) &&
+      ws_bytes >= P.ws_bytes)
+    return pm_mul_vdm_u32((uint32_t)p, m, n, k, d, (const uint32_t*)A, (const uint32_t*)B,
+                          (uint32_t*)C, ws, ws_bytes, stream);
   st = check_operands(P, A, B, C);
   if (st != PM_OK) return (pm_status)st;
   const uint64_t eb = (uint64_t)elem_bytes;
@@ -297,6 +322,113 @@ pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, con
                      const uint64_t* B, uint64_t* C, void* workspace, uint64_t workspace_bytes,
                      void* stream) {
   return mul_common(p, m, n, k, d, 8, A, B, C, workspace, workspace_bytes, stream);
+}
+
+// ---- evaluation at 0 .. 2d-2 by Vandermonde products -------------------------
+
+static uint64_t vdm_ws_bytes(int m, int n, int k, int d) {
+  const uint64_t N = 2ull * d - 1;
+  return align_up(4 * N * (uint64_t)m * n, 256) + align_up(4 * N * (uint64_t)n * k, 256) +
+         align_up(4 * N * (uint64_t)m * k, 256);
+}
+
+static int vdm_check(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d) {
+  if (m < 1 || n < 1 || k < 1 || d < 1) return PM_EINVAL;
+  if (p < 2 || p >= (1ull << 31)) return PM_ERANGE;
+  if (!is_prime_u64(p)) return PM_EINVAL;
+  const uint64_t N = 2ull * d - 1;
+  if (N > (uint64_t)p || N > (uint64_t)kGemmMaxK - 1 || n >= 4096) return PM_EUNSUPPORTED;
+  const uint64_t lim = 1ull << 32;
+  if (N * m * n >= lim || N * n * k >= lim || N * m * k >= lim) return PM_ERANGE;
+  return PM_OK;
+}
+
+static void gemm_consts(uint32_t q, int K, GemmLaunch* g) {
+  g->q = q;
+  uint32_t inv = 1;  // q^{-1} mod 2^32 (q odd)
+  for (int it = 0; it < 5; ++it) inv *= 2u - q * inv;
+  g->qninv = 0u - inv;
+  uint64_t w = (1ull << 32) % q;
+  for (int s = 0; s < 7; ++s) {
+    g->cs[s] = (uint32_t)w;
+    w = (w << 8) % q;
+  }
+  g->bias = (uint64_t)q * 7ull * (uint64_t)K * 65536ull;
+}
+
+pm_status pm_vdm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                                 uint64_t* out) {
+  if (!out) return PM_EINVAL;
+  const int st = vdm_check(p, m, n, k, d);
+  if (st != PM_OK) return (pm_status)st;
+  *out = vdm_ws_bytes(m, n, k, d);
+  return PM_OK;
+}
+
+pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         const uint32_t* A, const uint32_t* B, uint32_t* C, void* workspace,
+                         uint64_t workspace_bytes, void* stream) {
+  int st = vdm_check(p, m, n, k, d);
+  if (st != PM_OK) return (pm_status)st;
+  if (p == 2) return PM_EUNSUPPORTED;  // the Montgomery epilogue needs q odd
+  Plan P{};
+  P.m = m; P.n = n; P.k = k; P.d = d; P.da = d; P.db = d; P.lo = 0; P.nout = 2 * d - 1;
+  P.elem_bytes = 4;
+  st = check_operands(P, A, B, C);
+  if (st != PM_OK) return (pm_status)st;
+  const uint64_t need = vdm_ws_bytes(m, n, k, d);
+  st = check_workspace(workspace, workspace_bytes, need, A, 4ull * d * m * n, B,
+                       4ull * d * n * k, C, 4ull * P.nout * m * k);
+  if (st != PM_OK) return (pm_status)st;
+  const uint32_t *V = nullptr, *W = nullptr;
+  st = get_vdm_tables(p, d, &V, &W);
+  if (st != PM_OK) return (pm_status)st;
+  const int N = 2 * d - 1;
+  uint8_t* ws = (uint8_t*)workspace;
+  uint32_t* ahat = (uint32_t*)ws;
+  uint32_t* bhat = (uint32_t*)(ws + align_up(4ull * N * m * n, 256));
+  uint32_t* chat = (uint32_t*)(ws + align_up(4ull * N * m * n, 256) +
+                               align_up(4ull * N * n * k, 256));
+  hipStream_t s = (hipStream_t)stream;
+  {
+    KernelTimer kt(K_VDM_EVAL, s);
+    GemmLaunch g{};
+    gemm_consts(p, d, &g);
+    g.M = N; g.K = d; g.ldx = d; g.X = V;
+    g.N = m * n; g.ldy = m * n; g.Y = A; g.ldz = m * n; g.Z = ahat;
+    if (launch_gemm_modp(g, s) != hipSuccess) return PM_EDEVICE;
+    g.N = n * k; g.ldy = n * k; g.Y = B; g.ldz = n * k; g.Z = bhat;
+    if (launch_gemm_modp(g, s) != hipSuccess) return PM_EDEVICE;
+  }
+  {
+    // one m x n by n x k product per point, no scaling (interpolation is W)
+    PointwiseLaunch pw;
+    memset(&pw, 0, sizeof pw);
+    pw.m = m; pw.n = n; pw.k = k; pw.L = N;
+    pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
+    pw.pc[0].q = p;
+    pw.pc[0].linv = 1;
+    pw.pc[0].linv_p = (uint32_t)((1ull << 32) / p);
+    pw.pc[0].mu = ~0ull / p;
+    GemmLaunch c{};
+    gemm_consts(p, n, &c);
+    for (int t = 0; t < 7; ++t) pw.cs[0][t] = c.cs[t];
+    pw.bias[0] = c.bias;
+    pw.qninv[0] = c.qninv;
+    KernelTimer kt(K_POINTWISE, s);
+    const int ok = choose_pointwise(m, n, k) == 1 ? launch_pointwise_mfma(pw, 1, s)
+                                                  : launch_pointwise(pw, 1, s);
+    if (ok != hipSuccess) return PM_EDEVICE;
+  }
+  {
+    KernelTimer kt(K_VDM_INTERP, s);
+    GemmLaunch g{};
+    gemm_consts(p, N, &g);
+    g.M = N; g.K = N; g.ldx = N; g.X = W;
+    g.N = m * k; g.ldy = m * k; g.Y = chat; g.ldz = m * k; g.Z = C;
+    if (launch_gemm_modp(g, s) != hipSuccess) return PM_EDEVICE;
+  }
+  return PM_OK;
 }
 
 pm_status pm_middle_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,

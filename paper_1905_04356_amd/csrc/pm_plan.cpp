@@ -195,7 +195,7 @@ static int ceil_log2(uint64_t x) {
 // length a multiple of 4 and below 2^12, both matrices' limb planes within
 // the 160 KiB of LDS of a CU), else the VALU kernel.  Tuning knob
 // PM_TUNE_POINTWISE=0 forces the VALU kernel.
-static int choose_pointwise(int m, int n, int k) {
+int choose_pointwise(int m, int n, int k) {
   const uint64_t mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
   const bool mfma_ok = n % 4 == 0 && n < 4096 && 4 * (mp + kp) * (np + 16) <= 160 * 1024;
   const char* env = getenv("PM_TUNE_POINTWISE");

@@ -92,6 +92,9 @@ int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out)
 int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
                     int elem_bytes, Plan* out);
 
+// Pointwise kernel for an m x n by n x k product per point: 1 int8-MFMA, 0 VALU.
+int choose_pointwise(int m, int n, int k);
+
 // Host number theory (the library's own; the test oracle has separate code).
 bool is_prime_u64(uint64_t n);
 uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t m);

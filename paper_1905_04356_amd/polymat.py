@@ -143,6 +143,29 @@ def middle_batched(p: int, As, Bs, windows, outs=None, workspace: Workspace | No
     return outs
 
 
+def mul_vdm(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+            workspace: Workspace | None = None, stream=None) -> torch.Tensor:
+    """C = A B mod p by Vandermonde evaluation/interpolation on the matrix
+    cores (uint32, p prime below 2^31, 2d - 1 <= p, 2d - 1 < 4096)."""
+    d, m, n = A.shape
+    d2, n2, k = B.shape
+    if d2 != d or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if A.dtype != torch.uint32 or B.dtype != torch.uint32:
+        raise TypeError("mul_vdm takes torch.uint32 residues")
+    A = A.contiguous()
+    B = B.contiguous()
+    if out is None:
+        out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
+    need = _b.pm_vdm_workspace_bytes(p, m, n, k, d)
+    ws = (workspace or _workspace(A.device)).get(need)
+    st = _b.pm_mul_vdm_u32(p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_mul_vdm")
+    return out
+
+
 def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
     """Evaluations of one operand (role 0: left factor A, 1: right factor B)
     as a device byte tensor, reusable by every product with the same p,
