@@ -291,6 +291,51 @@ def bench_newton(p=2013265921, n=32, da=2049, N=4096, rhs=64, seed=8):
             "products_transforming_S_ms": t_plain, "reuse_speedup": t_plain / t_reuse}
 
 
+def bench_vdm(p=1000000007, seed=9, reps=10):
+    """Products mod a prime without roots of unity of the needed order
+    (10^9 + 7: 2 is the only power of 2 dividing p - 1): Vandermonde
+    evaluation/interpolation on the matrix cores (pm_mul_vdm_u32) against
+    the three-prime CRT transforms (a one-product pm_mul_batched call, which
+    always takes the transforms), same operands, outputs compared."""
+    import torch
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for (m, n, k, d) in [(32, 32, 32, 16), (32, 32, 32, 64), (128, 128, 128, 64),
+                         (32, 32, 32, 256)]:
+        A = I.polymat_torch(seed, 0, I.TENSOR_A, p, d, m, n, dev)
+        B = I.polymat_torch(seed, 0, I.TENSOR_B, p, d, n, k, dev)
+        ws = polymat.Workspace(dev)
+        outv = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=dev)
+        outc = torch.empty_like(outv)
+        plan = Bd.pm_plan(p, m, n, k, d, 4)
+
+        def timed(fn):
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        t_v = timed(lambda: polymat.mul_vdm(p, A, B, out=outv, workspace=ws, stream=stream))
+        t_c = timed(lambda: polymat.mul_batched(p, [A], [B], [outc], workspace=ws,
+                                                stream=stream))
+        rows.append({"m": m, "n": n, "k": k, "d": d, "vandermonde_ms": t_v, "crt_ms": t_c,
+                     "crt_primes": plan.num_primes, "crt_L": 1 << plan.log2_len,
+                     "outputs_equal": bool(torch.equal(outv, outc))})
+        del A, B, ws, outv, outc
+    return {"workload": f"products mod {p} (no 2^k-th roots of unity for k > 1): Vandermonde "
+                        "evaluation on the matrix cores vs three-prime CRT", "runs": rows}
+
+
 def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
@@ -636,6 +681,8 @@ def main():
         out["pmbasis"] = bench_pmbasis()
         torch.cuda.empty_cache()
         out["newton"] = bench_newton()
+        torch.cuda.empty_cache()
+        out["vandermonde"] = bench_vdm()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
         out["serving"] = bench_serving(args.serving_seconds)
