@@ -274,6 +274,50 @@ int vdm_max_d() {
   return v;
 }
 
+// Products with 2^j < 2d - 1 <= 2^j + 2^(j-1): A B mod (x^(2^j) - 1) on a
+// transform of 2^j points, the t = 2d - 1 - 2^j coefficients at and above
+// 2^j, which involve only A[h..] and B[h..] (h = 2^j - d + 1), as the window
+// t-1 .. 2t-2 of that short product, and the wrapped rows corrected: at most
+// 1.5 2^j points instead of 2^(j+1).  PM_TUNE_WRAP=0 turns it off;
+// PM_TUNE_WRAP_MINLOG (default 10) is the least j.  Returns 1 when the
+// product was launched this way, 0 when it does not apply, or a pm_status.
+int wrap_min_log() {
+  static const int v = [] {
+    const char* e = getenv("PM_TUNE_WRAP");
+    if (e && e[0] == '0') return 99;
+    const char* f = getenv("PM_TUNE_WRAP_MINLOG");
+    return f ? atoi(f) : 10;
+  }();
+  return v;
+}
+
+int run_wrapped(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
+                uint64_t ws_bytes, hipStream_t s) {
+  const int j = P.logL - 1;
+  if (P.da != P.db || P.lo != 0 || j < wrap_min_log()) return 0;
+  const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
+  if (t < 1 || t > Lp / 2 || d > Lp) return 0;
+  Plan Pc, Pt;
+  if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, &Pc) != PM_OK) return 0;
+  if (make_slice_plan(P.p, P.m, P.n, P.k, t, t, t - 1, t, P.elem_bytes, &Pt) != PM_OK) return 0;
+  if (Pc.ws_bytes > ws_bytes || Pt.ws_bytes > ws_bytes) return 0;
+  const uint64_t eb = (uint64_t)P.elem_bytes;
+  const int h = Lp - d + 1;
+  int st = run_product(Pc, A, B, C, ws, s);
+  if (st != PM_OK) return st;
+  const uint8_t* At = (const uint8_t*)A + eb * h * P.m * P.n;
+  const uint8_t* Bt = (const uint8_t*)B + eb * h * P.n * P.k;
+  uint8_t* Ct = (uint8_t*)C + eb * (uint64_t)Lp * P.m * P.k;
+  st = run_product(Pt, At, Bt, Ct, ws, s);
+  if (st != PM_OK) return st;
+  const uint64_t mk = (uint64_t)P.m * P.k;
+  KernelTimer kt(K_CRT, s);
+  if (launch_unwrap(C, (uint64_t)t * mk, (uint64_t)Lp * mk, P.p, P.elem_bytes, s) !=
+      hipSuccess)
+    return PM_EDEVICE;
+  return 1;
+}
+
 pm_status mul_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int elem_bytes,
                      const void* A, const void* B, void* C, void* ws, uint64_t ws_bytes,
                      void* stream) {
@@ -290,6 +334,9 @@ pm_status mul_common(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int
   st = check_workspace(ws, ws_bytes, P.ws_bytes, A, eb * d * m * n, B, eb * d * n * k, C,
                        eb * (2ull * d - 1) * m * k);
   if (st != PM_OK) return (pm_status)st;
+  st = run_wrapped(P, A, B, C, (uint8_t*)ws, ws_bytes, (hipStream_t)stream);
+  if (st == 1) return PM_OK;
+  if (st != 0) return (pm_status)st;
   return (pm_status)run_product(P, A, B, C, (uint8_t*)ws, (hipStream_t)stream);
 }
 

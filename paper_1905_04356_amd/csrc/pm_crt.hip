@@ -46,4 +46,31 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
   return hipGetLastError();
 }
 
+// Coefficients of A B from A B mod (x^L - 1): rows L .. L + t - 1 of C hold
+// the true top coefficients, which wrapped onto rows 0 .. t - 1; subtract
+// them there (count = t m k elements, off = L m k).
+template <typename T>
+__global__ __launch_bounds__(256) void unwrap_kernel(T* C, uint64_t count, uint64_t off,
+                                                     uint64_t p) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const T a = C[i], b = C[off + i];
+    C[i] = a >= b ? a - b : (T)(a + (p - b));
+  }
+}
+
+int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,
+                  hipStream_t s) {
+  uint64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) return hipSuccess;
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(unwrap_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (uint64_t*)C, count, off, p);
+  else
+    hipLaunchKernelGGL(unwrap_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (uint32_t*)C, count, off, p);
+  return hipGetLastError();
+}
+
 }  // namespace pm

@@ -77,6 +77,9 @@ int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
                    hipStream_t s);
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s);
 int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
+// C[i] -= C[off + i] mod p for i < count (elements of elem_bytes bytes).
+int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,
+                  hipStream_t s);
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 size_t pointwise_mfma_lds(int m, int n, int k);
 int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s);

@@ -203,8 +203,23 @@ int choose_pointwise(int m, int n, int k) {
   return mfma_ok ? 1 : 0;
 }
 
+static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
+                          int elem_bytes, int force_log, Plan* out);
+
 int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
                     int elem_bytes, Plan* out) {
+  return make_plan_core(p, m, n, k, da, db, lo, nout, elem_bytes, -1, out);
+}
+
+int make_cyclic_plan(uint64_t p, int m, int n, int k, int d, int logL, int elem_bytes,
+                     Plan* out) {
+  if (logL < 0 || logL > kMaxLogLen || d < 1 || d > (1 << logL)) return PM_EINVAL;
+  return make_plan_core(p, m, n, k, d, d, 0, std::min(1 << logL, 2 * d - 1), elem_bytes, logL,
+                        out);
+}
+
+static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
+                          int elem_bytes, int force_log, Plan* out) {
   if (!out) return PM_EINVAL;
   if (elem_bytes != 4 && elem_bytes != 8) return PM_EINVAL;
   if (m < 1 || n < 1 || k < 1 || da < 1 || db < 1 || lo < 0 || nout < 1) return PM_EINVAL;
@@ -214,7 +229,8 @@ int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int
   if (elem_bytes == 4 && p > 0xFFFFFFFFull) return PM_ERANGE;
   if (elem_bytes == 8 && p >= (1ull << 62)) return PM_ERANGE;
   const uint64_t need = std::max<uint64_t>((uint64_t)da + db - 1 - lo, (uint64_t)lo + nout);
-  const int logL = ceil_log2(need);
+  // a forced length computes A B mod (x^L - 1) (coefficients wrap)
+  const int logL = force_log >= 0 ? force_log : ceil_log2(need);
   if (logL > kMaxLogLen) return PM_EUNSUPPORTED;
   const uint64_t L = 1ull << logL;
   const uint64_t lim = 1ull << 32;
@@ -234,7 +250,9 @@ int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int
     P.q[0] = (uint32_t)p;
   } else {
     // Integer coefficients of the lifted product lie in
-    // [0, n * min(da, db) * (p-1)^2].
+    // [0, n * min(da, db) * (p-1)^2]; so do those of a cyclic product with
+    // da = db = d <= L, since a + b = c mod L has at most one solution b in
+    // [0, d) for each a.
     Big bound = big_mul(big_mul(big_from(p - 1), p - 1), (uint64_t)n * std::min(da, db));
     Big prod = big_from(1);
     P.mode = 1;

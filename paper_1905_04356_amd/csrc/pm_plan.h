@@ -92,6 +92,10 @@ int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out)
 int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
                     int elem_bytes, Plan* out);
 
+// Plan of A B mod (x^L - 1), L = 2^logL >= d (coefficients 0 .. min(L, 2d-1) - 1).
+int make_cyclic_plan(uint64_t p, int m, int n, int k, int d, int logL, int elem_bytes,
+                     Plan* out);
+
 // Pointwise kernel for an m x n by n x k product per point: 1 int8-MFMA, 0 VALU.
 int choose_pointwise(int m, int n, int k);
 

@@ -399,3 +399,33 @@ def test_mfma_centred_limbs_for_primes_above_0x7f7f7f7f(fill):
         A, B = tensors(p, m, n, k, d, seed=13)
     C = gpu_mul(p, A, B)
     assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
+
+
+@pytest.mark.parametrize("p,dtype,m,n,k,d", [
+    (P30, np.uint32, 3, 4, 2, 600),        # 2d-1 = 1199: 1024 points + a 175-coefficient top
+    (P31, np.uint32, 4, 4, 4, 700),
+    (P30, np.uint32, 2, 2, 2, 768),        # t = 511, the largest wrapped case at 2^10
+    (P30, np.uint32, 2, 2, 2, 769),        # t = 513: the plain 2048-point transform
+    (P32, np.uint32, 3, 3, 3, 600),        # CRT mode
+    ((1 << 61) - 1, np.uint64, 2, 2, 2, 1100),
+])
+def test_wrapped_lengths(p, dtype, m, n, k, d):
+    """Products with 2^j < 2d-1 <= 1.5 2^j: a cyclic product on 2^j points,
+    the top coefficients from a short window product, and the correction."""
+    full_check(p, m, n, k, d, seed=14, dtype=dtype)
+
+
+def test_wrapped_equals_plain_transforms():
+    p, m, n, k = P30, 16, 16, 16
+    for d in (1030, 1300, 1536, 2500):
+        A, B = tensors(p, m, n, k, d, seed=15)
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        wrapped = polymat.mul(p, tA, tB)
+        plain, = polymat.mul_batched(p, [tA], [tB])      # one product: plain transforms
+        torch.cuda.synchronize()
+        assert torch.equal(wrapped, plain), d
+    pairs = I.sample_pairs(15, m, k, 4)
+    rows = O.polymatmul_entries(p, A, B, pairs)
+    W = wrapped.cpu().numpy()
+    for s, (i, j) in enumerate(pairs):
+        assert np.array_equal(W[:, i, j].astype(np.uint64), rows[s])
