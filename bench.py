@@ -336,6 +336,44 @@ def bench_vdm(p=1000000007, seed=9, reps=10):
                         "evaluation on the matrix cores vs three-prime CRT", "runs": rows}
 
 
+def bench_wrap(p=998244353, seed=10, reps=10):
+    """Degrees where 2d - 1 lies just above a power of two: the wrapped form
+    (cyclic product on 2^j points, short product for the top coefficients,
+    correction) that pm_mul takes, against the plain 2^(j+1)-point transforms
+    (a one-product pm_mul_batched call), same operands, outputs compared."""
+    import torch
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for (m, n, k, d) in [(64, 64, 32, 1100), (64, 64, 32, 2100), (64, 64, 32, 2500)]:
+        A = I.polymat_torch(seed, 0, I.TENSOR_A, p, d, m, n, dev)
+        B = I.polymat_torch(seed, 0, I.TENSOR_B, p, d, n, k, dev)
+        ws = polymat.Workspace(dev)
+        ow = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=dev)
+        op = torch.empty_like(ow)
+
+        def timed(fn):
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        t_w = timed(lambda: polymat.mul(p, A, B, out=ow, workspace=ws, stream=stream))
+        t_p = timed(lambda: polymat.mul_batched(p, [A], [B], [op], workspace=ws, stream=stream))
+        rows.append({"m": m, "n": n, "k": k, "d": d, "wrapped_ms": t_w, "plain_ms": t_p,
+                     "outputs_equal": bool(torch.equal(ow, op))})
+        del A, B, ws, ow, op
+    return {"workload": f"products mod {p} with 2d - 1 just above a power of two", "runs": rows}
+
+
 def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
@@ -683,6 +721,8 @@ def main():
         out["newton"] = bench_newton()
         torch.cuda.empty_cache()
         out["vandermonde"] = bench_vdm()
+        torch.cuda.empty_cache()
+        out["wrapped_lengths"] = bench_wrap()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
         out["serving"] = bench_serving(args.serving_seconds)
