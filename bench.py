@@ -31,6 +31,8 @@ INT8_MFMA_PEAK_TOPS = 5000.0          # dense int8, 5.0 POP/s
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
 VALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # 39.3 T 32-bit lane-ops/s
 
+PROFILE_EVERY = 4        # kernel timing on every 4th step of the timed loop
+
 # 32-bit VALU operations of one radix-2 butterfly with canonical residues
 # (q may exceed 2^30, so no lazy reduction) and Shoup multiplication, whose
 # product a*w - floor(a*w'/2^32)*q mod 2^32 takes mul_hi, mul_lo and one
@@ -458,10 +460,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def summarize_profiles(root, steps_stats, steps_pmc, workload):
+def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
     """Turn rocprofv3 CSV output under `root` (st/: --kernel-trace --stats,
     f/ and w/: --pmc FETCH_SIZE / WRITE_SIZE of the benchmark, cf/ and cw/:
-    the same counters on the calibration copy) into profiles/ summaries."""
+    the same counters on the calibration copy) into profiles/ summaries.
+    Besides the --stats averages over every call (warm-up included), each
+    kernel's average over the dispatches of the timed steps (its last
+    steps_stats / (steps_stats + warmup_stats) calls, from the trace) is
+    the figure that bench.py's kernel timing measures."""
     import collections
     import csv
 
@@ -470,16 +476,25 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
         files = glob.glob(os.path.join(root, sub, f"*{name}*.csv"))
         return list(csv.DictReader(open(files[0]))) if files else []
 
+    total_steps = steps_stats + warmup_stats
+    trace = collections.defaultdict(list)
+    for r in rows("st", "kernel_trace"):
+        trace[r["Kernel_Name"]].append((int(r["Start_Timestamp"]),
+                                        int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     stats = rows("st", "kernel_stats")
     per_kind = collections.defaultdict(lambda: [0.0, 0])
     lines = []
     for r in stats:
         kd = kind_of(r["Name"])
-        lines.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+        calls = int(r["Calls"])
+        durs = [dn for _, dn in sorted(trace.get(r["Name"], []))]
+        timed = durs[len(durs) - len(durs) * steps_stats // total_steps:] if durs else []
+        avg_timed = sum(timed) / len(timed) / 1e3 if timed else float("nan")
+        lines.append((r["Name"], calls, float(r["AverageNs"]) / 1e3, avg_timed,
                       float(r["TotalDurationNs"]) / 1e6, kd))
-        if kd:
-            per_kind[kd][0] += float(r["TotalDurationNs"]) / 1e6
-            per_kind[kd][1] += int(r["Calls"])
+        if kd and timed:
+            per_kind[kd][0] += sum(timed) / 1e6
+            per_kind[kd][1] += len(timed)
 
     def counter(sub, cname):
         out = collections.defaultdict(float)
@@ -503,17 +518,22 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
         if kind_of(name) and wscale:
             traffic[kind_of(name)] += v * wscale / steps_pmc
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
-              f"python3 bench.py --steps {steps_stats} --warmup 2 --no-cpu-baseline --no-batched "
-              "--no-middle --no-pmbasis --serving-seconds 0")
+              f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
+              "--no-batched --no-middle --no-pmbasis --serving-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
-          "| kernel | calls | avg us | total ms | kind |", "|---|---|---|---|---|"]
-    for name, calls, avg, tot, kd in sorted(lines, key=lambda x: -x[3]):
-        md.append(f"| `{name}` | {calls} | {avg:.1f} | {tot:.3f} | {kd} |")
-    md += ["", f"Per benchmark step ({steps_stats} timed + 2 warm-up steps profiled):", "",
+          f"`avg us` is rocprofv3's --stats average over all calls ({warmup_stats} warm-up "
+          f"and {steps_stats} timed steps); `timed avg us` averages, from the kernel trace, "
+          f"only the dispatches of the {steps_stats} timed steps, after the clocks have "
+          "ramped up.", "",
+          "| kernel | calls | avg us | timed avg us | total ms | kind |",
+          "|---|---|---|---|---|---|"]
+    for name, calls, avg, avg_t, tot, kd in sorted(lines, key=lambda x: -x[4]):
+        md.append(f"| `{name}` | {calls} | {avg:.1f} | {avg_t:.1f} | {tot:.3f} | {kd} |")
+    md += ["", f"Per timed step ({steps_stats} steps):", "",
            "| kind | device ms per step |", "|---|---|"]
     for kd, (tot, calls) in sorted(per_kind.items()):
-        md.append(f"| {kd} | {tot / (steps_stats + 2):.4f} |")
+        md.append(f"| {kd} | {tot / steps_stats:.4f} |")
     md += ["", "## HBM traffic (rocprofv3 --pmc)", "",
            "Commands:", "", "```"]
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
@@ -536,7 +556,7 @@ def summarize_profiles(root, steps_stats, steps_pmc, workload):
     with open(os.path.join(ROOT, "profiles", f"{workload}_traffic.json"), "w") as f:
         json.dump({"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
                    "bytes_per_step": dict(traffic),
-                   "device_ms_per_step": {k: v[0] / (steps_stats + 2)
+                   "device_ms_per_step": {k: v[0] / steps_stats
                                           for k, v in per_kind.items()}}, f, indent=1)
     print("wrote profiles for", workload)
 
@@ -602,7 +622,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -621,7 +641,7 @@ def main():
         calibration_copy()
         return
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, 10, 3, args.workload)
+        summarize_profiles(args.summarize_profiles, 20, 100, 3, args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every product on a single "
@@ -652,18 +672,23 @@ def main():
         polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
     torch.cuda.synchronize()
 
+    # Kernel durations come from the dispatch events of every
+    # PROFILE_EVERY-th step of the timed loop (each timed launch costs a few
+    # microseconds of dispatch work, so not every step carries them).
     Bd.pm_profile_begin()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        Bd.pm_profile_pause(i % PROFILE_EVERY != 0)
         polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kstats = Bd.pm_profile_end()
+    timed_steps = len(range(0, args.steps, PROFILE_EVERY))
 
     wall = t1 - t0
     work = float(m) * n * k * d
@@ -673,9 +698,9 @@ def main():
         if launches == 0:
             continue
         byts, ops = kernel_work(kind, plan, p, m, n, k, d, eb)
-        sec = ms / 1e3 / args.steps           # device seconds per product
-        kernels[kind] = {"ms_per_step": ms / args.steps, "launches_per_step":
-                         launches / args.steps, "algorithmic_bytes": byts,
+        sec = ms / 1e3 / timed_steps          # device seconds per product
+        kernels[kind] = {"ms_per_step": ms / timed_steps, "launches_per_step":
+                         launches / timed_steps, "algorithmic_bytes": byts,
                          "ops": ops}
         kernels[kind]["roofline"] = roofline_for(kind, byts, ops, sec, plan)
     traffic = load_traffic(args.workload)
@@ -706,6 +731,8 @@ def main():
                    "pointwise": "mfma_int8" if plan.pointwise == 1 else "valu"},
         "roofline": roof,
         "kernels": kernels,
+        "kernel_timing": f"dispatch start/stop events on {timed_steps} of the {args.steps} "
+                         f"timed steps (every {PROFILE_EVERY}th)",
     }
     del tA, tB, tC, ws
     torch.cuda.empty_cache()

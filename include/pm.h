@@ -260,13 +260,17 @@ pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count,
                             void* workspace, void* stream);
 
 /* Kernel timing for measurement.  Between pm_profile_begin and
- * pm_profile_end, every kernel the library launches (from any thread) is
- * bracketed by two HIP events recorded on the stream it is launched on;
- * pm_profile_end waits for those events and returns, per kernel kind, the
- * summed device time and the launch count.  Kinds (index into the arrays):
- * 0 forward transform, 1 pointwise products, 2 inverse transform,
- * 3 Chinese remaindering, 4 batched persistent kernel, 5 evaluation and
- * 6 interpolation by Vandermonde products.  Returns PM_EDEVICE if
+ * pm_profile_end, every kernel the library launches (from any thread)
+ * carries a start and a stop HIP event that its own dispatch fills
+ * (hipExtLaunchKernel, on the stream it is launched on), so timing adds no
+ * work between kernels; pm_profile_end waits for those events and returns,
+ * per kernel kind, the summed device time and the launch count.  Kinds
+ * (index into the arrays): 0 forward transform, 1 pointwise products,
+ * 2 inverse transform, 3 Chinese remaindering, 5 evaluation and
+ * 6 interpolation by Vandermonde products; 4 is a whole batched call of
+ * more than two products, timed by an event pair around it (an eager one
+ * also reports its phase kernels under 0-3; a replayed graph does not).
+ * Launches inside a stream capture are not timed.  Returns PM_EDEVICE if
  * an event could not be created or read; PM_EINVAL if out is NULL. */
 #define PM_KERNEL_KINDS 8
 typedef struct pm_kernel_stats {
@@ -275,6 +279,11 @@ typedef struct pm_kernel_stats {
 } pm_kernel_stats;
 pm_status pm_profile_begin(void);
 pm_status pm_profile_end(pm_kernel_stats* out);
+/* Pause (paused != 0) or resume timing inside a pm_profile_begin /
+ * pm_profile_end session without dropping what it has recorded, e.g. to
+ * time every n-th step of a loop (each timed launch adds a few
+ * microseconds of dispatch work).  Returns PM_EINVAL outside a session. */
+pm_status pm_profile_pause(int32_t paused);
 
 /* Wait for `stream` and report any device error raised by earlier calls. */
 pm_status pm_sync(void* stream);

@@ -28,7 +28,8 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_eval_u64", "pm_check_residues", "pm_profile_begin", "pm_profile_end",
            "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
            "pm_matinv_host", "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
-           "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32")
+           "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
+           "pm_profile_pause")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
@@ -107,13 +108,15 @@ def lib():
     L.pm_mul_vdm_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
+    L.pm_profile_pause.argtypes = [i32]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
                  "pm_eval_bytes", "pm_eval_u32", "pm_eval_u64", "pm_middle_plan",
                  "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host",
                  "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
-                 "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32"):
+                 "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
+                 "pm_profile_pause"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -192,6 +195,10 @@ def pm_sync(stream) -> None:
 
 def pm_profile_begin() -> None:
     _check(lib().pm_profile_begin(), "pm_profile_begin")
+
+
+def pm_profile_pause(paused: bool) -> None:
+    _check(lib().pm_profile_pause(1 if paused else 0), "pm_profile_pause")
 
 
 def pm_profile_end() -> dict:

@@ -838,7 +838,7 @@ int enqueue_batch(const BatchBuild& B, const void* host_src, const BatchLayout& 
   const BatchSeg* dsegs = (const BatchSeg*)(ws + lay.seg_off);
   static const int kind_of_phase[kBatchPhases] = {K_NTT_FWD, K_NTT_FWD, K_POINTWISE,
                                                   K_NTT_INV, K_NTT_INV, K_CRT};
-  KernelTimer kt(K_BATCHED, s);
+  KernelTimer kt(K_BATCHED, s, true);
   for (const BatchGroup& G : B.groups) {
     KernelTimer kp(kind_of_phase[G.phase], s);
     if (launch_batch_phase(G.phase, dprods, dsegs + G.first_seg, (int)G.nseg,
@@ -960,7 +960,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   if (e && e->exec) {
     e->tick = ++g_tick;
     e->last = s;
-    KernelTimer kt(K_BATCHED, s);
+    KernelTimer kt(K_BATCHED, s, true);
     return hipGraphLaunch(e->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
   }
   BatchBuild B;
@@ -1022,7 +1022,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   }
   e->tick = ++g_tick;
   e->last = s;
-  KernelTimer kt(K_BATCHED, s);
+  KernelTimer kt(K_BATCHED, s, true);
   return hipGraphLaunch(e->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 

@@ -19,6 +19,7 @@
 #include "pm_crt_dev.h"
 #include "pm_ntt_dev.h"
 #include "pm_pointwise_dev.h"
+#include "pm_profile.h"
 
 namespace pm {
 
@@ -141,9 +142,8 @@ static int launch_phase_t(const ProductLaunches* prods, const BatchSeg* segs, in
       (const void*)batch_kernel<PHASE, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
       160 * 1024);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((batch_kernel<PHASE, NT>), dim3(ntiles), dim3(NT), lds, s, prods, segs,
+  return launch((batch_kernel<PHASE, NT>), dim3(ntiles), dim3(NT), lds, s, prods, segs,
                      nseg);
-  return hipGetLastError();
 }
 
 int launch_batch_phase(int phase, const ProductLaunches* prods, const BatchSeg* segs, int nseg,

@@ -1,6 +1,7 @@
 // pm_crt.hip -- single-product Chinese remaindering kernel (device work in
 // pm_crt_dev.h) and the opt-in residue check.
 #include "pm_crt_dev.h"
+#include "pm_profile.h"
 
 namespace pm {
 
@@ -15,10 +16,9 @@ int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s) {
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
   if (out_elem_bytes == 8)
-    hipLaunchKernelGGL(crt_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return launch(crt_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(crt_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+    return launch(crt_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
 template <typename T>
@@ -38,12 +38,11 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
   if (blocks > 16384) blocks = 16384;
   if (blocks == 0) blocks = 1;
   if (elem_bytes == 8)
-    hipLaunchKernelGGL(check_residues_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       p, (const uint64_t*)x, count, counter);
+    return launch(check_residues_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, p,
+                  (const uint64_t*)x, count, counter);
   else
-    hipLaunchKernelGGL(check_residues_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       p, (const uint32_t*)x, count, counter);
-  return hipGetLastError();
+    return launch(check_residues_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, p,
+                  (const uint32_t*)x, count, counter);
 }
 
 // Coefficients of A B from A B mod (x^L - 1): rows L .. L + t - 1 of C hold
@@ -65,12 +64,11 @@ int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_by
   if (blocks > 4096) blocks = 4096;
   if (blocks == 0) return hipSuccess;
   if (elem_bytes == 8)
-    hipLaunchKernelGGL(unwrap_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (uint64_t*)C, count, off, p);
+    return launch(unwrap_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                  (uint64_t*)C, count, off, p);
   else
-    hipLaunchKernelGGL(unwrap_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (uint32_t*)C, count, off, p);
-  return hipGetLastError();
+    return launch(unwrap_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                  (uint32_t*)C, count, off, p);
 }
 
 }  // namespace pm

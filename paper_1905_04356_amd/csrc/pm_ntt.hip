@@ -3,6 +3,7 @@
 // The device work of each workgroup lives in pm_ntt_dev.h; this file wraps
 // it in one kernel per tile kind and launches one product's transforms.
 #include "pm_ntt_dev.h"
+#include "pm_profile.h"
 
 namespace pm {
 
@@ -91,8 +92,7 @@ static int launch_lds(K kernel, const NttLaunch& a, int nprimes, int zblocks, hi
   }
   const int EB = 1 << a.eb_log;
   dim3 grid((a.E + EB - 1) / EB, nprimes, zblocks);
-  hipLaunchKernelGGL(kernel, grid, dim3(nt), lds, s, a);
-  return hipGetLastError();
+  return launch(kernel, grid, dim3(nt), lds, s, a);
 }
 
 template <typename K>
@@ -100,8 +100,7 @@ static int launch_col(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) 
   const uint64_t items = col_items(a);
   uint64_t blocks = (items + kColNT - 1) / kColNT;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)blocks, nprimes), dim3(kColNT), 0, s, a);
-  return hipGetLastError();
+  return launch(kernel, dim3((unsigned)blocks, nprimes), dim3(kColNT), 0, s, a);
 }
 
 template <typename TIn, bool REDUCE>

@@ -1,6 +1,7 @@
 // pm_pointwise.hip -- single-product pointwise kernels and launchers (the
 // per-workgroup work is in pm_pointwise_dev.h).
 #include "pm_pointwise_dev.h"
+#include "pm_profile.h"
 
 namespace pm {
 
@@ -20,16 +21,14 @@ int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   const size_t lds = sizeof(uint32_t) * ((size_t)a.m * a.n + (size_t)a.n * a.k);
   if (lds > 128 * 1024) {
     // operands too large to stage: read them from global memory (L2)
-    hipLaunchKernelGGL(pointwise_valu_kernel<false>, dim3(a.L, nprimes), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return launch(pointwise_valu_kernel<false>, dim3(a.L, nprimes), dim3(256), 0, s, a);
   }
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)pointwise_valu_kernel<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(pointwise_valu_kernel<true>, dim3(a.L, nprimes), dim3(256), lds, s, a);
-  return hipGetLastError();
+  return launch(pointwise_valu_kernel<true>, dim3(a.L, nprimes), dim3(256), lds, s, a);
 }
 
 
@@ -44,14 +43,12 @@ int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s) 
   const size_t lds = pointwise_mfma_lds(a.m, a.n, a.k);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds <= 64 * 1024) {
-    hipLaunchKernelGGL(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
-    return hipGetLastError();
+    return launch(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
   }
   hipError_t e = hipFuncSetAttribute((const void*)pointwise_mfma_kernel<512>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pointwise_mfma_kernel<512>, dim3(a.L, nprimes), dim3(512), lds, s, a);
-  return hipGetLastError();
+  return launch(pointwise_mfma_kernel<512>, dim3(a.L, nprimes), dim3(512), lds, s, a);
 }
 
 }  // namespace pm

@@ -1,6 +1,7 @@
 // pm_profile.cpp -- optional per-kernel device timing with HIP events.
 #include "pm_profile.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -17,33 +18,55 @@ struct Rec {
   int kind;
   hipEvent_t a, b;
 };
-std::atomic<int> g_on{0};
+std::atomic<int> g_on{0};  // 0 off, 1 timing, 2 paused
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 bool g_failed = false;
+thread_local int t_kind = -1;  // kind of the innermost per-launch scope
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// timing-only events: without the system-scope fence, completing one does
+// not write back and invalidate the caches
+bool make_pair(hipEvent_t* a, hipEvent_t* b) {
+  if (hipEventCreateWithFlags(a, hipEventDisableSystemFence) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(b, hipEventDisableSystemFence) != hipSuccess) {
+    (void)hipEventDestroy(*a);
+    return false;
+  }
+  return true;
+}
+
+void failed() {
+  std::lock_guard<std::mutex> l(g_mu);
+  g_failed = true;
+}
 }  // namespace
 
-bool profiling() { return g_on.load(std::memory_order_relaxed) != 0; }
+bool profiling() { return g_on.load(std::memory_order_relaxed) == 1; }
 
-KernelTimer::KernelTimer(int kind, hipStream_t s) : kind_(kind), s_(s) {
-  if (!profiling()) return;
-  // no timing inside a stream capture: the events would become graph nodes
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
-  if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
-    std::lock_guard<std::mutex> l(g_mu);
-    g_failed = true;
+KernelTimer::KernelTimer(int kind, hipStream_t s, bool scope_events)
+    : kind_(kind), prev_kind_(t_kind), s_(s) {
+  t_kind = scope_events ? -1 : kind;
+  if (!scope_events || !profiling() || capturing(s_)) return;
+  if (!make_pair(&a_, &b_)) {
+    failed();
     return;
   }
   if (hipEventRecord(a_, s_) != hipSuccess) {
-    std::lock_guard<std::mutex> l(g_mu);
-    g_failed = true;
+    (void)hipEventDestroy(a_);
+    (void)hipEventDestroy(b_);
+    failed();
     return;
   }
   armed_ = true;
 }
 
 KernelTimer::~KernelTimer() {
+  t_kind = prev_kind_;
   if (!armed_) return;
   std::lock_guard<std::mutex> l(g_mu);
   if (hipEventRecord(b_, s_) != hipSuccess) {
@@ -51,6 +74,31 @@ KernelTimer::~KernelTimer() {
     return;
   }
   g_recs.push_back(Rec{kind_, a_, b_});
+}
+
+hipError_t launch_kernel(const void* fn, dim3 grid, dim3 block, void** args, size_t lds,
+                         hipStream_t s) {
+  hipError_t e;
+  hipEvent_t a, b;
+  bool timed = t_kind >= 0 && profiling() && !capturing(s);
+  if (timed && !make_pair(&a, &b)) {
+    failed();
+    timed = false;
+  }
+  if (timed) {
+    e = hipExtLaunchKernel(fn, grid, block, args, lds, s, a, b, 0);
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> l(g_mu);
+      g_recs.push_back(Rec{t_kind, a, b});
+    } else {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } else {
+    e = hipLaunchKernel(fn, grid, block, args, lds, s);
+  }
+  const hipError_t last = hipGetLastError();
+  return e != hipSuccess ? e : last;
 }
 
 }  // namespace pm
@@ -62,6 +110,13 @@ pm_status pm_profile_begin(void) {
   pm::g_recs.clear();
   pm::g_failed = false;
   pm::g_on.store(1);
+  return PM_OK;
+}
+
+pm_status pm_profile_pause(int32_t paused) {
+  std::lock_guard<std::mutex> l(pm::g_mu);
+  if (pm::g_on.load() == 0) return PM_EINVAL;
+  pm::g_on.store(paused ? 2 : 1);
   return PM_OK;
 }
 

@@ -15,6 +15,7 @@
 // bias q 7 K 2^16 keeps the weighted sum in [0, q 2^32) for K <= 4096.
 #include "pm_pointwise_dev.h"
 #include "pm_vdm.h"
+#include "pm_profile.h"
 
 namespace pm {
 
@@ -124,10 +125,9 @@ int launch_gemm_modp(const GemmLaunch& g, hipStream_t s) {
     return hipErrorInvalidValue;
   const dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
   if (g.q <= 0x7F7F7F7Fu)
-    hipLaunchKernelGGL(gemm_modp_kernel<false>, grid, dim3(256), 0, s, g);
+    return launch(gemm_modp_kernel<false>, grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL(gemm_modp_kernel<true>, grid, dim3(256), 0, s, g);
-  return hipGetLastError();
+    return launch(gemm_modp_kernel<true>, grid, dim3(256), 0, s, g);
 }
 
 }  // namespace pm

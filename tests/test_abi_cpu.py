@@ -187,3 +187,17 @@ def test_middle_batched_workspace_and_checks():
     bad = B.windows_array([(4, 4, 4, 16, 32, 40, 16, A, Bp, C)])   # window past the product
     with pytest.raises(B.PmError):
         B.pm_middle_batched_workspace_bytes(998244353, bad, 1, 4)
+
+
+def test_profile_session_rules():
+    """pm_profile_pause works only inside a begin/end session; an empty
+    session reports nothing (no device calls are made)."""
+    lib = B.lib()
+    assert lib.pm_profile_pause(1) == B.PM_EINVAL
+    B.pm_profile_begin()
+    B.pm_profile_pause(True)
+    B.pm_profile_pause(False)
+    stats = B.pm_profile_end()
+    assert set(stats) == set(B.KERNEL_KINDS)
+    assert all(ms == 0.0 and n == 0 for ms, n in stats.values())
+    assert lib.pm_profile_pause(0) == B.PM_EINVAL

@@ -429,3 +429,29 @@ def test_wrapped_equals_plain_transforms():
     W = wrapped.cpu().numpy()
     for s, (i, j) in enumerate(pairs):
         assert np.array_equal(W[:, i, j].astype(np.uint64), rows[s])
+
+
+def test_kernel_timing_counts_only_unpaused_launches():
+    """Timed launches carry dispatch events; paused ones are not counted, and
+    timing changes no result."""
+    p, m, n, k, d = P31, 16, 16, 8, 4096
+    A, B = tensors(p, m, n, k, d, seed=16)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = polymat.mul(p, tA, tB)
+    Bd.pm_profile_begin()
+    C1 = polymat.mul(p, tA, tB)
+    one = Bd.pm_profile_end()
+    Bd.pm_profile_begin()
+    C2 = polymat.mul(p, tA, tB)
+    Bd.pm_profile_pause(True)
+    C3 = polymat.mul(p, tA, tB)
+    Bd.pm_profile_pause(False)
+    C4 = polymat.mul(p, tA, tB)
+    two = Bd.pm_profile_end()
+    torch.cuda.synchronize()
+    for C in (C1, C2, C3, C4):
+        assert torch.equal(C, ref)
+    for kind in ("ntt_fwd", "pointwise", "ntt_inv"):
+        assert one[kind][1] >= 1 and one[kind][0] > 0.0, kind
+        assert two[kind][1] == 2 * one[kind][1], kind
+    assert one["crt"][1] == 0 and one["batched"][1] == 0
