@@ -146,11 +146,13 @@ def cpu_baseline(p, A, B, m, n, k, d, target_s):
     t0 = time.perf_counter()
     O.polymatmul_entries(p, A, B, pairs[:count], threads=threads)
     dt = time.perf_counter() - t0
+    macs = count * n * d * d            # schoolbook: d^2 coefficient MACs per (i, l, j)
     return {"value": count * n * d / dt, "unit": "coefficient-MAC/s (m*n*k*d per product)",
             "cores": threads, "kind": "oracle",
             "sample": f"{count} of {m * k} whole output entries (all {2 * d - 1} coefficients, "
                       f"schoolbook) of the same product, {dt:.2f} s wall",
-            "seconds": dt}
+            "seconds": dt, "schoolbook_mac_per_s": macs / dt,
+            "extrapolated_full_product_s": dt * (m * k) / count}
 
 
 def bench_middle(steps=10, warmup=2, seed=6, p=2013265921, m=64, n=64, k=32, c=4096,
@@ -690,6 +692,22 @@ def main():
     kstats = Bd.pm_profile_end()
     timed_steps = len(range(0, args.steps, PROFILE_EVERY))
 
+    # Distribution of single-step device times, from a separate loop of the
+    # same length with an event between consecutive steps (so these events
+    # stay out of the timed loop above).
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
+        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    dist = {"median": per_step[len(per_step) // 2] if len(per_step) % 2 else
+            0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2]),
+            "min": per_step[0],
+            "p90": per_step[max(0, -(-9 * len(per_step) // 10) - 1)],   # nearest rank
+            "steps": args.steps}
+
     wall = t1 - t0
     work = float(m) * n * k * d
     value = work * args.steps / wall
@@ -719,6 +737,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "device_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "device_ms_per_step_dist": dist,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -149,13 +149,14 @@ static int launch_phase_t(const ProductLaunches* prods, const BatchSeg* segs, in
 int launch_batch_phase(int phase, const ProductLaunches* prods, const BatchSeg* segs, int nseg,
                        uint32_t ntiles, size_t lds, hipStream_t s) {
   // The transform tiles are written for kBatchNT threads; pointwise tiles
-  // that fit in 64 KiB of LDS run with 256 threads so more of them share a CU
-  // (as in the single-product launch).
+  // with small limb planes run with 256 threads so more of them share a CU
+  // (the single-product launch's rule).
   switch (phase) {
     case 0: return launch_phase_t<0, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 1: return launch_phase_t<1, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 2:
-      if (lds <= 64 * 1024) return launch_phase_t<2, 256>(prods, segs, nseg, ntiles, lds, s);
+      if (lds <= pointwise_small_lds())
+        return launch_phase_t<2, 256>(prods, segs, nseg, ntiles, lds, s);
       return launch_phase_t<2, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 3: return launch_phase_t<3, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 4: return launch_phase_t<4, kBatchNT>(prods, segs, nseg, ntiles, lds, s);

@@ -3,6 +3,8 @@
 #include "pm_pointwise_dev.h"
 #include "pm_profile.h"
 
+#include <stdlib.h>
+
 namespace pm {
 
 template <bool STAGED>
@@ -37,12 +39,23 @@ size_t pointwise_mfma_lds(int m, int n, int k) {
   return 4 * (mp + kp) * (np + 16);
 }
 
-// Up to 64 KiB of limb planes: 256 threads, several workgroups per CU; larger
-// shapes take most of the LDS, so one workgroup of 512 threads per CU.
+// Up to 44 KiB of limb planes: 256 threads, so that several workgroups share
+// a CU.  Above it, 512 threads: each thread stages half as many items and
+// so waits for fewer load round trips (measured on single products: 128x64x8
+// 44 -> 40 us, 64x128x32 70 -> 53 us, 128x32x64 109 -> 78 us, while 41 KiB
+// and below lose).  Tuning knob PM_TUNE_PW_SMALL_LDS (bytes).
+size_t pointwise_small_lds() {
+  static const size_t v = [] {
+    const char* e = getenv("PM_TUNE_PW_SMALL_LDS");
+    return e && *e ? (size_t)strtoull(e, nullptr, 10) : (size_t)44 * 1024;
+  }();
+  return v;
+}
+
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   const size_t lds = pointwise_mfma_lds(a.m, a.n, a.k);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds <= 64 * 1024) {
+  if (lds <= pointwise_small_lds()) {
     return launch(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
   }
   hipError_t e = hipFuncSetAttribute((const void*)pointwise_mfma_kernel<512>,
