@@ -467,9 +467,11 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
     f/ and w/: --pmc FETCH_SIZE / WRITE_SIZE of the benchmark, cf/ and cw/:
     the same counters on the calibration copy) into profiles/ summaries.
     Besides the --stats averages over every call (warm-up included), each
-    kernel's average over the dispatches of the timed steps (its last
-    steps_stats / (steps_stats + warmup_stats) calls, from the trace) is
-    the figure that bench.py's kernel timing measures."""
+    kernel's average over the dispatches of the steady-state steps (the
+    steps_stats timed steps and the steps_stats steps of the per-step
+    distribution loop after them: its last 2 steps_stats / (warmup_stats +
+    2 steps_stats) calls, from the trace) is the figure that bench.py's
+    kernel timing measures."""
     import collections
     import csv
 
@@ -478,7 +480,8 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
         files = glob.glob(os.path.join(root, sub, f"*{name}*.csv"))
         return list(csv.DictReader(open(files[0]))) if files else []
 
-    total_steps = steps_stats + warmup_stats
+    total_steps = warmup_stats + 2 * steps_stats    # warm-up, timed, distribution loop
+    steady_steps = 2 * steps_stats
     trace = collections.defaultdict(list)
     for r in rows("st", "kernel_trace"):
         trace[r["Kernel_Name"]].append((int(r["Start_Timestamp"]),
@@ -490,7 +493,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
         kd = kind_of(r["Name"])
         calls = int(r["Calls"])
         durs = [dn for _, dn in sorted(trace.get(r["Name"], []))]
-        timed = durs[len(durs) - len(durs) * steps_stats // total_steps:] if durs else []
+        timed = durs[len(durs) - len(durs) * steady_steps // total_steps:] if durs else []
         avg_timed = sum(timed) / len(timed) / 1e3 if timed else float("nan")
         lines.append((r["Name"], calls, float(r["AverageNs"]) / 1e3, avg_timed,
                       float(r["TotalDurationNs"]) / 1e6, kd))
@@ -512,30 +515,34 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
     fscale = cal_bytes / cf if cf else None
     wscale = cal_bytes / cw if cw else None
     fetch, write = counter("f", "FETCH_SIZE"), counter("w", "WRITE_SIZE")
+    # the counter runs: 1 warm-up step, steps_pmc - 1 timed steps and as many
+    # distribution-loop steps
+    pmc_total_steps = 1 + 2 * (steps_pmc - 1)
     traffic = collections.defaultdict(float)
     for name, v in fetch.items():
         if kind_of(name) and fscale:
-            traffic[kind_of(name)] += v * fscale / steps_pmc
+            traffic[kind_of(name)] += v * fscale / pmc_total_steps
     for name, v in write.items():
         if kind_of(name) and wscale:
-            traffic[kind_of(name)] += v * wscale / steps_pmc
+            traffic[kind_of(name)] += v * wscale / pmc_total_steps
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
               "--no-batched --no-middle --no-pmbasis --serving-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           f"`avg us` is rocprofv3's --stats average over all calls ({warmup_stats} warm-up "
-          f"and {steps_stats} timed steps); `timed avg us` averages, from the kernel trace, "
-          f"only the dispatches of the {steps_stats} timed steps, after the clocks have "
-          "ramped up.", "",
+          f"steps, {steps_stats} timed steps and the {steps_stats} steps of bench.py's "
+          "per-step distribution loop); `timed avg us` averages, from the kernel trace, only "
+          f"the dispatches of the last {steady_steps} steps, after the clocks have ramped up.",
+          "",
           "| kernel | calls | avg us | timed avg us | total ms | kind |",
           "|---|---|---|---|---|---|"]
     for name, calls, avg, avg_t, tot, kd in sorted(lines, key=lambda x: -x[4]):
         md.append(f"| `{name}` | {calls} | {avg:.1f} | {avg_t:.1f} | {tot:.3f} | {kd} |")
-    md += ["", f"Per timed step ({steps_stats} steps):", "",
+    md += ["", f"Per steady-state step (last {steady_steps} steps):", "",
            "| kind | device ms per step |", "|---|---|"]
     for kd, (tot, calls) in sorted(per_kind.items()):
-        md.append(f"| {kd} | {tot / steps_stats:.4f} |")
+        md.append(f"| {kd} | {tot / steady_steps:.4f} |")
     md += ["", "## HBM traffic (rocprofv3 --pmc)", "",
            "Commands:", "", "```"]
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
@@ -558,7 +565,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
     with open(os.path.join(ROOT, "profiles", f"{workload}_traffic.json"), "w") as f:
         json.dump({"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
                    "bytes_per_step": dict(traffic),
-                   "device_ms_per_step": {k: v[0] / steps_stats
+                   "device_ms_per_step": {k: v[0] / steady_steps
                                           for k, v in per_kind.items()}}, f, indent=1)
     print("wrote profiles for", workload)
 

@@ -677,10 +677,13 @@ struct HostSeg {
   uint32_t lds;    // bytes of LDS a tile needs
 };
 
-// LDS classes: tiles of one phase are launched in up to four groups so that
-// small tiles are not held to the occupancy of the largest.
-constexpr int kLdsClasses = 4;
-static const uint32_t kLdsClassMax[kLdsClasses] = {16 * 1024, 40 * 1024, 80 * 1024, 160 * 1024};
+// LDS classes: tiles of one phase are launched in groups so that small tiles
+// are not held to the occupancy of the largest.  Class c holds footprints up
+// to 160 KiB / n_c (rounded down to 256 bytes) for n_c = 10, 8, 7, 6, 5, 4,
+// 3, 2, 1 workgroups per CU.
+constexpr int kLdsClasses = 9;
+static const uint32_t kLdsClassMax[kLdsClasses] = {16384, 20480, 23296, 27136, 32768,
+                                                   40960, 54528, 81920, 163840};
 int lds_class(uint32_t bytes) {
   for (int c = 0; c < kLdsClasses; ++c)
     if (bytes <= kLdsClassMax[c]) return c;
