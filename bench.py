@@ -462,7 +462,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
+def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out_dir=None):
     """Turn rocprofv3 CSV output under `root` (st/: --kernel-trace --stats,
     f/ and w/: --pmc FETCH_SIZE / WRITE_SIZE of the benchmark, cf/ and cw/:
     the same counters on the calibration copy) into profiles/ summaries.
@@ -559,10 +559,11 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload):
            "|---|---|"]
     for kd, b in sorted(traffic.items()):
         md.append(f"| {kd} | {b / 1e6:.1f} MB |")
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", f"{workload}_kernels.md"), "w") as f:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"{workload}_kernels.md"), "w") as f:
         f.write("\n".join(md) + "\n")
-    with open(os.path.join(ROOT, "profiles", f"{workload}_traffic.json"), "w") as f:
+    with open(os.path.join(out_dir, f"{workload}_traffic.json"), "w") as f:
         json.dump({"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
                    "bytes_per_step": dict(traffic),
                    "device_ms_per_step": {k: v[0] / steady_steps
