@@ -65,7 +65,8 @@ __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, ui
 template <bool DIF>
 __device__ __forceinline__ void block_v(const NttLaunch& a, int prime, int x, int z,
                                         uint32_t* lds) {
-  if (a.vec == 4) block_tile<DIF, 4, kBatchNT, 2>(a, prime, x, z, lds);
+  if (a.reg_kind) block_tile_reg_kind<DIF, kBatchNT>(a, prime, x, z, lds);
+  else if (a.vec == 4) block_tile<DIF, 4, kBatchNT, 2>(a, prime, x, z, lds);
   else if (a.vec == 2) block_tile<DIF, 2, kBatchNT, 2>(a, prime, x, z, lds);
   else block_tile<DIF, 1, kBatchNT, 2>(a, prime, x, z, lds);
 }

@@ -31,6 +31,9 @@ struct NttLaunch {
   int vec;                   // residues per global load/store (1, 2, 4)
   int col_vec;               // column pass: consecutive entries per item (1, 2, 4)
   int blk_pitch;             // block step: LDS words per position (>= 2^eb_log, 4 | pitch)
+  int reg_kind;              // block step: 0 LDS-resident tile; 1..5 register-resident
+                             // tile with block passes {3,3,3}, {4,3}, {4,4}, {4,3,3},
+                             // {4,4,3} (set for the thread count that runs the step)
   int lds_stride;            // 32-bit words between entries in LDS
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers

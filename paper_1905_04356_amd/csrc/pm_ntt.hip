@@ -2,6 +2,7 @@
 //
 // The device work of each workgroup lives in pm_ntt_dev.h; this file wraps
 // it in one kernel per tile kind and launches one product's transforms.
+#include "pm_batch.h"
 #include "pm_ntt_dev.h"
 #include "pm_profile.h"
 
@@ -23,6 +24,19 @@ template <bool DIF, int V, int NT>
 __global__ __launch_bounds__(NT, 4) void ntt_block_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];
   block_tile<DIF, V, NT>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
+}
+
+template <bool DIF, int NT, int PT>
+__global__ __launch_bounds__(NT, 4) void ntt_block_reg_kernel(NttLaunch a) {
+  extern __shared__ uint32_t lds[];
+  block_tile_reg<DIF, NT, PT>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
+}
+
+template <bool DIF, int NT, int PT, int R1, int R2, int R3>
+__global__ __launch_bounds__(NT, 4) void ntt_block_regc_kernel(NttLaunch a) {
+  extern __shared__ uint32_t lds[];
+  block_tile_regc<DIF, NT, PT, R1, R2, R3>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x),
+                                           blockIdx.z, lds);
 }
 
 template <typename TIn, bool REDUCE, int r>
@@ -75,6 +89,10 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   const int B = 1 << a->blk_log;
   a->lds_stride = B + (B >> 5) + 1;
   a->blk_pitch = ((1 << eb) + 3) / 4 * 4 + ntt_tune().blk_pad;
+  // the register tile, for the threads that run the block step: kBatchNT in
+  // the batched phase kernels, blk_nt in the single-product kernel
+  const int nt_log = batched ? (kBatchNT == 512 ? 9 : 8) : (T.blk_nt == 512 ? 9 : 8);
+  a->reg_kind = T.reg_tile ? reg_kind_of(*a, nt_log) : 0;
 }
 
 static size_t lds_bytes(const NttLaunch& a) {
@@ -121,10 +139,26 @@ static int launch_col_inv_r(const NttLaunch& a, int nprimes, hipStream_t s) {
   }
 }
 
+// The register-resident block step of a launch with reg_kind set.
+template <bool DIF, int NT>
+static int launch_reg(const NttLaunch& a, int nprimes, int zb, hipStream_t s, size_t lds) {
+  switch (a.reg_kind) {
+    case 1: return launch_lds(ntt_block_regc_kernel<DIF, NT, 8, 3, 3, 3>, a, nprimes, zb, s, lds, NT);
+    case 2: return launch_lds(ntt_block_regc_kernel<DIF, NT, 16, 4, 3, 0>, a, nprimes, zb, s, lds, NT);
+    case 3: return launch_lds(ntt_block_regc_kernel<DIF, NT, 16, 4, 4, 0>, a, nprimes, zb, s, lds, NT);
+    case 4: return launch_lds(ntt_block_regc_kernel<DIF, NT, 16, 4, 3, 3>, a, nprimes, zb, s, lds, NT);
+    case 5: return launch_lds(ntt_block_regc_kernel<DIF, NT, 16, 4, 4, 3>, a, nprimes, zb, s, lds, NT);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <bool DIF>
 static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
   const int zb = 1 << a.split;
   const size_t lds = block_lds_bytes(a);
+  if (a.reg_kind)
+    return ntt_tune().blk_nt == 256 ? launch_reg<DIF, 256>(a, nprimes, zb, s, lds)
+                                    : launch_reg<DIF, kNT>(a, nprimes, zb, s, lds);
   if (ntt_tune().blk_nt == 256) {
     if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4, 256>, a, nprimes, zb, s, lds, 256);
     if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2, 256>, a, nprimes, zb, s, lds, 256);

@@ -383,6 +383,171 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
   }
 }
 
+// ---- register-resident block tile ------------------------------------------
+// The same block step with the tile in registers: each of the NT threads
+// holds PT positions (8, or 16 when a pass has 4 stages) of ET = 32 / PT
+// adjacent entries, so a tile is NT * 32 residues (2^blk_log positions times
+// 2^eb_log entries).  In a pass of r stages at stride S a thread runs PT / 2^r
+// radix-2^r groups on its own registers; between passes the tile moves
+// through LDS once (a write in one pass's position order, a read in the
+// next's).  The first pass takes its values straight from the loads and the
+// last one stores straight from registers, so LDS sees two accesses per
+// residue per pass boundary and none at the ends.  Positions are swizzled in
+// LDS (p ^ ((p >> 3) & 7)) so that the strided position sets of a wave spread
+// over the banks.
+
+__device__ __forceinline__ int reg_swz(int p) { return p ^ ((p >> 3) & 7); }
+
+// r stages on each of the thread's PT / 2^r groups, twiddles of group c at
+// tw[k S + j].
+template <bool DIF, int PT, int ET, int r>
+__device__ __forceinline__ void reg_pass(uint32_t (&x)[ET][PT], int w, int s,
+                                         const Tw* __restrict__ tw, uint32_t q) {
+  constexpr int R = 1 << r;
+  const int S = 1 << s;
+#pragma unroll
+  for (int c = 0; c < PT / R; ++c) {
+    const int wg = w * (PT / R) + c;
+    const int j = wg & (S - 1);
+    Tw t[R - 1];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+#pragma unroll
+    for (int e = 0; e < ET; ++e) butterflies<r, DIF, false>(&x[e][c * R], t, q);
+  }
+}
+
+// Whether a launch's block step fits the register tile with NT threads and
+// PT positions per thread (the host picks the kernel with this).
+__host__ __device__ inline bool reg_tile_fits(const NttLaunch& a, int nt_log, int pt_log) {
+  if (!a.split || a.npass < 2) return false;
+  int maxr = 0;
+  for (int ps = 1; ps < a.npass; ++ps) maxr = a.stages[ps] > maxr ? a.stages[ps] : maxr;
+  const int et_log = 5 - pt_log;
+  return maxr <= pt_log && (pt_log == 4) == (maxr == 4) &&
+         a.blk_log + a.eb_log == nt_log + 5 && a.eb_log >= et_log &&
+         a.blk_log >= pt_log && a.vec >= (1 << et_log) && a.blk_pitch == (1 << a.eb_log);
+}
+
+// The register tile with the block passes fixed at compile time: R1, R2, R3
+// stages in forward (decreasing-stride) order (R3 = 0: two passes), so all
+// position and twiddle index arithmetic is shifts of constants.
+template <int R1, int R2, int R3>
+struct RegPasses {
+  static constexpr int np = R3 ? 3 : 2;
+  static constexpr int r(int i) { return i == 0 ? R1 : i == 1 ? R2 : R3; }
+  static constexpr int s(int i) { return i == 0 ? R2 + R3 : i == 1 ? R3 : 0; }
+};
+
+template <int PT, int r, int s>
+__device__ __forceinline__ int reg_pos_c(int w, int v) {
+  const int c = v >> r, u = v & ((1 << r) - 1);
+  const int wg = w * (PT >> r) + c;
+  return ((wg >> s) << (s + r)) + (wg & ((1 << s) - 1)) + (u << s);
+}
+
+template <bool DIF, int PT, int ET, int EBL, class RP, int K>
+__device__ __forceinline__ void reg_steps(uint32_t (&x)[ET][PT], int w, int el, uint32_t* lds,
+                                          const uint32_t* twoff, const Tw* twb, uint32_t q,
+                                          uint32_t* out, size_t E, bool live) {
+  constexpr int i = DIF ? K : RP::np - 1 - K;           // pass in forward order
+  constexpr int r = RP::r(i), s = RP::s(i);
+  if constexpr (K > 0) {
+    constexpr int ip = DIF ? K - 1 : RP::np - K;        // previous pass
+    constexpr int rp = RP::r(ip), sp = RP::s(ip);
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+      Vec<uint32_t, ET> y;
+#pragma unroll
+      for (int e = 0; e < ET; ++e) y.v[e] = x[e][v];
+      *(Vec<uint32_t, ET>*)(lds + (reg_swz(reg_pos_c<PT, rp, sp>(w, v)) << EBL) + el) = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+      const Vec<uint32_t, ET> y =
+          *(const Vec<uint32_t, ET>*)(lds + (reg_swz(reg_pos_c<PT, r, s>(w, v)) << EBL) + el);
+#pragma unroll
+      for (int e = 0; e < ET; ++e) x[e][v] = y.v[e];
+    }
+    __syncthreads();
+  }
+  reg_pass<DIF, PT, ET, r>(x, w, s, twb + twoff[i + 1], q);
+  if constexpr (K + 1 < RP::np) {
+    reg_steps<DIF, PT, ET, EBL, RP, K + 1>(x, w, el, lds, twoff, twb, q, out, E, live);
+  } else if (live) {
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+      Vec<uint32_t, ET> y;
+#pragma unroll
+      for (int e = 0; e < ET; ++e) y.v[e] = x[e][v];
+      *(Vec<uint32_t, ET>*)(out + (size_t)reg_pos_c<PT, r, s>(w, v) * E) = y;
+    }
+  }
+}
+
+// EBL = eb_log: 2^EBL entries per tile (so NT * 32 = 2^(R1+R2+R3+EBL)).
+template <bool DIF, int NT, int PT, int R1, int R2, int R3>
+__device__ __forceinline__ void block_tile_regc(const NttLaunch& a, int prime, int eb, int z,
+                                                uint32_t* lds) {
+  using RP = RegPasses<R1, R2, R3>;
+  constexpr int ET = 32 / PT;
+  constexpr int BL = R1 + R2 + R3;                        // blk_log
+  constexpr int EBL = (NT == 256 ? 13 : 14) - BL;         // eb_log
+  constexpr int GL = EBL - (ET == 4 ? 2 : 1);
+  const PrimeConst& P = a.pc[prime];
+  const int g = threadIdx.x & ((1 << GL) - 1), w = threadIdx.x >> GL;
+  const int el = g * ET;
+  const bool live = (eb << EBL) + el < a.E;
+  uint32_t* buf = (uint32_t*)a.out + a.out_prime_stride * prime + ((size_t)z << BL) * a.E +
+                  ((size_t)eb << EBL) + el;
+  constexpr int i0 = DIF ? 0 : RP::np - 1;
+  uint32_t x[ET][PT];
+#pragma unroll
+  for (int v = 0; v < PT; ++v) {
+    Vec<uint32_t, ET> y;
+    if (live) {
+      y = *(const Vec<uint32_t, ET>*)(buf + (size_t)reg_pos_c<PT, RP::r(i0), RP::s(i0)>(w, v) * a.E);
+    } else {
+#pragma unroll
+      for (int e = 0; e < ET; ++e) y.v[e] = 0;
+    }
+#pragma unroll
+    for (int e = 0; e < ET; ++e) x[e][v] = y.v[e];
+  }
+  reg_steps<DIF, PT, ET, EBL, RP, 0>(x, w, el, lds, a.tw_off, DIF ? P.tw_fwd : P.tw_inv, P.q,
+                                     buf, (size_t)a.E, live);
+}
+
+// Register-tile kind of a launch's block step for 2^nt_log threads (0: the
+// tile does not fit, or the passes are none of the compiled structures).
+__host__ __device__ inline int reg_kind_of(const NttLaunch& a, int nt_log) {
+  if (a.npass < 3 || a.npass > 4) return 0;
+  const int r1 = a.stages[1], r2 = a.stages[2], r3 = a.npass == 4 ? a.stages[3] : 0;
+  if (a.stride_log[1] != r2 + r3 || a.stride_log[2] != r3 || (r3 && a.stride_log[3] != 0))
+    return 0;
+  int kind = 0, pt_log = 4;
+  if (r1 == 3 && r2 == 3 && r3 == 3) kind = 1, pt_log = 3;
+  else if (r1 == 4 && r2 == 3 && r3 == 0) kind = 2;
+  else if (r1 == 4 && r2 == 4 && r3 == 0) kind = 3;
+  else if (r1 == 4 && r2 == 3 && r3 == 3) kind = 4;
+  else if (r1 == 4 && r2 == 4 && r3 == 3) kind = 5;
+  return kind && reg_tile_fits(a, nt_log, pt_log) ? kind : 0;
+}
+
+// The block step of a launch whose reg_kind is set, with NT threads.
+template <bool DIF, int NT>
+__device__ __forceinline__ void block_tile_reg_kind(const NttLaunch& a, int prime, int eb, int z,
+                                                    uint32_t* lds) {
+  switch (a.reg_kind) {
+    case 1: block_tile_regc<DIF, NT, 8, 3, 3, 3>(a, prime, eb, z, lds); break;
+    case 2: block_tile_regc<DIF, NT, 16, 4, 3, 0>(a, prime, eb, z, lds); break;
+    case 3: block_tile_regc<DIF, NT, 16, 4, 4, 0>(a, prime, eb, z, lds); break;
+    case 4: block_tile_regc<DIF, NT, 16, 4, 3, 3>(a, prime, eb, z, lds); break;
+    default: block_tile_regc<DIF, NT, 16, 4, 4, 3>(a, prime, eb, z, lds); break;
+  }
+}
+
 // First forward pass of a split transform, r stages at stride S = L / 2^r,
 // items [it0, it1) with stride `step`: item (j, g) reads, for the CV entries
 // e = g CV .. g CV + CV - 1, the rows j + u S below nin of the

@@ -117,7 +117,8 @@ const NttTune& ntt_tune() {
                             env_int("PM_TUNE_NTT_BLK_PAD", 0, 0, 64) & ~3,
                             env_int("PM_TUNE_NTT_BLK_NT", 256, 256, 512) > 256 ? 512 : 256,
                             env_int("PM_TUNE_NTT_BLK_TILE_LOG", 13, 11, 15),
-                            env_int("PM_TUNE_BATCH_TILE_LOG", 14, 11, 15)};
+                            env_int("PM_TUNE_BATCH_TILE_LOG", 14, 11, 15),
+                            env_int("PM_TUNE_NTT_REG_TILE", 1, 0, 1)};
   return T;
 }
 

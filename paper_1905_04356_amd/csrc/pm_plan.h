@@ -48,6 +48,7 @@ struct NttTune {
   int blk_nt;                  // block step: threads per workgroup (256 or 512)
   int blk_tile_log;            // block step: log2 residues per tile
   int batch_tile_log;          // ... in the batched phase kernels
+  int reg_tile;                // block step: register-resident tile where it fits (1)
 };
 const NttTune& ntt_tune();
 int split_stages(int logL);

@@ -455,3 +455,21 @@ def test_kernel_timing_counts_only_unpaused_launches():
         assert one[kind][1] >= 1 and one[kind][0] > 0.0, kind
         assert two[kind][1] == 2 * one[kind][1], kind
     assert one["crt"][1] == 0 and one["batched"][1] == 0
+
+
+@pytest.mark.parametrize("p,m,n,k,d", [
+    (P30, 8, 8, 8, 1024),     # L = 2^11: block passes {4, 3}, 64-entry tiles
+    (P31, 8, 8, 6, 2048),     # 2^12: {4, 4}, 32-entry tiles, 48 entries (ragged)
+    (P30, 8, 4, 6, 4096),     # 2^13: {3, 3, 3}, 16-entry tiles, 24 and 48 entries
+    (P31, 4, 4, 2, 8192),     # 2^14: {4, 3, 3}, 8-entry tiles
+    (P30, 2, 2, 3, 16384),    # 2^15: {4, 4, 3}, 4-entry tiles, 6 entries
+    (P31, 3, 3, 1, 16384),    # 2^15, odd entry counts: 1-word vectors, LDS-tile path
+])
+def test_block_step_pass_structures(p, m, n, k, d):
+    """Split transforms at every length from 2^11 to 2^15, so the block step
+    runs each of its pass structures (forward and inverse), with tiles whose
+    last entries lie beyond the matrix."""
+    say(f"[parity] block step p={p} m={m} n={n} k={k} d={d}")
+    A, B = tensors(p, m, n, k, d, seed=17)
+    C = gpu_mul(p, A, B)
+    sampled_check(p, A, B, C, seed=17, entries=2 if d >= 16384 else 4)
