@@ -437,6 +437,7 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
 
 KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing
     ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_block_kernel<true", "ntt_fwd"),
+    ("ntt_block_regc_kernel<true", "ntt_fwd"), ("ntt_block_regc_kernel<false", "ntt_inv"),
     ("ntt_fwd_kernel", "ntt_fwd"), ("pointwise", "pointwise"),
     ("ntt_block_kernel<false", "ntt_inv"), ("ntt_col_inv_kernel", "ntt_inv"),
     ("ntt_inv_kernel", "ntt_inv"), ("crt_kernel", "crt"), ("batch_kernel", "batched"))
