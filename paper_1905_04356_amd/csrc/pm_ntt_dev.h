@@ -58,8 +58,11 @@ struct alignas(sizeof(T) * V) Vec {
 // 2^v for v = r-1 .. 0, (a, b) -> (a + b, (a - b) w).  DIT: v = 0 .. r-1,
 // (a, b) -> (a + b w, a - b w).  ZHI (DIF only): x[2^(r-1) ..] are zero, so
 // the first stage is (a, 0) -> (a, a w).  t[(2^v - 1) + u'] is the twiddle of
-// stage v for butterflies whose lower index is u' mod 2^v.
-template <int r, bool DIF, bool ZHI>
+// stage v for butterflies whose lower index is u' mod 2^v.  UNIT0: the
+// butterflies run at stride 1 of the whole transform, where the twiddle of
+// lower index 0 is w^0 = 1 in every stage, so those take no product (half
+// of the last stage, a quarter of the one before, ...).
+template <int r, bool DIF, bool ZHI, bool UNIT0 = false>
 __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q) {
   constexpr int R = 1 << r;
   const uint32_t nq = opaque_neg(q);
@@ -70,7 +73,14 @@ __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q
       for (int u = 0; u < R; ++u) {
         if (u & (1 << v)) continue;
         const int u2 = u | (1 << v);
-        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        const int ul = u & ((1 << v) - 1);
+        if (UNIT0 && ul == 0) {
+          const uint32_t a0 = x[u], b0 = x[u2];
+          x[u] = add_mod(a0, b0, q);
+          x[u2] = sub_mod(a0, b0, q);
+          continue;
+        }
+        const Tw tt = t[(1 << v) - 1 + ul];
         if (ZHI && v == r - 1) {
           x[u2] = mul_shoup_nq(x[u], tt.w, tt.wp, q, nq);
         } else {
@@ -87,9 +97,13 @@ __device__ __forceinline__ void butterflies(uint32_t* x, const Tw* t, uint32_t q
       for (int u = 0; u < R; ++u) {
         if (u & (1 << v)) continue;
         const int u2 = u | (1 << v);
-        const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+        const int ul = u & ((1 << v) - 1);
         const uint32_t a0 = x[u];
-        const uint32_t b0 = mul_shoup_nq(x[u2], tt.w, tt.wp, q, nq);
+        uint32_t b0 = x[u2];
+        if (!(UNIT0 && ul == 0)) {
+          const Tw tt = t[(1 << v) - 1 + ul];
+          b0 = mul_shoup_nq(b0, tt.w, tt.wp, q, nq);
+        }
         x[u] = add_mod(a0, b0, q);
         x[u2] = sub_mod(a0, b0, q);
       }
@@ -398,13 +412,13 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
 
 __device__ __forceinline__ int reg_swz(int p) { return p ^ ((p >> 3) & 7); }
 
-// r stages on each of the thread's PT / 2^r groups, twiddles of group c at
-// tw[k S + j].
-template <bool DIF, int PT, int ET, int r>
-__device__ __forceinline__ void reg_pass(uint32_t (&x)[ET][PT], int w, int s,
+// r stages at stride 2^s on each of the thread's PT / 2^r groups, twiddles
+// of group c at tw[k S + j].  At stride 1 (s = 0) every group has j = 0, so
+// its twiddles are the same for all lanes and those of w^0 = 1 are skipped.
+template <bool DIF, int PT, int ET, int r, int s>
+__device__ __forceinline__ void reg_pass(uint32_t (&x)[ET][PT], int w,
                                          const Tw* __restrict__ tw, uint32_t q) {
-  constexpr int R = 1 << r;
-  const int S = 1 << s;
+  constexpr int R = 1 << r, S = 1 << s;
 #pragma unroll
   for (int c = 0; c < PT / R; ++c) {
     const int wg = w * (PT / R) + c;
@@ -413,7 +427,7 @@ __device__ __forceinline__ void reg_pass(uint32_t (&x)[ET][PT], int w, int s,
 #pragma unroll
     for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
 #pragma unroll
-    for (int e = 0; e < ET; ++e) butterflies<r, DIF, false>(&x[e][c * R], t, q);
+    for (int e = 0; e < ET; ++e) butterflies<r, DIF, false, s == 0>(&x[e][c * R], t, q);
   }
 }
 
@@ -472,7 +486,7 @@ __device__ __forceinline__ void reg_steps(uint32_t (&x)[ET][PT], int w, int el, 
     }
     __syncthreads();
   }
-  reg_pass<DIF, PT, ET, r>(x, w, s, twb + twoff[i + 1], q);
+  reg_pass<DIF, PT, ET, r, s>(x, w, twb + twoff[i + 1], q);
   if constexpr (K + 1 < RP::np) {
     reg_steps<DIF, PT, ET, EBL, RP, K + 1>(x, w, el, lds, twoff, twb, q, out, E, live);
   } else if (live) {
