@@ -341,17 +341,20 @@ def bench_vdm(p=1000000007, seed=9, reps=10):
 
 
 def bench_wrap(p=998244353, seed=10, reps=10):
-    """Degrees where 2d - 1 lies just above a power of two: the wrapped form
-    (cyclic product on 2^j points, short product for the top coefficients,
-    correction) that pm_mul takes, against the plain 2^(j+1)-point transforms
-    (a one-product pm_mul_batched call), same operands, outputs compared."""
+    """Degrees where 2d - 1 lies just above a power of two: pm_mul, which takes
+    the wrapped form (cyclic product on 2^j points, short product for the
+    top coefficients, correction) when the top is small and the product
+    large, against the plain 2^(j+1)-point transforms (a one-product
+    pm_mul_batched call), same operands, outputs compared."""
     import torch
+    from paper_1905_04356_amd import binding as Bd
     from paper_1905_04356_amd import inputs as I
     from paper_1905_04356_amd import polymat
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
     rows = []
-    for (m, n, k, d) in [(64, 64, 32, 1100), (64, 64, 32, 2100), (64, 64, 32, 2500)]:
+    for (m, n, k, d) in [(64, 64, 32, 1100), (64, 64, 32, 2100), (64, 64, 32, 2500),
+                         (128, 128, 64, 1100), (128, 128, 64, 2100), (32, 32, 32, 2100)]:
         A = I.polymat_torch(seed, 0, I.TENSOR_A, p, d, m, n, dev)
         B = I.polymat_torch(seed, 0, I.TENSOR_B, p, d, n, k, dev)
         ws = polymat.Workspace(dev)
@@ -372,7 +375,13 @@ def bench_wrap(p=998244353, seed=10, reps=10):
 
         t_w = timed(lambda: polymat.mul(p, A, B, out=ow, workspace=ws, stream=stream))
         t_p = timed(lambda: polymat.mul_batched(p, [A], [B], [op], workspace=ws, stream=stream))
-        rows.append({"m": m, "n": n, "k": k, "d": d, "wrapped_ms": t_w, "plain_ms": t_p,
+        # in direct mode only the wrap's correction kernel is timed as CRT
+        Bd.pm_profile_begin()
+        polymat.mul(p, A, B, out=ow, workspace=ws, stream=stream)
+        wrapped = Bd.pm_profile_end()["crt"][1] > 0
+        rows.append({"m": m, "n": n, "k": k, "d": d,
+                     "pm_mul_path": "wrapped" if wrapped else "plain",
+                     "pm_mul_ms": t_w, "plain_ms": t_p,
                      "outputs_equal": bool(torch.equal(ow, op))})
         del A, B, ws, ow, op
     return {"workload": f"products mod {p} with 2d - 1 just above a power of two", "runs": rows}

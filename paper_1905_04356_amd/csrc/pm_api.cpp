@@ -278,7 +278,12 @@ int vdm_max_d() {
 // transform of 2^j points, the t = 2d - 1 - 2^j coefficients at and above
 // 2^j, which involve only A[h..] and B[h..] (h = 2^j - d + 1), as the window
 // t-1 .. 2t-2 of that short product, and the wrapped rows corrected: at most
-// 1.5 2^j points instead of 2^(j+1).  PM_TUNE_WRAP=0 turns it off;
+// 1.5 2^j points instead of 2^(j+1).  The short product and the correction
+// cost launches of their own, so this pays only for large products with a
+// small top: t <= 2^j / 4 and (mn + nk + mk) 2^j >= 2^25 (measured: 128x128x64
+// at t = 103..175 0.60-0.84 of the plain time, 64x64x32 at 2^12 + 103 0.74 and
+// 2^12 + 903 0.94; at 2^11 + 151, where (mn + nk + mk) 2^j = 2^24, 1.03; small
+// shapes and tops near 2^(j-1) 1.0-2.3).  PM_TUNE_WRAP=0 turns it off;
 // PM_TUNE_WRAP_MINLOG (default 10) is the least j.  Returns 1 when the
 // product was launched this way, 0 when it does not apply, or a pm_status.
 int wrap_min_log() {
@@ -296,7 +301,8 @@ int run_wrapped(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   const int j = P.logL - 1;
   if (P.da != P.db || P.lo != 0 || j < wrap_min_log()) return 0;
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
-  if (t < 1 || t > Lp / 2 || d > Lp) return 0;
+  const uint64_t entries = (uint64_t)P.m * P.n + (uint64_t)P.n * P.k + (uint64_t)P.m * P.k;
+  if (t < 1 || t > Lp / 4 || d > Lp || (entries << j) < (1ull << 25)) return 0;
   Plan Pc, Pt;
   if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, &Pc) != PM_OK) return 0;
   if (make_slice_plan(P.p, P.m, P.n, P.k, t, t, t - 1, t, P.elem_bytes, &Pt) != PM_OK) return 0;

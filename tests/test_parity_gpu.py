@@ -401,34 +401,56 @@ def test_mfma_centred_limbs_for_primes_above_0x7f7f7f7f(fill):
     assert np.array_equal(C.astype(np.uint64), O.polymatmul(p, A, B))
 
 
-@pytest.mark.parametrize("p,dtype,m,n,k,d", [
-    (P30, np.uint32, 3, 4, 2, 600),        # 2d-1 = 1199: 1024 points + a 175-coefficient top
-    (P31, np.uint32, 4, 4, 4, 700),
-    (P30, np.uint32, 2, 2, 2, 768),        # t = 511, the largest wrapped case at 2^10
-    (P30, np.uint32, 2, 2, 2, 769),        # t = 513: the plain 2048-point transform
-    (P32, np.uint32, 3, 3, 3, 600),        # CRT mode
-    ((1 << 61) - 1, np.uint64, 2, 2, 2, 1100),
+def _wrapped(p, A, B):
+    """The product on the GPU and whether it took the wrapped path (in direct
+    mode only the wrap's correction kernel is timed as Chinese remaindering)."""
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    Bd.pm_profile_begin()
+    tC = polymat.mul(p, tA, tB)
+    stats = Bd.pm_profile_end()
+    torch.cuda.synchronize()
+    return tC.cpu().numpy(), stats["crt"][1] > 0
+
+
+@pytest.mark.parametrize("p,m,n,k,d,wraps", [
+    (P30, 3, 4, 2, 600, False),      # small products: plain transforms
+    (P30, 64, 64, 64, 1100, False),  # (mn + nk + mk) 2^11 below 2^25
+    (P30, 128, 128, 64, 600, True),  # 2^10 points + a 175-coefficient top
+    (P31, 64, 64, 64, 2100, True),   # 2^12 + 103
+    (P30, 64, 64, 64, 2560, True),   # top 1023 <= 2^12 / 4: wrapped
+    (P30, 64, 64, 64, 2562, False),  # top 1027: the plain 8192-point transform
 ])
-def test_wrapped_lengths(p, dtype, m, n, k, d):
-    """Products with 2^j < 2d-1 <= 1.5 2^j: a cyclic product on 2^j points,
-    the top coefficients from a short window product, and the correction."""
-    full_check(p, m, n, k, d, seed=14, dtype=dtype)
+def test_wrapped_lengths(p, m, n, k, d, wraps):
+    """Products with 2^j < 2d-1 <= 1.25 2^j and enough work: a cyclic product
+    on 2^j points, the top coefficients from a short window product, and the
+    correction; sampled entries against the oracle, points and Freivalds on
+    all, and the path taken as the rule says."""
+    say(f"[parity] wrapped p={p} m={m} n={n} k={k} d={d}")
+    A, B = tensors(p, m, n, k, d, seed=14)
+    C, took = _wrapped(p, A, B)
+    assert took == wraps
+    sampled_check(p, A, B, C, seed=14, entries=4)
+
+
+def test_wrapped_crt_u64():
+    """The wrapped path in CRT mode with 64-bit residues."""
+    p, m, n, k, d = (1 << 61) - 1, 64, 64, 64, 2100
+    say("[parity] wrapped CRT u64")
+    A, B = tensors(p, m, n, k, d, seed=18, dtype=np.uint64)
+    C = gpu_mul(p, A, B)
+    sampled_check(p, A, B, C, seed=18, entries=2)
 
 
 def test_wrapped_equals_plain_transforms():
-    p, m, n, k = P30, 16, 16, 16
-    for d in (1030, 1300, 1536, 2500):
+    p, m, n, k = P30, 64, 64, 64
+    for d in (2050, 2100, 2560):
         A, B = tensors(p, m, n, k, d, seed=15)
+        wrapped, took = _wrapped(p, A, B)
+        assert took, d
         tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
-        wrapped = polymat.mul(p, tA, tB)
         plain, = polymat.mul_batched(p, [tA], [tB])      # one product: plain transforms
         torch.cuda.synchronize()
-        assert torch.equal(wrapped, plain), d
-    pairs = I.sample_pairs(15, m, k, 4)
-    rows = O.polymatmul_entries(p, A, B, pairs)
-    W = wrapped.cpu().numpy()
-    for s, (i, j) in enumerate(pairs):
-        assert np.array_equal(W[:, i, j].astype(np.uint64), rows[s])
+        assert np.array_equal(wrapped, plain.cpu().numpy()), d
 
 
 def test_kernel_timing_counts_only_unpaused_launches():
