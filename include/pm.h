@@ -71,7 +71,7 @@ typedef enum pm_status {
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 2
+#define PM_ABI_VERSION 3
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -84,6 +84,12 @@ typedef struct pm_plan_info {
   int32_t pointwise;
   uint32_t primes[8];        /* q_1..q_r (primes[0] = p in direct mode)     */
   uint64_t workspace_bytes;  /* what pm_mul_* needs for this product        */
+  int32_t wrap_log2_len;     /* j > 0: pm_mul_* computes the product as
+                                A B mod (x^(2^j) - 1) on 2^j points plus its
+                                top coefficients from a short product (large
+                                products with 2d - 1 a little above 2^j);
+                                0: on 2^log2_len points                     */
+  int32_t reserved;
 } pm_plan_info;
 
 /* Plan the product of an (m x n) by (n x k) matrix of degree < d mod p with

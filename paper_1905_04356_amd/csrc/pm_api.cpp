@@ -35,8 +35,13 @@ static bool vdm_eligible(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d)
   return p > 2 && vdm_check(p, m, n, k, d) == PM_OK;
 }
 
+namespace {
+int wrap_log_of(const Plan& P);
+}
+
 static void fill_plan_info(const Plan& P, pm_plan_info* out) {
   memset(out, 0, sizeof *out);
+  out->wrap_log2_len = wrap_log_of(P);
   out->mode = P.mode;
   out->log2_len = P.logL;
   out->num_primes = P.r;
@@ -296,17 +301,31 @@ int wrap_min_log() {
   return v;
 }
 
-int run_wrapped(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                uint64_t ws_bytes, hipStream_t s) {
+// j when a whole product of plan P takes the wrapped form on 2^j points
+// (with P's own workspace), else 0; the cyclic and top plans through pc, pt.
+int wrap_log_plans(const Plan& P, Plan* pc, Plan* pt) {
   const int j = P.logL - 1;
   if (P.da != P.db || P.lo != 0 || j < wrap_min_log()) return 0;
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t entries = (uint64_t)P.m * P.n + (uint64_t)P.n * P.k + (uint64_t)P.m * P.k;
   if (t < 1 || t > Lp / 4 || d > Lp || (entries << j) < (1ull << 25)) return 0;
+  if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, pc) != PM_OK) return 0;
+  if (make_slice_plan(P.p, P.m, P.n, P.k, t, t, t - 1, t, P.elem_bytes, pt) != PM_OK) return 0;
+  if (pc->ws_bytes > P.ws_bytes || pt->ws_bytes > P.ws_bytes) return 0;
+  return j;
+}
+
+int wrap_log_of(const Plan& P) {
+  Plan pc, pt;
+  return wrap_log_plans(P, &pc, &pt);
+}
+
+int run_wrapped(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
+                uint64_t ws_bytes, hipStream_t s) {
   Plan Pc, Pt;
-  if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, &Pc) != PM_OK) return 0;
-  if (make_slice_plan(P.p, P.m, P.n, P.k, t, t, t - 1, t, P.elem_bytes, &Pt) != PM_OK) return 0;
-  if (Pc.ws_bytes > ws_bytes || Pt.ws_bytes > ws_bytes) return 0;
+  const int j = wrap_log_plans(P, &Pc, &Pt);
+  if (!j || Pc.ws_bytes > ws_bytes || Pt.ws_bytes > ws_bytes) return 0;
+  const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t eb = (uint64_t)P.elem_bytes;
   const int h = Lp - d + 1;
   int st = run_product(Pc, A, B, C, ws, s);

@@ -5,7 +5,9 @@ Requests name an operand pair from a device-resident pool. The pool keeps
 each operand's evaluations at the transform points (the precomputation of
 the paper's multiplier classes, Section 2, "Polynomial matrix
 multiplication"), so a request costs only its pointwise products, inverse
-transform and (for CRT moduli) reconstruction. The host loop:
+transform and (for CRT moduli) reconstruction; products that pm_mul
+computes in the wrapped form on half the points run as pm_mul calls
+instead. The host loop:
 
 * moves requests whose arrival time has passed into a FIFO ready queue;
 * polls the events of in-flight batches; a finished batch frees its streams'
@@ -43,22 +45,27 @@ class PoolItem:
     A_eval: torch.Tensor | None
     B_eval: torch.Tensor | None
     footprint: int          # workspace + output bytes of one product
+    wraps: bool = False     # pm_mul takes the wrapped form (no evaluations kept)
 
 
 def make_pool(p: int, seed: int, count: int, device, with_evals: bool = True,
               dims_cap: int | None = None) -> list[PoolItem]:
     """`count` operand pairs with the batched shape rule, generated on the
-    device; evaluations precomputed when `with_evals`."""
+    device; evaluations precomputed when `with_evals`, except for products
+    that pm_mul computes in the wrapped form (2d - 1 a little above a power
+    of two 2^j, large shapes): on 2^j points they cost less than the
+    2^(j+1)-point evaluations would save."""
     pool = []
     for i, (m, n, k, d) in enumerate(I.batched_shapes(seed, count)):
         if dims_cap:
             m, n, k = min(m, dims_cap), min(n, dims_cap), min(k, dims_cap)
         A = I.polymat_torch(seed, i, I.TENSOR_A, p, d, m, n, device)
         B = I.polymat_torch(seed, i, I.TENSOR_B, p, d, n, k, device)
-        Ae = polymat.evaluate(p, A, 0) if with_evals else None
-        Be = polymat.evaluate(p, B, 1) if with_evals else None
+        wraps = _b.pm_plan(p, m, n, k, d, 4).wrap_log2_len > 0
+        Ae = polymat.evaluate(p, A, 0) if with_evals and not wraps else None
+        Be = polymat.evaluate(p, B, 1) if with_evals and not wraps else None
         fp = _b.pm_workspace_bytes(p, m, n, k, d, 4) + 4 * (2 * d - 1) * m * k
-        pool.append(PoolItem(m, n, k, d, A, B, Ae, Be, fp))
+        pool.append(PoolItem(m, n, k, d, A, B, Ae, Be, fp, wraps))
     torch.cuda.synchronize()
     return pool
 
@@ -105,10 +112,18 @@ class Server:
         with torch.cuda.stream(st):
             outs = [torch.empty((2 * it.d - 1, it.m, it.k), dtype=torch.uint32,
                                 device=it.A.device) for it in its]
-            polymat.mul_batched(self.p, [it.A for it in its], [it.B for it in its], outs,
-                                workspace=self.ws[si], stream=st,
-                                A_evals=[it.A_eval for it in its],
-                                B_evals=[it.B_eval for it in its])
+            # wrapped-form products one pm_mul each, the rest as one batch
+            # reusing their evaluations
+            rest = [i for i, it in enumerate(its) if not it.wraps]
+            for i, it in enumerate(its):
+                if it.wraps:
+                    polymat.mul(self.p, it.A, it.B, out=outs[i], workspace=self.ws[si],
+                                stream=st)
+            if rest:
+                polymat.mul_batched(self.p, [its[i].A for i in rest], [its[i].B for i in rest],
+                                    [outs[i] for i in rest], workspace=self.ws[si], stream=st,
+                                    A_evals=[its[i].A_eval for i in rest],
+                                    B_evals=[its[i].B_eval for i in rest])
             ev = torch.cuda.Event()
             ev.record(st)
         return ev, outs

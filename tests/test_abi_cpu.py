@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(B.EXPORTS)
-    assert L.pm_abi_version() == 2
+    assert L.pm_abi_version() == 3
     assert B.status_str(B.PM_EWORKSPACE).startswith("PM_EWORKSPACE")
 
 
@@ -201,3 +201,18 @@ def test_profile_session_rules():
     assert set(stats) == set(B.KERNEL_KINDS)
     assert all(ms == 0.0 and n == 0 for ms, n in stats.values())
     assert lib.pm_profile_pause(0) == B.PM_EINVAL
+
+
+@pytest.mark.parametrize("m,n,k,d,j", [
+    (128, 8, 128, 4740, 13),   # 2d - 1 = 9479: 8192 points plus a 1287-coefficient top
+    (64, 64, 64, 2560, 12),    # top 1023 <= 2^12 / 4
+    (64, 64, 64, 2562, 0),     # top 1027 > 2^12 / 4
+    (64, 64, 64, 1100, 0),     # (mn + nk + mk) 2^11 < 2^25
+    (128, 128, 64, 600, 10),
+    (3, 4, 2, 600, 0),
+    (64, 64, 32, 4096, 0),     # 2d - 1 = 8191 < 2^13: no top
+])
+def test_plan_reports_the_wrapped_form(m, n, k, d, j):
+    """pm_plan's wrap_log2_len follows the rule pm_mul applies: wrap only
+    large products whose top t = 2d - 1 - 2^j is at most 2^j / 4."""
+    assert B.pm_plan(998244353, m, n, k, d, 4).wrap_log2_len == j
