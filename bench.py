@@ -233,9 +233,10 @@ def bench_pmbasis(p=786433, seed=7):
                      "leaf_seconds": pm.leaf_seconds, "leaves": pm.leaves,
                      "basis_degree": int(P.shape[0]) - 1})
         del F, P
-    # eight independent instances in lockstep (batched windows, leaves on a
-    # thread pool) against one run after another
-    m, n, sigma, T, K = 32, 16, 2048, 8, 8
+    # sixteen independent instances in lockstep (batched windows, leaves on
+    # the device, one workgroup per instance) against the same with leaves on
+    # a host thread pool and against one run after another
+    m, n, sigma, T, K = 32, 16, 2048, 8, 16
     Fs = [I.polymat_torch(seed + 1 + i, 0, I.TENSOR_A, p, sigma, m, n, dev) for i in range(K)]
     PB.PMBasisMany(p, T)([F[:64] for F in Fs], 64, [[0] * m] * K)
     torch.cuda.synchronize()
@@ -244,6 +245,10 @@ def bench_pmbasis(p=786433, seed=7):
     torch.cuda.synchronize()
     t_many = time.perf_counter() - t0
     t0 = time.perf_counter()
+    PB.PMBasisMany(p, T, device_leaf_min=1 << 30)(Fs, sigma, [[0] * m] * K)
+    torch.cuda.synchronize()
+    t_many_host = time.perf_counter() - t0
+    t0 = time.perf_counter()
     for F in Fs:
         PB.PMBasis(p, T)(F, sigma, [0] * m)
     torch.cuda.synchronize()
@@ -251,7 +256,8 @@ def bench_pmbasis(p=786433, seed=7):
     del Fs
     return {"workload": f"PM-Basis, F m x n of order sigma, mod {p}, zero shift", "runs": rows,
             "lockstep": {"instances": K, "m": m, "n": n, "order": sigma, "threshold": T,
-                         "lockstep_seconds": t_many, "one_after_another_seconds": t_seq}}
+                         "lockstep_seconds": t_many, "lockstep_host_leaves_seconds": t_many_host,
+                         "one_after_another_seconds": t_seq}}
 
 
 def bench_newton(p=2013265921, n=32, da=2049, N=4096, rhs=64, seed=8):

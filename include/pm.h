@@ -187,6 +187,25 @@ pm_status pm_middle_batched_u32(uint32_t p, int32_t count, const pm_window_produ
 pm_status pm_middle_batched_u64(uint64_t p, int32_t count, const pm_window_product* wins,
                                 void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* The same M-Basis on the device for `count` instances of one shape at once
+ * (one workgroup each), with the same result residue for residue as
+ * pm_mbasis_host.  p must be prime (not checked here), 2 <= p < 2^31
+ * (PM_ERANGE otherwise).  F: device, instance i at F + i*f_stride
+ * (f_stride >= sigma*m*n), residues taken mod p; shift: device, count*m
+ * integers; P: device, count*(sigma+1)*m*m residues (instance i at
+ * i*(sigma+1)*m*m), overwritten; rdeg: device, count*m integers.
+ * workspace: device, at least pm_mbasis_workspace_bytes bytes, 256-byte
+ * aligned (PM_EWORKSPACE otherwise).  PM_EUNSUPPORTED when the m x (n + m)
+ * elimination matrix does not fit the 160 KiB of LDS (m (n + m) about
+ * 40000 at most); PM_EINVAL on sizes < 1 or NULL pointers.  Asynchronous on
+ * `stream`. */
+pm_status pm_mbasis_workspace_bytes(int32_t count, int32_t m, int32_t n, int32_t sigma,
+                                    uint64_t* out);
+pm_status pm_mbasis_u32(uint32_t p, int32_t count, int32_t m, int32_t n, int32_t sigma,
+                        const uint32_t* F, uint64_t f_stride, const int64_t* shift,
+                        uint32_t* P, int64_t* rdeg, void* workspace,
+                        uint64_t workspace_bytes, void* stream);
+
 /* Algorithm M-Basis (Section 3, "Approximant bases": sigma rounds of
  * residual, M-Basis-1 returning the s'-Popov basis at order 1, P := Q P and
  * s' := rdeg_s(P)) on the host, for the leaves of PM-Basis, whose polynomial

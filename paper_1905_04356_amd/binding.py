@@ -29,7 +29,7 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
            "pm_matinv_host", "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
            "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
-           "pm_profile_pause")
+           "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
@@ -110,6 +110,8 @@ def lib():
     L.pm_profile_begin.argtypes = []
     L.pm_profile_end.argtypes = [ctypes.POINTER(pm_kernel_stats)]
     L.pm_profile_pause.argtypes = [i32]
+    L.pm_mbasis_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_mbasis_u32.argtypes = [u32, i32, i32, i32, i32, vp, u64, vp, vp, vp, vp, u64, vp]
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
@@ -117,7 +119,7 @@ def lib():
                  "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host", "pm_matinv_host",
                  "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
                  "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
-                 "pm_profile_pause"):
+                 "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -253,6 +255,17 @@ def pm_mbasis_host(p: int, F, sigma: int, shift):
     _check(lib().pm_mbasis_host(p, m, n, sigma, F.ctypes.data, sh.ctypes.data, P.ctypes.data,
                                 rd.ctypes.data), "pm_mbasis_host")
     return P, [int(x) for x in rd]
+
+
+def pm_mbasis_workspace_bytes(count: int, m: int, n: int, sigma: int) -> int | None:
+    """Workspace bytes of pm_mbasis_u32, or None when the shape does not fit
+    the device elimination."""
+    out = ctypes.c_uint64(0)
+    st = lib().pm_mbasis_workspace_bytes(count, m, n, sigma, ctypes.byref(out))
+    if st == PM_EUNSUPPORTED:
+        return None
+    _check(st, "pm_mbasis_workspace_bytes")
+    return out.value
 
 
 def pm_matinv_host(p: int, M):

@@ -26,12 +26,6 @@ __global__ __launch_bounds__(NT, 4) void ntt_block_kernel(NttLaunch a) {
   block_tile<DIF, V, NT>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
 }
 
-template <bool DIF, int NT, int PT>
-__global__ __launch_bounds__(NT, 4) void ntt_block_reg_kernel(NttLaunch a) {
-  extern __shared__ uint32_t lds[];
-  block_tile_reg<DIF, NT, PT>(a, blockIdx.y, xcd_block(blockIdx.x, gridDim.x), blockIdx.z, lds);
-}
-
 template <bool DIF, int NT, int PT, int R1, int R2, int R3>
 __global__ __launch_bounds__(NT, 4) void ntt_block_regc_kernel(NttLaunch a) {
   extern __shared__ uint32_t lds[];

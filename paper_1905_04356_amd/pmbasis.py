@@ -1,15 +1,20 @@
 """Algorithm PM-Basis (Section 3, "Approximant bases") with its polynomial
 products on the GPU.
 
-PM-Basis(F, sigma, s): below the threshold T it is M-Basis (pm_mbasis_host,
-host code: a short sequential elimination per order); above it,
+PM-Basis(F, sigma, s): below the threshold T it is M-Basis, on the host
+(pm_mbasis_host), or on the device (pm_mbasis_u32, one workgroup per
+instance) for families of at least `device_leaf_min` same-shape instances
+in lockstep (32-bit residues mod p < 2^31, shapes whose elimination fits
+the LDS): one elimination is a serial chain that a host core runs faster,
+but the device runs many at once; above it,
     P1 = PM-Basis(F mod x^c, c, s)            c = ceil(sigma / 2)
     R  = MiddleProduct(P1, F, c, sigma - c)   coefficients c .. sigma-1 of P1 F
     P2 = PM-Basis(R, sigma - c, rdeg_s(P1))
     return P2 P1
 The residual and the product run through pm_middle (the residual on a
 transform of about sigma points instead of 1.5 sigma). Bases stay on the
-device between levels; only the leaves' inputs and outputs cross to the host.
+device; a device leaf sends only its row degrees to the host (they steer
+the recursion), a host leaf its input and output.
 The shifts follow the predictable-degree property: the row degrees
 rdeg_s(P2 P1) equal rdeg_{rdeg_s(P1)}(P2), so deg(P) <= max rdeg - min s
 bounds the coefficients kept.
@@ -38,19 +43,44 @@ class PMBasis:
     """One PM-Basis computation mod a prime p (residues as torch.uint32 for
     p < 2^32, torch.uint64 otherwise)."""
 
-    def __init__(self, p: int, threshold: int = 16, stream=None):
+    def __init__(self, p: int, threshold: int = 16, stream=None, device_leaf_min: int = 16):
         if threshold < 1:
             raise ValueError("threshold must be >= 1")
         self.p = p
         self.T = threshold
+        self.device_leaf_min = device_leaf_min
         self.stream = stream
         self.ws = None
         self.leaves = 0
         self.products = 0
         self.leaf_seconds = 0.0   # host time in the leaves (copies included)
 
+    def _device_leaf(self, F: torch.Tensor, sigma: int, count: int = 1) -> bool:
+        return (count >= self.device_leaf_min and F.dtype == torch.uint32 and
+                polymat.mbasis_fits(self.p, F.shape[1], F.shape[2], sigma))
+
+    def _device_leaves(self, Fs, sigma: int, ss):
+        """M-Basis of same-shape instances in one pm_mbasis_u32 call; their
+        row degrees are read back (one small copy)."""
+        if self.ws is None:
+            self.ws = polymat.Workspace(Fs[0].device)
+        stack = torch.stack([F[:sigma] for F in Fs])
+        sh = torch.tensor(ss, dtype=torch.int64, device=Fs[0].device)
+        P, rd = polymat.mbasis(self.p, stack, sigma, sh, workspace=self.ws, stream=self.stream)
+        if self.stream is not None:
+            self.stream.synchronize()
+        rds = rd.tolist()
+        # each basis in an allocation of its own: the products take 16-byte
+        # aligned operands, which views into the stack need not be
+        return [self._bound(P[i], rds[i], ss[i]).clone() for i in range(len(Fs))], rds
+
     def _leaf(self, F: torch.Tensor, sigma: int, s: list[int]):
         t0 = time.perf_counter()
+        if self._device_leaf(F, sigma):
+            (P,), (rd,) = self._device_leaves([F], sigma, [s])
+            self.leaves += 1
+            self.leaf_seconds += time.perf_counter() - t0
+            return P, rd
         Fh = F[:sigma].to("cpu").numpy().astype(np.uint64)
         P, rd = _b.pm_mbasis_host(self.p, Fh, sigma, s)
         P = _trim_host(P)
@@ -108,25 +138,45 @@ class PMBasisMany(PMBasis):
     batched phase kernels carry the whole family (shapes and degrees may
     differ between instances)."""
 
-    def __init__(self, p: int, threshold: int = 16, stream=None, workers: int | None = None):
-        super().__init__(p, threshold, stream)
+    def __init__(self, p: int, threshold: int = 16, stream=None, workers: int | None = None,
+                 device_leaf_min: int = 16):
+        super().__init__(p, threshold, stream, device_leaf_min)
         self.workers = workers or min(16, os.cpu_count() or 1)
         self.pool = None
 
     def _leaves(self, Fs, sigma: int, ss):
-        """The instances' leaves are independent: their host eliminations run
-        on a thread pool (the C calls release the interpreter lock)."""
+        """The instances' leaves are independent: on the device, instances of
+        one shape share a pm_mbasis_u32 call; on the host, the eliminations
+        run on a thread pool (the C calls release the interpreter lock)."""
         t0 = time.perf_counter()
-        hosts = [F[:sigma].to("cpu").numpy().astype(np.uint64) for F in Fs]
-        if self.pool is None:
-            self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.workers)
-        res = list(self.pool.map(lambda a: _b.pm_mbasis_host(self.p, a[0], sigma, a[1]),
-                                 zip(hosts, ss)))
-        npdt = np.uint64 if Fs[0].dtype == torch.uint64 else np.uint32
-        Ps = [torch.from_numpy(_trim_host(P).astype(npdt)).to(Fs[0].device) for P, _ in res]
+        Ps, rds = [None] * len(Fs), [None] * len(Fs)
+        shapes = {}
+        for i, F in enumerate(Fs):
+            shapes.setdefault((F.shape[1], F.shape[2]), []).append(i)
+        groups, host = [], []
+        for idx in shapes.values():
+            if self._device_leaf(Fs[idx[0]], sigma, len(idx)):
+                groups.append(idx)
+            else:
+                host.extend(idx)
+        host.sort()
+        for idx in groups:
+            P, rd = self._device_leaves([Fs[i] for i in idx], sigma, [ss[i] for i in idx])
+            for j, i in enumerate(idx):
+                Ps[i], rds[i] = P[j], rd[j]
+        if host:
+            hosts = [Fs[i][:sigma].to("cpu").numpy().astype(np.uint64) for i in host]
+            if self.pool is None:
+                self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.workers)
+            res = list(self.pool.map(lambda a: _b.pm_mbasis_host(self.p, a[0], sigma, a[1]),
+                                     zip(hosts, [ss[i] for i in host])))
+            npdt = np.uint64 if Fs[0].dtype == torch.uint64 else np.uint32
+            for i, (P, rd) in zip(host, res):
+                Ps[i] = torch.from_numpy(_trim_host(P).astype(npdt)).to(Fs[i].device)
+                rds[i] = rd
         self.leaves += len(Fs)
         self.leaf_seconds += time.perf_counter() - t0
-        return Ps, [rd for _, rd in res]
+        return Ps, rds
 
     def _run_many(self, Fs, sigma: int, ss):
         if sigma <= self.T:

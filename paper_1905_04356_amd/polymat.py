@@ -166,6 +166,38 @@ def mul_vdm(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
     return out
 
 
+def mbasis_fits(p: int, m: int, n: int, sigma: int) -> bool:
+    """Whether pm_mbasis_u32 takes this shape and modulus."""
+    return 2 <= p < (1 << 31) and _b.pm_mbasis_workspace_bytes(1, m, n, sigma) is not None
+
+
+def mbasis(p: int, F: torch.Tensor, sigma: int, shifts: torch.Tensor,
+           workspace: Workspace | None = None, stream=None):
+    """Algorithm M-Basis on the device (pm_mbasis_u32) for a stack of
+    instances: F (count, >= sigma, m, n) uint32 residues, shifts (count, m)
+    int64 on the device -> (P (count, sigma+1, m, m) uint32, rdeg (count, m)
+    int64), the same as pm_mbasis_host instance by instance."""
+    if F.dim() != 4 or F.dtype != torch.uint32 or not F.is_cuda:
+        raise ValueError("F must be a (count, >= sigma, m, n) uint32 GPU tensor")
+    count, _, m, n = F.shape
+    F = F[:, :sigma].contiguous()
+    shifts = shifts.to(device=F.device, dtype=torch.int64).contiguous()
+    if tuple(shifts.shape) != (count, m):
+        raise ValueError("shifts must be (count, m)")
+    P = torch.empty((count, sigma + 1, m, m), dtype=torch.uint32, device=F.device)
+    rd = torch.empty((count, m), dtype=torch.int64, device=F.device)
+    need = _b.pm_mbasis_workspace_bytes(count, m, n, sigma)
+    if need is None:
+        raise _b.PmError(_b.PM_EUNSUPPORTED, "pm_mbasis_u32")
+    ws = (workspace or _workspace(F.device)).get(need)
+    st = _b.lib().pm_mbasis_u32(p, count, m, n, sigma, F.data_ptr(), sigma * m * n,
+                                shifts.data_ptr(), P.data_ptr(), rd.data_ptr(), ws.data_ptr(),
+                                ws.numel(), _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_mbasis_u32")
+    return P, rd
+
+
 def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
     """Evaluations of one operand (role 0: left factor A, 1: right factor B)
     as a device byte tensor, reusable by every product with the same p,

@@ -216,3 +216,28 @@ def test_plan_reports_the_wrapped_form(m, n, k, d, j):
     """pm_plan's wrap_log2_len follows the rule pm_mul applies: wrap only
     large products whose top t = 2d - 1 - 2^j is at most 2^j / 4."""
     assert B.pm_plan(998244353, m, n, k, d, 4).wrap_log2_len == j
+
+
+def test_device_mbasis_argument_checks():
+    """pm_mbasis_u32 and its workspace query reject bad arguments before any
+    device work."""
+    assert B.pm_mbasis_workspace_bytes(3, 5, 2, 4) == 4 * 3 * 5 * 2 * 4
+    assert B.pm_mbasis_workspace_bytes(1, 256, 128, 2) is None        # LDS too small
+    lib = B.lib()
+    one = ctypes.c_void_p(16)
+    for p, count, m, n, sigma, want in [((1 << 31) + 11, 1, 2, 1, 1, B.PM_ERANGE),
+                                        (1, 1, 2, 1, 1, B.PM_ERANGE),
+                                        (97, 0, 2, 1, 1, B.PM_EINVAL),
+                                        (97, 1, 0, 1, 1, B.PM_EINVAL),
+                                        (97, 1, 2, 1, 0, B.PM_EINVAL)]:
+        got = lib.pm_mbasis_u32(p, count, m, n, sigma, one, 1 << 20, one, one, one, one,
+                                1 << 20, None)
+        assert got == want, (p, count, m, n, sigma)
+    # a workspace that is too small or misaligned
+    assert lib.pm_mbasis_u32(97, 1, 2, 1, 1, one, 2, one, one, one, ctypes.c_void_p(256), 4,
+                             None) == B.PM_EWORKSPACE
+    assert lib.pm_mbasis_u32(97, 1, 2, 1, 1, one, 2, one, one, one, ctypes.c_void_p(8), 1 << 20,
+                             None) == B.PM_EWORKSPACE
+    # a stride shorter than one instance
+    assert lib.pm_mbasis_u32(97, 1, 2, 1, 3, one, 5, one, one, one, ctypes.c_void_p(256),
+                             1 << 20, None) == B.PM_EINVAL

@@ -122,3 +122,30 @@ def test_middle_batched_equals_single_windows():
         for A, B, (lo, ln), g in zip(As, Bs, wins, got):
             assert torch.equal(g, polymat.middle(p, A, B, lo, ln)), (rep, lo, ln)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p,sigma,m,n,shift,T", [
+    (P30, 13, 4, 2, [0, 0, 0, 0], 2),
+    (P31, 21, 4, 2, [3, -1, 0, 2], 4),
+    (97, 17, 3, 2, [0, 5, 1], 3),
+    (786433, 64, 32, 16, [0] * 32, 8),
+])
+def test_pmbasis_device_leaves_equal_host_leaves(p, sigma, m, n, shift, T):
+    """Leaves on the device (pm_mbasis_u32) give the same basis as leaves on
+    the host, for one instance and for a lockstep family of two shapes."""
+    say(f"[pmbasis] device leaves p={p} sigma={sigma} m={m} n={n} T={T}")
+    F = torch.from_numpy(series(p, sigma, m, n, seed=sigma + 3 * m)).cuda()
+    dev = PB.PMBasis(p, T, device_leaf_min=1)
+    Pd, rdd = dev(F, sigma, shift)
+    Ph, rdh = PB.PMBasis(p, T, device_leaf_min=1 << 30)(F, sigma, shift)
+    assert dev.leaves > 0 and Pd.shape == Ph.shape and torch.equal(Pd, Ph) and rdd == rdh
+    if m <= 5:
+        ref = X.pmbasis(F.cpu().numpy().astype(object), sigma, shift, p, T)
+        assert np.array_equal(Pd.cpu().numpy().astype(object), ref)
+    G = torch.from_numpy(series(p, sigma, m + 1, n, seed=7)).cuda()
+    fam = [F, G, F.flip(1).contiguous(), G]
+    shifts = [shift, [0] * (m + 1), shift[::-1], [1] * (m + 1)]
+    many = PB.PMBasisMany(p, T, device_leaf_min=2)(fam, sigma, shifts)
+    for Fi, si, (P, rd) in zip(fam, shifts, many):
+        P1, rd1 = PB.PMBasis(p, T, device_leaf_min=1 << 30)(Fi, sigma, si)
+        assert P.shape == P1.shape and torch.equal(P, P1) and rd == rd1
