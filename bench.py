@@ -350,8 +350,8 @@ def bench_wrap(p=998244353, seed=10, reps=10):
     """Degrees where 2d - 1 lies just above a power of two: pm_mul, which takes
     the wrapped form (cyclic product on 2^j points, short product for the
     top coefficients, correction) when the top is small and the product
-    large, against the plain 2^(j+1)-point transforms (a one-product
-    pm_mul_batched call), same operands, outputs compared."""
+    large, against the plain 2^(j+1)-point transforms (pm_middle over the
+    whole window), same operands, outputs compared."""
     import torch
     from paper_1905_04356_amd import binding as Bd
     from paper_1905_04356_amd import inputs as I
@@ -380,7 +380,8 @@ def bench_wrap(p=998244353, seed=10, reps=10):
             return e0.elapsed_time(e1) / reps
 
         t_w = timed(lambda: polymat.mul(p, A, B, out=ow, workspace=ws, stream=stream))
-        t_p = timed(lambda: polymat.mul_batched(p, [A], [B], [op], workspace=ws, stream=stream))
+        t_p = timed(lambda: polymat.middle(p, A, B, 0, 2 * d - 1, out=op, workspace=ws,
+                                           stream=stream))
         # in direct mode only the wrap's correction kernel is timed as CRT
         Bd.pm_profile_begin()
         polymat.mul(p, A, B, out=ow, workspace=ws, stream=stream)

@@ -677,6 +677,44 @@ int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_
   return PM_OK;
 }
 
+// Corrections of the wrapped products of a batch (as in run_wrapped).
+struct UnwrapJob {
+  void* C;
+  uint64_t count, off, p;
+  int elem_bytes;
+};
+
+// The entries a batch runs: a whole product that pm_mul computes in the
+// wrapped form (and that carries no precomputed evaluations, which are at
+// the plain length) becomes two, the cyclic product into C and the product
+// of the tops into C's rows 2^j .., plus a correction after the batch;
+// other products stay as they are.
+void expand_wrapped(const std::vector<Plan>& plans, const pm_product* prods, int eb,
+                    std::vector<Plan>* xplans, std::vector<pm_product>* xprods,
+                    std::vector<UnwrapJob>* jobs) {
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan& P = plans[i];
+    const pm_product& pr = prods[i];
+    Plan Pc, Pt;
+    const int j = (pr.A_eval || pr.B_eval) ? 0 : wrap_log_plans(P, &Pc, &Pt);
+    if (!j) {
+      xplans->push_back(P);
+      xprods->push_back(pr);
+      continue;
+    }
+    const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp, h = Lp - d + 1;
+    const uint64_t mk = (uint64_t)P.m * P.k;
+    xplans->push_back(Pc);
+    xprods->push_back(pm_product{P.m, P.n, P.k, d, pr.A, pr.B, pr.C, nullptr, nullptr});
+    xplans->push_back(Pt);
+    xprods->push_back(pm_product{P.m, P.n, P.k, 0,
+                                 (const uint8_t*)pr.A + (uint64_t)eb * h * P.m * P.n,
+                                 (const uint8_t*)pr.B + (uint64_t)eb * h * P.n * P.k,
+                                 (uint8_t*)pr.C + (uint64_t)eb * Lp * mk, nullptr, nullptr});
+    jobs->push_back(UnwrapJob{pr.C, (uint64_t)t * mk, (uint64_t)Lp * mk, P.p, eb});
+  }
+}
+
 // Plans of a batch of coefficient windows (pm_window_product), with the
 // products re-expressed as pm_product (no precomputed evaluations) for the
 // shared launch code.
@@ -1062,11 +1100,15 @@ pm_status pm_batched_workspace_bytes(uint64_t p, int32_t count, const pm_product
                                      int32_t elem_bytes, uint64_t* out) {
   if (!out || count < 0 || (count > 0 && !prods)) return PM_EINVAL;
   try {
-    std::vector<Plan> plans;
+    std::vector<Plan> plans, xplans;
     std::vector<uint64_t> offs;
     BatchLayout lay;
     int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
     if (st != PM_OK) return (pm_status)st;
+    std::vector<pm_product> xprods;
+    std::vector<UnwrapJob> jobs;
+    expand_wrapped(plans, prods, elem_bytes, &xplans, &xprods, &jobs);
+    layout_batch(xplans, offs, &lay);
     *out = lay.total;
     return PM_OK;
   } catch (const std::bad_alloc&) {
@@ -1091,11 +1133,15 @@ static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods
                               int elem_bytes, void* ws, uint64_t ws_bytes, void* stream) {
   if (count < 0 || (count > 0 && !prods)) return PM_EINVAL;
   if (count == 0) return PM_OK;
-  std::vector<Plan> plans;
+  std::vector<Plan> plans, xplans;
   std::vector<uint64_t> offs;
   BatchLayout lay;
   int st = plan_batch(p, count, prods, elem_bytes, plans, offs, &lay);
   if (st != PM_OK) return (pm_status)st;
+  std::vector<pm_product> xprods;
+  std::vector<UnwrapJob> jobs;
+  expand_wrapped(plans, prods, elem_bytes, &xplans, &xprods, &jobs);
+  layout_batch(xplans, offs, &lay);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < lay.total) return PM_EWORKSPACE;
   for (int32_t i = 0; i < count; ++i) {
     st = check_operands(plans[i], prods[i].A, prods[i].B, prods[i].C);
@@ -1107,8 +1153,15 @@ static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods
                          eb * P.db * P.n * P.k, prods[i].C, eb * (uint64_t)P.nout * P.m * P.k);
     if (st != PM_OK) return (pm_status)st;
   }
-  return (pm_status)run_batch(p, elem_bytes, plans, offs, lay, prods, (uint8_t*)ws, ws_bytes,
-                              (hipStream_t)stream);
+  const hipStream_t s = (hipStream_t)stream;
+  st = run_batch(p, elem_bytes, xplans, offs, lay, xprods.data(), (uint8_t*)ws, ws_bytes, s);
+  if (st != PM_OK) return (pm_status)st;
+  for (const UnwrapJob& u : jobs) {
+    KernelTimer kt(K_CRT, s);
+    if (launch_unwrap(u.C, u.count, u.off, u.p, u.elem_bytes, s) != hipSuccess)
+      return PM_EDEVICE;
+  }
+  return PM_OK;
 }
 
 static pm_status window_batched_impl(uint64_t p, int32_t count,

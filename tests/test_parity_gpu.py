@@ -448,9 +448,30 @@ def test_wrapped_equals_plain_transforms():
         wrapped, took = _wrapped(p, A, B)
         assert took, d
         tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
-        plain, = polymat.mul_batched(p, [tA], [tB])      # one product: plain transforms
+        plain = polymat.middle(p, tA, tB, 0, 2 * d - 1)   # whole window: plain transforms
         torch.cuda.synchronize()
         assert np.array_equal(wrapped, plain.cpu().numpy()), d
+
+
+def test_batched_wraps_like_single_calls():
+    """A batch takes the wrapped form for the products pm_mul wraps (two
+    entries and a correction each) and plain transforms for the others."""
+    p = P30
+    shapes = [(128, 128, 64, 1100), (8, 8, 8, 100), (64, 64, 64, 2100), (64, 64, 64, 1100)]
+    As, Bs = [], []
+    for i, (m, n, k, d) in enumerate(shapes):
+        A, B = tensors(p, m, n, k, d, seed=19, product=i)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+    Bd.pm_profile_begin()
+    outs = polymat.mul_batched(p, As, Bs)
+    stats = Bd.pm_profile_end()
+    torch.cuda.synchronize()
+    assert stats["crt"][1] == 2                       # two corrections: two wrapped products
+    for (m, n, k, d), tA, tB, C in zip(shapes, As, Bs, outs):
+        plain = polymat.middle(p, tA, tB, 0, 2 * d - 1)
+        torch.cuda.synchronize()
+        assert torch.equal(C, plain), (m, n, k, d)
 
 
 def test_kernel_timing_counts_only_unpaused_launches():
