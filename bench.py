@@ -588,6 +588,52 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     print("wrote profiles for", workload)
 
 
+def summarize_batched(root, batched_calls, single_rounds):
+    """profiles/c3_batched_kernels.md from a rocprofv3 --kernel-trace run of
+    `bench.py --only-batched` under root/sb/: the batched calls' kernels (the
+    phase kernels and the corrections of wrapped products, up to the end of
+    the last phase kernel) and the one-call-per-product kernels after them,
+    as device time per call or round."""
+    import collections
+    import csv
+    import glob
+    files = glob.glob(os.path.join(root, "sb", "*kernel_trace.csv"))
+    rows = sorted(csv.DictReader(open(files[0])), key=lambda r: int(r["Start_Timestamp"]))
+    rows = [r for r in rows if "pm::" in r["Kernel_Name"]]
+    batch = [i for i, r in enumerate(rows) if "batch_kernel" in r["Kernel_Name"]]
+    first, last = batch[0], batch[-1]
+    while last + 1 < len(rows) and "unwrap_kernel" in rows[last + 1]["Kernel_Name"]:
+        last += 1
+
+    def table(sel, per):
+        agg = collections.defaultdict(lambda: [0, 0.0])
+        for r in sel:
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            agg[name][0] += 1
+            agg[name][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        out = ["| kernel | calls | ms per call or round |", "|---|---|---|"]
+        for name, (c, ms) in sorted(agg.items(), key=lambda x: -x[1][1]):
+            out.append(f"| `{name}` | {c} | {ms / per:.3f} |")
+        tot = sum(v[1] for v in agg.values()) / per
+        return out + [f"| total | | {tot:.3f} |"], tot
+
+    cmd = ("rocprofv3 --kernel-trace --output-format csv -d gpurun_out/sb -o sb -- "
+           "python3 bench.py --only-batched")
+    tb, b_ms = table(rows[first:last + 1], batched_calls)
+    ts, s_ms = table(rows[last + 1:], single_rounds)
+    md = ["# Kernel profile: c3 (512 products, one batched call vs one pm_mul per product)", "",
+          "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
+          f"Device time of the kernels per batched call ({batched_calls} calls: warm-up, "
+          "graph capture and replays) and per round of 512 single calls "
+          f"({single_rounds} rounds), from the kernel trace; the wall time per call in "
+          "bench.py's `batched` object also holds the gaps between launches.", "",
+          f"## One batched call: {b_ms:.1f} ms of kernels", ""] + tb + \
+         ["", f"## 512 single calls: {s_ms:.1f} ms of kernels", ""] + ts
+    with open(os.path.join(ROOT, "profiles", "c3_batched_kernels.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote profiles/c3_batched_kernels.md")
+
+
 def load_traffic(workload):
     """Per-step HBM bytes by kernel kind from profiles/, or None when the
     library sources changed since the counters were taken."""
@@ -661,6 +707,10 @@ def main():
                     help="length of the serving trace (0: skip)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run only the 1 GiB copy used to calibrate HBM byte counters")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched comparison (configuration 3) and print it")
+    ap.add_argument("--summarize-batched", metavar="DIR",
+                    help="write profiles/c3_batched_kernels.md from DIR/sb (rocprofv3 trace)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 CSV output in DIR")
     args = ap.parse_args()
@@ -670,10 +720,17 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, 20, 100, 3, args.workload)
         return
+    if args.summarize_batched:
+        summarize_batched(args.summarize_batched, 1 + args.batched_steps, 1 + args.batched_steps)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs every product on a single "
-              "MI355X and has no multi-GPU path (see the sharding design).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs every product on a single "
+              "MI355X and has no multi-GPU path (the sharding design is documented).",
+              file=sys.stderr)
         sys.exit(2)
+    if args.only_batched:
+        print(json.dumps(bench_batched(args.batched_steps, 1)), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -516,3 +516,20 @@ def test_block_step_pass_structures(p, m, n, k, d):
     A, B = tensors(p, m, n, k, d, seed=17)
     C = gpu_mul(p, A, B)
     sampled_check(p, A, B, C, seed=17, entries=2 if d >= 16384 else 4)
+
+
+def test_batched_wraps_crt_u64():
+    """Wrapped products inside a batch in CRT mode with 64-bit residues equal
+    single pm_mul calls (whose wrapped path is checked against the oracle)."""
+    p = (1 << 61) - 1
+    shapes = [(64, 64, 64, 2100), (4, 4, 4, 300), (64, 64, 64, 2100)]
+    As, Bs = [], []
+    for i, (m, n, k, d) in enumerate(shapes):
+        A, B = tensors(p, m, n, k, d, seed=21, dtype=np.uint64, product=i)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+    outs = polymat.mul_batched(p, As, Bs)
+    for tA, tB, C in zip(As, Bs, outs):
+        ref = polymat.mul(p, tA, tB)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref)
