@@ -91,10 +91,14 @@ __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, ui
 }
 
 // The block phases (1, 3) are held to 4 waves per SIMD so that two
-// 512-thread workgroups share a CU.
+// 512-thread workgroups share a CU; the 256-thread pointwise phase to 5,
+// as the single-product pointwise kernel runs.  The descriptors are never
+// written while a phase runs: __restrict__ lets their fields load into
+// scalar registers instead of taking vector registers in every lane.
 template <int PHASE, int NT>
-__global__ __launch_bounds__(NT, (PHASE == 1 || PHASE == 3) ? 4 : 1) void batch_kernel(const ProductLaunches* prods,
-                                                   const BatchSeg* segs, int nseg) {
+__global__ __launch_bounds__(NT, (PHASE == 1 || PHASE == 3) ? 4 : (PHASE == 2 && NT == 256) ? 5 : 1)
+void batch_kernel(const ProductLaunches* __restrict__ prods, const BatchSeg* __restrict__ segs,
+                  int nseg) {
   extern __shared__ uint32_t lds[];
   const uint32_t b = blockIdx.x;
   const BatchSeg g = segs[find_segment(segs, nseg, b)];
