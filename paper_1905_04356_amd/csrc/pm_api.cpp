@@ -796,16 +796,28 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
       const double x = v && *v ? atof(v) : 8192.0;
       return x < 1.0 ? 1.0 : x;
     }();
+    // pipelined tiles (limb planes above the 256-thread limit): about
+    // PM_TUNE_BATCH_PW_PIPE_PTS (default 16) points each, so that a
+    // workgroup's loads run ahead of its products
+    static const double pipe_pts = [] {
+      const char* v = getenv("PM_TUNE_BATCH_PW_PIPE_PTS");
+      const double x = v && *v ? atof(v) : 16.0;
+      return x < 1.0 ? 1.0 : x;
+    }();
     const double mnk = (double)P.m * P.n * P.k;
+    size_t need = 0;
+    if (L.pointwise == 1) need = pointwise_mfma_lds(P.m, P.n, P.k);
+    else if (L.pw_staged) need = 4ull * ((uint64_t)P.m * P.n + (uint64_t)P.n * P.k);
+    const int pipe = L.pointwise == 1 && need > pointwise_small_lds()
+                         ? pointwise_pipe_variant(P.m, P.n, P.k) : 0;
     uint32_t z = (uint32_t)(pw_work / mnk);
+    if (pipe && z < (uint32_t)pipe_pts) z = (uint32_t)pipe_pts;
     if (z < 1) z = 1;
     if (z > L_) z = L_;
     if (z > 65535) z = 65535;
     const uint32_t nt = (L_ + z - 1) / z;
-    size_t need = 0;
-    if (L.pointwise == 1) need = pointwise_mfma_lds(P.m, P.n, P.k);
-    else if (L.pw_staged) need = 4ull * ((uint64_t)P.m * P.n + (uint64_t)P.n * P.k);
-    for (int q = 0; q < P.r; ++q) add(2, BK_PW, 0, q, nt, nt, z * mnk, need, (uint16_t)z);
+    for (int q = 0; q < P.r; ++q)
+      add(pipe == 2 ? 6 : 2, BK_PW, pipe == 1 ? 1 : 0, q, nt, nt, z * mnk, need, (uint16_t)z);
   }
   {
     const NttLaunch& a = L.inv;
@@ -849,7 +861,7 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
   B->groups.clear();
   ProductLaunches* hp = (ProductLaunches*)B->host.data();
   std::vector<HostSeg> ph[kBatchPhases];
-  size_t lds[kBatchPhases] = {0, 0, 0, 0, 0, 0};  // unused: LDS is tracked per segment
+  size_t lds[kBatchPhases] = {};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
     const Plan& P = plans[i];
     int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i],
@@ -873,7 +885,8 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
   // counts; one launch per non-empty (phase, class).
   BatchSeg* hs = (BatchSeg*)(B->host.data() + (lay.seg_off - lay.prod_off));
   uint64_t seg_base = 0;
-  for (int f = 0; f < kBatchPhases; ++f) {
+  for (int fo = 0; fo < kBatchPhases; ++fo) {
+    const int f = kBatchPhaseOrder[fo];
     std::vector<HostSeg> cls[kLdsClasses];
     for (auto& h : ph[f]) cls[lds_class(h.lds)].push_back(h);
     for (int c = 0; c < kLdsClasses; ++c) {
@@ -902,8 +915,8 @@ int enqueue_batch(const BatchBuild& B, const void* host_src, const BatchLayout& 
     return PM_EDEVICE;
   const ProductLaunches* dprods = (const ProductLaunches*)(ws + lay.prod_off);
   const BatchSeg* dsegs = (const BatchSeg*)(ws + lay.seg_off);
-  static const int kind_of_phase[kBatchPhases] = {K_NTT_FWD, K_NTT_FWD, K_POINTWISE,
-                                                  K_NTT_INV, K_NTT_INV, K_CRT};
+  static const int kind_of_phase[kBatchPhases] = {K_NTT_FWD, K_NTT_FWD, K_POINTWISE, K_NTT_INV,
+                                                  K_NTT_INV, K_CRT,     K_POINTWISE};
   KernelTimer kt(K_BATCHED, s, true);
   for (const BatchGroup& G : B.groups) {
     KernelTimer kp(kind_of_phase[G.phase], s);

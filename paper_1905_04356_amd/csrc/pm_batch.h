@@ -35,13 +35,17 @@ enum BatchKind : uint16_t {
   BK_FWD_LDS = 0,    // phase 0: unsplit forward transform, x = entry block
   BK_COL_FWD = 1,    // phase 0: column pass, x = item chunk
   BK_BLOCK_FWD = 2,  // phase 1: split forward LDS block, x = entry block, z = position block
-  BK_PW = 3,         // phase 2: points [x * z, x * z + z)
+  BK_PW = 3,         // phase 2 (or 6): points [x * z, x * z + z)
   BK_BLOCK_INV = 4,  // phase 3: split inverse LDS block
   BK_INV_LDS = 5,    // phase 4: unsplit inverse transform
   BK_COL_INV = 6,    // phase 4: column pass of a split inverse
   BK_CRT = 7,        // phase 5: outputs [x * kCrtChunk, ...)
 };
-constexpr int kBatchPhases = 6;
+// Phase 6 holds the pointwise tiles of products that take the pipelined
+// kernel with 8 A groups per thread (its own launch: its registers allow one
+// workgroup per CU); it runs after phase 2, before phase 3.
+constexpr int kBatchPhases = 7;
+constexpr int kBatchPhaseOrder[kBatchPhases] = {0, 1, 2, 6, 3, 4, 5};
 constexpr int kBatchNT = 512;
 constexpr uint32_t kColChunk = 4096;
 constexpr uint32_t kCrtChunk = 8192;
@@ -52,7 +56,7 @@ struct BatchSeg {
   uint32_t first;   // index of the segment's first tile within its phase
   uint32_t prod;
   uint32_t nx;
-  uint16_t kind, op;
+  uint16_t kind, op;      // op: operand (transforms); pipelined variant (pointwise)
   uint16_t prime, zpts;  // zpts: points per pointwise tile
 };
 

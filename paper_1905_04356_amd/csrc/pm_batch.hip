@@ -112,10 +112,18 @@ void batch_kernel(const ProductLaunches* __restrict__ prods, const BatchSeg* __r
     else phase0<uint32_t, false>(a, g, x, lds);
   } else if (PHASE == 1) {
     block_v<true>(P.f[g.op], g.prime, x, z, lds);
-  } else if (PHASE == 2) {
+  } else if (PHASE == 2 || PHASE == 6) {
     const uint32_t t0 = x * g.zpts;
     uint32_t t1 = t0 + g.zpts;
     if (t1 > (uint32_t)P.pw.L) t1 = P.pw.L;
+    if (PHASE == 6) {
+      pointwise_mfma_pipe_any<NT, 8, 2>(P.pw, g.prime, t0, t1, 1, lds);
+      return;
+    }
+    if (NT == kBatchNT && g.op == 1) {
+      pointwise_mfma_pipe_any<NT, 4, 1>(P.pw, g.prime, t0, t1, 1, lds);
+      return;
+    }
     for (uint32_t t = t0; t < t1; ++t) {
       if (P.pointwise == 1) pointwise_mfma_tile(P.pw, t, g.prime, lds);
       else if (P.pw_staged) pointwise_valu_tile<true>(P.pw, t, g.prime, lds);
@@ -127,7 +135,7 @@ void batch_kernel(const ProductLaunches* __restrict__ prods, const BatchSeg* __r
   } else if (PHASE == 4) {
     if (P.mode == 1 || P.elem_bytes == 4) phase4<uint32_t>(P.inv, g, x, lds);
     else phase4<uint64_t>(P.inv, g, x, lds);
-  } else {
+  } else if (PHASE == 5) {
     const uint64_t i0 = (uint64_t)x * kCrtChunk;
     if (P.elem_bytes == 8)
       crt_range<uint64_t>(P.crt, i0 + threadIdx.x, i0 + kCrtChunk, kBatchNT);
@@ -165,6 +173,7 @@ int launch_batch_phase(int phase, const ProductLaunches* prods, const BatchSeg* 
       return launch_phase_t<2, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 3: return launch_phase_t<3, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 4: return launch_phase_t<4, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
+    case 6: return launch_phase_t<6, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     default: return launch_phase_t<5, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
   }
 }

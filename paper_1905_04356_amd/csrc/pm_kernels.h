@@ -87,6 +87,7 @@ int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 size_t pointwise_mfma_lds(int m, int n, int k);
 // Largest pointwise LDS footprint launched with 256 threads (larger: 512).
 size_t pointwise_small_lds();
+int pointwise_pipe_variant(int m, int n, int k);
 int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s);
 int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_bytes,
                           unsigned long long* counter, hipStream_t s);

@@ -5,6 +5,8 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
+
 namespace pm {
 
 template <bool STAGED>
@@ -17,6 +19,12 @@ template <int NT>
 __global__ __launch_bounds__(NT) void pointwise_mfma_kernel(PointwiseLaunch a) {
   extern __shared__ uint32_t smem[];
   pointwise_mfma_tile(a, blockIdx.x, blockIdx.y, smem);
+}
+
+template <int NT, int PA, int PB>
+__global__ __launch_bounds__(NT) void pointwise_mfma_pipe_kernel(PointwiseLaunch a) {
+  extern __shared__ uint32_t smem[];
+  pointwise_mfma_pipe_any<NT, PA, PB>(a, blockIdx.y, blockIdx.x, a.L, gridDim.x, smem);
 }
 
 int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
@@ -52,11 +60,62 @@ size_t pointwise_small_lds() {
   return v;
 }
 
+// Pipelined-kernel variant for a shape with 512 threads: 1 (4 A groups and
+// one B block per thread: 122 VGPRs, two workgroups per CU), 2 (8 and 2:
+// 154 VGPRs, one), or 0 when the shape needs more registers or k is not a
+// multiple of 4.  Tuning knob PM_TUNE_PW_PIPE: 0 never pipelines, 1 or 2
+// forces that variant where it suffices.
+int pointwise_pipe_variant(int m, int n, int k) {
+  static const int knob = [] {
+    const char* e = getenv("PM_TUNE_PW_PIPE");
+    return e && *e ? atoi(e) : -1;
+  }();
+  if (knob == 0 || k % 4 != 0) return 0;
+  const long mp = (m + 15) & ~15, kp = (k + 15) & ~15, ng = ((n + 63) & ~63) >> 2;
+  const long need_a = (mp * ng + 511) / 512, need_b = (ng * (kp / 4) + 511) / 512;
+  const bool small = need_a <= 4 && need_b <= 1, big = need_a <= 8 && need_b <= 2;
+  if (knob == 1) return small ? 1 : 0;
+  if (knob == 2) return big ? 2 : 0;
+  return small ? 1 : big ? 2 : 0;
+}
+
+namespace {
+int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cus;
+}
+
+// One resident workgroup per slot of the chip, each running every
+// gridDim.x-th point.
+template <int PA, int PB>
+int launch_pipe(const PointwiseLaunch& a, int nprimes, size_t lds, hipStream_t s) {
+  const void* fn = (const void*)pointwise_mfma_pipe_kernel<512, PA, PB>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, lds);
+  if (e != hipSuccess) return e;
+  const int cus = cu_count();
+  if (per_cu < 1 || cus < 1) return hipErrorInvalidValue;
+  const long g = std::min<long>(a.L, (long)per_cu * cus);
+  return launch(pointwise_mfma_pipe_kernel<512, PA, PB>, dim3((unsigned)g, nprimes), dim3(512),
+                lds, s, a);
+}
+}  // namespace
+
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   const size_t lds = pointwise_mfma_lds(a.m, a.n, a.k);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds <= pointwise_small_lds()) {
     return launch(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
+  }
+  switch (pointwise_pipe_variant(a.m, a.n, a.k)) {
+    case 1: return launch_pipe<4, 1>(a, nprimes, lds, s);
+    case 2: return launch_pipe<8, 2>(a, nprimes, lds, s);
+    default: break;
   }
   hipError_t e = hipFuncSetAttribute((const void*)pointwise_mfma_kernel<512>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -134,27 +134,16 @@ __device__ __forceinline__ void stage_limbs(const uint32_t* A, const uint32_t* B
   }
 }
 
-__device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, int t, int prime,
-                                                    uint32_t* smem) {
+// The products of point t from the limb planes in LDS: 16x16 output tiles
+// spread over the workgroup's waves, recombined, reduced and stored.
+__device__ __forceinline__ void mfma_point(const PointwiseLaunch& a, int t, int prime,
+                                           const uint8_t* As, const uint8_t* Bs, int mp, int kp,
+                                           int np, int rs) {
   const PrimeConst& P = a.pc[prime];
-  const uint32_t q = P.q, half_q = P.q >> 1;
-  const int m = a.m, n = a.n, k = a.k;
-  const int mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
-  const int rs = np + 16;                   // bytes per LDS row (padded)
-  uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
-  uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]
-  const uint32_t* A = a.ahat + a.a_prime_stride * prime + (size_t)t * ((size_t)m * n);
-  const uint32_t* B = a.bhat + a.b_prime_stride * prime + (size_t)t * ((size_t)n * k);
+  const uint32_t q = P.q;
+  const int m = a.m, k = a.k;
   uint32_t* C = a.chat + a.prime_stride * prime + (size_t)t * ((size_t)m * k);
-  const int nt = blockDim.x;
-  const int ng = np >> 2;                   // groups of 4 contraction indices (multiple of 16)
-  if (q <= 0x7F7F7F7Fu)
-    stage_limbs<false>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
-  else
-    stage_limbs<true>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = nt >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int tiles_m = mp >> 4, tiles = tiles_m * (kp >> 4);
   const int lr = lane & 15, lk = (lane >> 4) * 16;
   // c_s < q < 2^31, so each weight is a non-negative int32 and each term a
@@ -198,6 +187,209 @@ __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, in
       if (i < m && j < k) C[i * k + j] = v;
     }
   }
+}
+
+__device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, int t, int prime,
+                                                    uint32_t* smem) {
+  const PrimeConst& P = a.pc[prime];
+  const uint32_t q = P.q, half_q = P.q >> 1;
+  const int m = a.m, n = a.n, k = a.k;
+  const int mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
+  const int rs = np + 16;                   // bytes per LDS row (padded)
+  uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
+  uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]
+  const uint32_t* A = a.ahat + a.a_prime_stride * prime + (size_t)t * ((size_t)m * n);
+  const uint32_t* B = a.bhat + a.b_prime_stride * prime + (size_t)t * ((size_t)n * k);
+  const int ng = np >> 2;                   // groups of 4 contraction indices (multiple of 16)
+  if (q <= 0x7F7F7F7Fu)
+    stage_limbs<false>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
+  else
+    stage_limbs<true>(A, B, As, Bs, m, n, k, mp, kp, ng, rs, q, half_q);
+  __syncthreads();
+  mfma_point(a, t, prime, As, Bs, mp, kp, np, rs);
+}
+
+// ---- pipelined int8-MFMA variant --------------------------------------------
+//
+// Where the limb planes leave only one to three workgroups on a CU, a
+// workgroup that loads, converts, multiplies and stores one point after the
+// other leaves HBM idle while its matrix cores work.  Here a workgroup runs
+// a sequence of points and the residues of the next point are already on
+// their way into registers while the matrix cores work on this one.  Each
+// thread owns the same items at every point: up to PA 16-byte groups of A
+// (row i, contraction indices 4g .. 4g + 3; consecutive threads take
+// consecutive groups of a row) and up to PB 4 x 4 blocks of B (rows
+// 4g .. 4g + 3, columns 4h .. 4h + 3, one 16-byte load per row; 16
+// consecutive threads take consecutive g, and 4 such groups consecutive h,
+// so that a wave reads 64-byte runs of 16 rows and its transposed LDS
+// stores hit 64 distinct banks).  B's row length k must be a multiple of 4.
+// The barriers between the phases order only LDS accesses, so they do not
+// wait for those loads.
+
+// Barrier for the workgroup's LDS accesses only; global loads in flight stay
+// in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// x, hidden from the optimiser: the slot coordinates derived from it are
+// recomputed at each point instead of being kept live across the loop in
+// registers (a handful of ALU operations against 2-4 registers per slot).
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// One point's items of this thread in registers.
+template <int PA, int PB>
+struct PipeRegs {
+  uint4 a[PA];
+  uint4 b[PB][4];
+};
+
+// Item coordinates.  A item f = i ng + g; B item f = 64 (hh G16 + gh) + 16 hl
+// + gl with g = 16 gh + gl, h = 4 hh + hl (G16 = ng / 16).  The quotients
+// take one high multiply: for divisors 2 <= D < 2^12, floor(f ceil(2^32 /
+// D) / 2^32) = floor(f / D) as long as f D < 2^32 (here f < 2^13).  D = 1
+// (G16 when ng = 16) has no 32-bit multiplier and is taken apart.
+struct PipeShape {
+  int m, n, k, mp, kp, ng, rs;
+  uint32_t na, nb, g16, rng, rg16;
+  __device__ __forceinline__ PipeShape(int m_, int n_, int k_)
+      : m(m_), n(n_), k(k_), mp((m_ + 15) & ~15), kp((k_ + 15) & ~15),
+        ng(((n_ + 63) & ~63) >> 2), rs(((n_ + 63) & ~63) + 16) {
+    na = mp * ng;
+    nb = ng * (kp >> 2);
+    g16 = ng >> 4;
+    rng = 0xFFFFFFFFu / (uint32_t)ng + 1;
+    rg16 = g16 > 1 ? 0xFFFFFFFFu / g16 + 1 : 0u;
+  }
+  __device__ __forceinline__ void a_item(uint32_t f, uint32_t& i, uint32_t& l0) const {
+    i = __umulhi(f, rng);
+    l0 = (f - i * ng) * 4;
+  }
+  __device__ __forceinline__ void b_item(uint32_t f, uint32_t& l0, uint32_t& j0) const {
+    const uint32_t r = f >> 6, hh = g16 == 1 ? r : __umulhi(r, rg16), gh = r - hh * g16;
+    l0 = (gh * 16 + (f & 15)) * 4;
+    j0 = (hh * 4 + ((f >> 4) & 3)) * 4;
+  }
+};
+
+// Every slot issues its loads (an item outside the matrices reads element
+// 0 and is zeroed when staged), so the number of loads in flight is a
+// compile-time constant and a wait for one buffer never waits for the
+// loads issued after it.
+template <int NT, int PA, int PB>
+__device__ __forceinline__ void pipe_load(PipeRegs<PA, PB>& r, const PipeShape& S,
+                                          const uint32_t* A, const uint32_t* B) {
+  const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+  for (int s = 0; s < PA; ++s) {
+    const uint32_t f = tid + s * NT;
+    uint32_t i, l0;
+    S.a_item(f, i, l0);
+    const bool ok = f < S.na && i < (uint32_t)S.m && l0 < (uint32_t)S.n;
+    r.a[s] = *(const uint4*)(A + (ok ? i * (uint32_t)S.n + l0 : 0u));
+  }
+#pragma unroll
+  for (int s = 0; s < PB; ++s) {
+    const uint32_t f = tid + s * NT;
+    uint32_t l0, j0;
+    S.b_item(f, l0, j0);
+    const bool ok = f < S.nb && j0 < (uint32_t)S.k && l0 < (uint32_t)S.n;
+    const uint32_t o = ok ? l0 * (uint32_t)S.k + j0 : 0u, dk = ok ? (uint32_t)S.k : 0u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r.b[s][c] = *(const uint4*)(B + (o + c * dk));
+  }
+}
+
+// Limb planes of the point held in r, written to LDS (items outside the
+// matrices as zeros).
+template <bool CENTER, int NT, int PA, int PB>
+__device__ __forceinline__ void pipe_stage(const PipeRegs<PA, PB>& r, const PipeShape& S,
+                                           uint8_t* As, uint8_t* Bs, uint32_t q,
+                                           uint32_t half_q) {
+  const uint32_t tid = opaque(threadIdx.x);
+#pragma unroll
+  for (int s = 0; s < PA; ++s) {
+    const uint32_t f = tid + s * NT;
+    if (f < S.na) {
+      uint32_t i, l0;
+      S.a_item(f, i, l0);
+      const bool ok = i < (uint32_t)S.m && l0 < (uint32_t)S.n;
+      uint32_t in[4] = {ok ? limbs_of<CENTER>(r.a[s].x, q, half_q) : 0u,
+                        ok ? limbs_of<CENTER>(r.a[s].y, q, half_q) : 0u,
+                        ok ? limbs_of<CENTER>(r.a[s].z, q, half_q) : 0u,
+                        ok ? limbs_of<CENTER>(r.a[s].w, q, half_q) : 0u};
+      uint32_t out[4];
+      transpose4x4(in, out);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * S.mp + i) * S.rs + l0) = out[pl];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PB; ++s) {
+    const uint32_t f = tid + s * NT;
+    if (f < S.nb) {
+      uint32_t l0, j0;
+      S.b_item(f, l0, j0);
+      const bool ok = j0 < (uint32_t)S.k && l0 < (uint32_t)S.n;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {  // column j0 + cc: its rows l0 .. l0 + 3
+        uint32_t in[4], out[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t w = cc == 0 ? r.b[s][c].x : cc == 1 ? r.b[s][c].y
+                           : cc == 2 ? r.b[s][c].z : r.b[s][c].w;
+          in[c] = ok ? limbs_of<CENTER>(w, q, half_q) : 0u;
+        }
+        transpose4x4(in, out);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          *(uint32_t*)(Bs + (pl * S.kp + j0 + cc) * S.rs + l0) = out[pl];
+      }
+    }
+  }
+}
+
+// Points t0, t0 + ts, ... below t1; the next point loads while the matrix
+// cores work on this one.  (A second register buffer, so that the load
+// starts before this point's limb planes are written, measured no faster.)
+template <bool CENTER, int NT, int PA, int PB>
+__device__ __forceinline__ void pointwise_mfma_pipe(const PointwiseLaunch& a, int prime,
+                                                    uint32_t t0, uint32_t t1, uint32_t ts,
+                                                    uint32_t* smem) {
+  const uint32_t q = a.pc[prime].q, half_q = q >> 1;
+  const PipeShape S(a.m, a.n, a.k);
+  const int np = S.ng * 4;
+  uint8_t* As = (uint8_t*)smem;
+  uint8_t* Bs = As + 4 * S.mp * S.rs;
+  const uint32_t* A0 = a.ahat + a.a_prime_stride * prime;
+  const uint32_t* B0 = a.bhat + a.b_prime_stride * prime;
+  const size_t mn = (size_t)a.m * a.n, nk = (size_t)a.n * a.k;
+  if (t0 >= t1) return;
+  PipeRegs<PA, PB> r;
+  pipe_load<NT>(r, S, A0 + t0 * mn, B0 + t0 * nk);
+  for (uint32_t t = t0; t < t1; t += ts) {
+    lds_barrier();  // the previous point's products have read the planes
+    pipe_stage<CENTER, NT>(r, S, As, Bs, q, half_q);
+    lds_barrier();
+    if (t + ts < t1) pipe_load<NT>(r, S, A0 + (t + ts) * mn, B0 + (t + ts) * nk);
+    mfma_point(a, t, prime, As, Bs, S.mp, S.kp, np, S.rs);
+  }
+}
+
+// The pipelined kernel for a shape: 1 (PA = 4, PB = 1), 2 (8, 2).
+template <int NT, int PA, int PB>
+__device__ __forceinline__ void pointwise_mfma_pipe_any(const PointwiseLaunch& a, int prime,
+                                                        uint32_t t0, uint32_t t1, uint32_t ts,
+                                                        uint32_t* smem) {
+  if (a.pc[prime].q <= 0x7F7F7F7Fu)
+    pointwise_mfma_pipe<false, NT, PA, PB>(a, prime, t0, t1, ts, smem);
+  else
+    pointwise_mfma_pipe<true, NT, PA, PB>(a, prime, t0, t1, ts, smem);
 }
 
 }  // namespace pm

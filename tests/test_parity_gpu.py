@@ -194,6 +194,26 @@ def test_pointwise_variants_match_oracle(p, m, n, k, d, monkeypatch):
     full_check(p, m, n, k, d, seed=11)
 
 
+@pytest.mark.parametrize("p,m,n,k,d", [
+    (P30, 128, 8, 128, 2048),    # 4 A groups + 1 B block per thread; ng = 16, 32 block columns
+    (P31, 128, 128, 128, 2048),  # 8 A groups + 2 B blocks per thread
+    (P30, 96, 36, 112, 1500),    # contraction padded 36 -> 64
+    (P31, 121, 20, 4, 1100),     # rows padded 121 -> 128, 4 columns
+    (P30, 40, 200, 24, 700),     # ng = 64: four 16-group bands per block column
+    (P32, 128, 32, 64, 600),     # three CRT primes (one grid row each)
+])
+def test_pipelined_pointwise_long_sequences(p, m, n, k, d):
+    """Limb planes above 44 KiB take the pipelined MFMA kernel, whose
+    workgroups each run a sequence of points (here 3-16 per workgroup)
+    while the next point loads; outputs against the oracle."""
+    info = Bd.pm_plan(p, m, n, k, d, 4)
+    assert info.pointwise == 1
+    say(f"[parity] pipelined pointwise p={p} m={m} n={n} k={k} d={d}")
+    A, B = tensors(p, m, n, k, d, seed=13)
+    C = gpu_mul(p, A, B)
+    sampled_check(p, A, B, C, seed=13, entries=3)
+
+
 def test_mfma_limb_extremes():
     """Residues at the centring boundary ((q-1)/2, (q+1)/2), 0, 1, q-1 in every
     position exercise the largest limb magnitudes."""
