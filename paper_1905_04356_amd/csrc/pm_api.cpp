@@ -867,8 +867,10 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
     int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i],
                                    true);
     if (st != PM_OK) return st;
-    // the phase kernels run column items of one entry (register budget)
-    hp[i].f[0].col_vec = hp[i].f[1].col_vec = hp[i].inv.col_vec = 1;
+    // the phase kernels run column items of at most two entries (register
+    // budget: two workgroups per CU)
+    for (NttLaunch* a : {&hp[i].f[0], &hp[i].f[1], &hp[i].inv})
+      if (a->col_vec > 2) a->col_vec = 2;
     // given evaluations replace the forward transforms of that operand
     if (prods[i].A_eval) {
       hp[i].pw.ahat = (const uint32_t*)prods[i].A_eval;

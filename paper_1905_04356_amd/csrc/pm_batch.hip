@@ -32,6 +32,20 @@ __device__ __forceinline__ int find_segment(const BatchSeg* segs, int nseg, uint
   return lo;
 }
 
+// Column items of 1 or 2 consecutive entries (2 where the descriptor's col_vec
+// allows).
+template <typename TIn, bool RED, int r>
+__device__ __forceinline__ void col_fwd_cv(const NttLaunch& a, int prime, uint32_t i0, uint32_t i1,
+                                           bool zhi) {
+  if (!zhi) {
+    col_fwd_items<TIn, RED, r, 1, false>(a, prime, i0, i1, kBatchNT);
+  } else if (a.col_vec >= 2) {
+    col_fwd_items<TIn, RED, r, 2>(a, prime, i0, i1, kBatchNT);
+  } else {
+    col_fwd_items<TIn, RED, r, 1>(a, prime, i0, i1, kBatchNT);
+  }
+}
+
 template <typename TIn, bool RED>
 __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, uint32_t x,
                                        uint32_t* lds) {
@@ -42,18 +56,9 @@ __device__ __forceinline__ void phase0(const NttLaunch& a, const BatchSeg& g, ui
     // whole products have nin = d <= L/2; coefficient windows may not
     const bool zhi = 2 * a.nin <= (1 << a.logL);
     switch (a.split) {
-      case 2:
-        if (zhi) col_fwd_items<TIn, RED, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        else col_fwd_items<TIn, RED, 2, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        break;
-      case 3:
-        if (zhi) col_fwd_items<TIn, RED, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        else col_fwd_items<TIn, RED, 3, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        break;
-      default:
-        if (zhi) col_fwd_items<TIn, RED, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        else col_fwd_items<TIn, RED, 4, 1, false>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT);
-        break;
+      case 2: col_fwd_cv<TIn, RED, 2>(a, g.prime, i0 + threadIdx.x, i1, zhi); break;
+      case 3: col_fwd_cv<TIn, RED, 3>(a, g.prime, i0 + threadIdx.x, i1, zhi); break;
+      default: col_fwd_cv<TIn, RED, 4>(a, g.prime, i0 + threadIdx.x, i1, zhi); break;
     }
   } else {
     constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;
@@ -71,6 +76,13 @@ __device__ __forceinline__ void block_v(const NttLaunch& a, int prime, int x, in
   else block_tile<DIF, 1, kBatchNT, 2>(a, prime, x, z, lds);
 }
 
+template <typename TOut, int r>
+__device__ __forceinline__ void col_inv_cv(const NttLaunch& a, int prime, uint32_t i0,
+                                           uint32_t i1) {
+  if (a.col_vec >= 2) col_inv_items<TOut, r, 2>(a, prime, i0, i1, kBatchNT);
+  else col_inv_items<TOut, r, 1>(a, prime, i0, i1, kBatchNT);
+}
+
 template <typename TOut>
 __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, uint32_t x,
                                        uint32_t* lds) {
@@ -79,9 +91,9 @@ __device__ __forceinline__ void phase4(const NttLaunch& a, const BatchSeg& g, ui
     const uint32_t i0 = x * kColChunk;
     const uint32_t i1 = i0 + kColChunk < items ? i0 + kColChunk : items;
     switch (a.split) {
-      case 2: col_inv_items<TOut, 2, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      case 3: col_inv_items<TOut, 3, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
-      default: col_inv_items<TOut, 4, 1>(a, g.prime, i0 + threadIdx.x, i1, kBatchNT); break;
+      case 2: col_inv_cv<TOut, 2>(a, g.prime, i0 + threadIdx.x, i1); break;
+      case 3: col_inv_cv<TOut, 3>(a, g.prime, i0 + threadIdx.x, i1); break;
+      default: col_inv_cv<TOut, 4>(a, g.prime, i0 + threadIdx.x, i1); break;
     }
   } else {
     constexpr int VW = sizeof(TOut) == 4 ? 4 : 2;
