@@ -44,6 +44,7 @@ int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
 
 size_t pointwise_mfma_lds(int m, int n, int k) {
   const size_t mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
+  if (n <= 16) return 4 * (mp + kp) * kK16Row + kK16Row;  // packed contraction
   return 4 * (mp + kp) * (np + 16);
 }
 
@@ -62,15 +63,16 @@ size_t pointwise_small_lds() {
 
 // Pipelined-kernel variant for a shape with 512 threads: 1 (4 A groups and
 // one B block per thread: 122 VGPRs, two workgroups per CU), 2 (8 and 2:
-// 154 VGPRs, one), or 0 when the shape needs more registers or k is not a
-// multiple of 4.  Tuning knob PM_TUNE_PW_PIPE: 0 never pipelines, 1 or 2
-// forces that variant where it suffices.
+// 154 VGPRs, one), or 0 when the shape needs more registers, k is not a
+// multiple of 4 or n <= 16 (packed contraction).  Tuning knob
+// PM_TUNE_PW_PIPE: 0 never pipelines, 1 or 2 forces that variant where it
+// suffices.
 int pointwise_pipe_variant(int m, int n, int k) {
   static const int knob = [] {
     const char* e = getenv("PM_TUNE_PW_PIPE");
     return e && *e ? atoi(e) : -1;
   }();
-  if (knob == 0 || k % 4 != 0) return 0;
+  if (knob == 0 || k % 4 != 0 || n <= 16) return 0;  // n <= 16: packed contraction
   const long mp = (m + 15) & ~15, kp = (k + 15) & ~15, ng = ((n + 63) & ~63) >> 2;
   const long need_a = (mp * ng + 511) / 512, need_b = (ng * (kp / 4) + 511) / 512;
   const bool small = need_a <= 4 && need_b <= 1, big = need_a <= 8 && need_b <= 2;

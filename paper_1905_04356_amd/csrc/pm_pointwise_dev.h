@@ -134,8 +134,19 @@ __device__ __forceinline__ void stage_limbs(const uint32_t* A, const uint32_t* B
   }
 }
 
+// Contractions of at most 16 (n <= 16) are packed instead of padded to 64:
+// the four limb planes of A fill the 64 contraction bytes of one
+// v_mfma_i32_16x16x64_i8 (lanes 16g .. 16g + 15 supply plane g of A's row),
+// and for weight class s the same lanes supply plane s - g of B's column (a
+// zero row where s - g is outside 0 .. 3), so one instruction sums A_a B_b
+// over a + b = s: 7 instructions per output tile instead of 16, on LDS rows
+// of 16 bytes.
+constexpr int kK16Row = 16;
+
 // The products of point t from the limb planes in LDS: 16x16 output tiles
-// spread over the workgroup's waves, recombined, reduced and stored.
+// spread over the workgroup's waves, recombined, reduced and stored.  K16:
+// the packed form (rows of kK16Row bytes, B's zero row after its planes).
+template <bool K16 = false>
 __device__ __forceinline__ void mfma_point(const PointwiseLaunch& a, int t, int prime,
                                            const uint8_t* As, const uint8_t* Bs, int mp, int kp,
                                            int np, int rs) {
@@ -162,7 +173,18 @@ __device__ __forceinline__ void mfma_point(const PointwiseLaunch& a, int t, int 
     v4i acc[7];
 #pragma unroll
     for (int s = 0; s < 7; ++s) acc[s] = (v4i){0, 0, 0, 0};
-    for (int kc = 0; kc < np; kc += 64) {
+    if (K16) {
+      const int g = lane >> 4;
+      const v4i av = *(const v4i*)(As + (g * mp + ti * 16 + lr) * kK16Row);
+      const uint8_t* zero = Bs + 4 * kp * kK16Row;
+#pragma unroll
+      for (int s = 0; s < 7; ++s) {
+        const int x = s - g;
+        const uint8_t* src = x >= 0 && x < 4 ? Bs + (x * kp + tj * 16 + lr) * kK16Row : zero;
+        acc[s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, *(const v4i*)src, acc[s], 0, 0, 0);
+      }
+    }
+    for (int kc = 0; kc < (K16 ? 0 : np); kc += 64) {
       v4i av[4], bv[4];
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {
@@ -189,12 +211,62 @@ __device__ __forceinline__ void mfma_point(const PointwiseLaunch& a, int t, int 
   }
 }
 
+// A (m x n, n <= 16, a multiple of 4) and B (n x k, stored transposed) into
+// packed limb planes: A plane a row i and B plane b column j are 16-byte
+// rows (contraction indices 0 .. 15, zeros from n on); then B's zero row.
+template <bool CENTER>
+__device__ __forceinline__ void stage_limbs_k16(const uint32_t* A, const uint32_t* B,
+                                                uint8_t* As, uint8_t* Bs, int m, int n, int k,
+                                                int mp, int kp, uint32_t q, uint32_t half_q) {
+  const int nt = blockDim.x;
+  // A: item f = 4 i + g, the 16-byte group g of row i
+  for (int f = threadIdx.x; f < 4 * mp; f += nt) {
+    const int i = f >> 2, l0 = (f & 3) * 4;
+    uint32_t in[4] = {0, 0, 0, 0}, out[4];
+    if (i < m && l0 < n) {
+      const uint4 v = *(const uint4*)(A + i * n + l0);
+      in[0] = limbs_of<CENTER>(v.x, q, half_q); in[1] = limbs_of<CENTER>(v.y, q, half_q);
+      in[2] = limbs_of<CENTER>(v.z, q, half_q); in[3] = limbs_of<CENTER>(v.w, q, half_q);
+    }
+    transpose4x4(in, out);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(As + (pl * mp + i) * kK16Row + l0) = out[pl];
+  }
+  // B: item f = g kp + j, rows 4g .. 4g + 3 of column j (consecutive threads,
+  // consecutive columns)
+  for (int f = threadIdx.x; f < 4 * kp; f += nt) {
+    const int g = f / kp, j = f - g * kp, l0 = g * 4;
+    uint32_t in[4] = {0, 0, 0, 0}, out[4];
+    if (j < k && l0 < n) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) in[c] = limbs_of<CENTER>(B[(l0 + c) * k + j], q, half_q);
+    }
+    transpose4x4(in, out);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) *(uint32_t*)(Bs + (pl * kp + j) * kK16Row + l0) = out[pl];
+  }
+  if (threadIdx.x < kK16Row / 4) ((uint32_t*)(Bs + 4 * kp * kK16Row))[threadIdx.x] = 0u;
+}
+
 __device__ __forceinline__ void pointwise_mfma_tile(const PointwiseLaunch& a, int t, int prime,
                                                     uint32_t* smem) {
   const PrimeConst& P = a.pc[prime];
   const uint32_t q = P.q, half_q = P.q >> 1;
   const int m = a.m, n = a.n, k = a.k;
   const int mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
+  if (n <= 16) {
+    uint8_t* As = (uint8_t*)smem;             // [4][mp][16]
+    uint8_t* Bs = As + 4 * mp * kK16Row;      // [4][kp][16], then 16 zero bytes
+    const uint32_t* A = a.ahat + a.a_prime_stride * prime + (size_t)t * ((size_t)m * n);
+    const uint32_t* B = a.bhat + a.b_prime_stride * prime + (size_t)t * ((size_t)n * k);
+    if (q <= 0x7F7F7F7Fu)
+      stage_limbs_k16<false>(A, B, As, Bs, m, n, k, mp, kp, q, half_q);
+    else
+      stage_limbs_k16<true>(A, B, As, Bs, m, n, k, mp, kp, q, half_q);
+    __syncthreads();
+    mfma_point<true>(a, t, prime, As, Bs, mp, kp, kK16Row, kK16Row);
+    return;
+  }
   const int rs = np + 16;                   // bytes per LDS row (padded)
   uint8_t* As = (uint8_t*)smem;             // [4][mp][rs]
   uint8_t* Bs = As + 4 * mp * rs;           // [4][kp][rs]

@@ -214,10 +214,12 @@ def test_pipelined_pointwise_long_sequences(p, m, n, k, d):
     sampled_check(p, A, B, C, seed=13, entries=3)
 
 
-def test_mfma_limb_extremes():
+@pytest.mark.parametrize("m,n,k", [(16, 64, 16), (24, 16, 40), (16, 4, 16)])
+def test_mfma_limb_extremes(m, n, k):
     """Residues at the centring boundary ((q-1)/2, (q+1)/2), 0, 1, q-1 in every
-    position exercise the largest limb magnitudes."""
-    p, m, n, k, d = P31, 16, 64, 16, 8
+    position exercise the largest limb magnitudes, with the contraction padded
+    to 64 and packed (n <= 16)."""
+    p, d = P31, 8
     vals = np.array([0, 1, (p - 1) // 2, (p + 1) // 2, p - 1, p - 2], dtype=np.uint32)
     rng = np.random.default_rng(12)
     A = vals[rng.integers(0, len(vals), size=(d, m, n))]
@@ -406,10 +408,12 @@ def test_batched_graph_replays_match_eager():
 
 
 @pytest.mark.parametrize("fill", ["max", "random"])
-def test_mfma_centred_limbs_for_primes_above_0x7f7f7f7f(fill):
+@pytest.mark.parametrize("n", [64, 12])
+def test_mfma_centred_limbs_for_primes_above_0x7f7f7f7f(fill, n):
     """A direct-mode prime above 0x7F7F7F7F (2^31 - 1 at d = 1, one point)
-    takes the MFMA kernel's centred digit path; all-(p-1) and random inputs."""
-    p, m, n, k, d = (1 << 31) - 1, 8, 64, 8, 1
+    takes the MFMA kernel's centred digit path; all-(p-1) and random inputs,
+    padded and packed contractions."""
+    p, m, k, d = (1 << 31) - 1, 8, 8, 1
     info = Bd.pm_plan(p, m, n, k, d, 4)
     assert info.mode == 0 and info.pointwise == 1
     if fill == "max":
