@@ -63,10 +63,13 @@ __device__ __forceinline__ void pointwise_valu_tile(const PointwiseLaunch& a, in
 // n < 2^15), recombined as sum_s c_s acc_s mod q in int64 with
 // c_s = 256^s L^{-1} mod q (|sum| < n 2^49, exact while n < 2^13).
 //
-// One workgroup (4 waves) per point: the two matrices are loaded with
+// One workgroup (4 or 8 waves) per point: the two matrices are loaded with
 // coalesced 16-byte reads, split, and stored as limb planes in LDS
 // (A: plane, row i, contraction index l; B transposed: plane, column j, l);
 // each wave then computes 16x16 output tiles with v_mfma_i32_16x16x64_i8.
+// Contractions of at most 16 are packed (see kK16Row), and large limb
+// planes run the pipelined variant at the end of this file, where a
+// workgroup runs a sequence of points.
 // Lane layout of that instruction (checked on gfx950): lane L supplies
 // A[L%16][16(L/16) + b] and B[16(L/16) + b][L%16] for bytes b < 16, and
 // receives C[4(L/16) + r][L%16] for r < 4.
