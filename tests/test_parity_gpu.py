@@ -529,6 +529,7 @@ def test_kernel_timing_counts_only_unpaused_launches():
     (P31, 8, 8, 6, 2048),     # 2^12: {4, 4}, 32-entry tiles, 48 entries (ragged)
     (P30, 8, 4, 6, 4096),     # 2^13: {3, 3, 3}, 16-entry tiles, 24 and 48 entries
     (P31, 4, 4, 2, 8192),     # 2^14: {4, 3, 3}, 8-entry tiles
+    (P30, 3, 3, 1, 6000),     # 2^14, odd entry counts: LDS-tile path
     (P30, 2, 2, 3, 16384),    # 2^15: {4, 4, 3}, 4-entry tiles, 6 entries
     (P31, 3, 3, 1, 16384),    # 2^15, odd entry counts: 1-word vectors, LDS-tile path
 ])
