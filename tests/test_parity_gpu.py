@@ -273,6 +273,20 @@ def test_batched_crt_u64_and_u32():
     _batch_vs_single(P32, shapes, seed=15)
 
 
+def test_batched_pipelined_pointwise_crt():
+    """Large limb planes in batched calls take the pipelined pointwise tiles
+    (phase 2 with 4 register slots, phase 6 with 8) and small contractions
+    the packed form; CRT moduli with 64-bit and 32-bit elements."""
+    shapes = [(128, 128, 128, 300), (128, 64, 96, 200), (96, 36, 112, 260),
+              (128, 8, 128, 150), (40, 200, 24, 90), (64, 64, 32, 120)]
+    for sh in shapes:
+        assert Bd.pm_plan(P30, *sh, 4).pointwise == 1
+    say("[parity] batched pipelined pointwise, CRT u64")
+    _batch_vs_single(I.seeded_prime_60(6), shapes, seed=21, dtype=np.uint64)
+    say("[parity] batched pipelined pointwise, CRT u32")
+    _batch_vs_single(P32, shapes, seed=22)
+
+
 def test_batched_single_product_and_repeats():
     shapes = [(64, 64, 32, 4096)]
     A, B = tensors(P31, 64, 64, 32, 4096, seed=16)
