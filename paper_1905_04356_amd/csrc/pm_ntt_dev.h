@@ -54,6 +54,27 @@ struct alignas(sizeof(T) * V) Vec {
   T v[V];
 };
 
+// A load marked non-temporal (read once: it should not displace data that
+// is read again from the last-level cache).
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> load_nt(const Vec<T, V>* p) {
+  constexpr int W = sizeof(T) * V / 4;
+  typedef uint32_t W4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t W2 __attribute__((ext_vector_type(2)));
+  Vec<T, V> r;
+  if constexpr (W == 4) {
+    const W4 x = __builtin_nontemporal_load((const W4*)p);
+    __builtin_memcpy(&r, &x, sizeof r);
+  } else if constexpr (W == 2) {
+    const W2 x = __builtin_nontemporal_load((const W2*)p);
+    __builtin_memcpy(&r, &x, sizeof r);
+  } else {
+    const uint32_t x = __builtin_nontemporal_load((const uint32_t*)p);
+    __builtin_memcpy(&r, &x, sizeof r);
+  }
+  return r;
+}
+
 // r radix-2 stages on x[0..2^r) held in registers.  DIF: stage distance
 // 2^v for v = r-1 .. 0, (a, b) -> (a + b, (a - b) w).  DIT: v = 0 .. r-1,
 // (a, b) -> (a + b w, a - b w).  ZHI (DIF only): x[2^(r-1) ..] are zero, so
@@ -590,7 +611,7 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
 #pragma unroll
       for (int c = 0; c < CV; ++c) v.v[c] = 0;
       if ((!ZHI || u < R / 2) && row < (uint32_t)a.nin)
-        v = *(const Vec<TIn, CV>*)(in + (size_t)row * E + e);
+        v = load_nt((const Vec<TIn, CV>*)(in + (size_t)row * E + e));
 #pragma unroll
       for (int c = 0; c < CV; ++c)
         x[c][u] = REDUCE ? reduce_u64((uint64_t)v.v[c], q, P.mu) : (uint32_t)v.v[c];
