@@ -35,16 +35,19 @@
  * stream (a hipStream_t passed as void*, NULL for the default stream).
  * Every pm_mul* call only enqueues work on that stream and returns; results
  * are valid once the stream has completed.  Buffers must stay alive until
- * then.  The library keeps per-device tables of roots of unity, built on the
- * first call that needs a given (prime, length) and reused until the process
- * ends (this first call copies them synchronously, so make it before any
- * stream capture).  Calls from several host threads are safe; two calls
- * that share a workspace must be ordered on one stream.
+ * then.  The library allocates no device memory: its tables (roots of unity
+ * per prime and length, Vandermonde matrices) live in regions of device
+ * memory the caller registers with pm_tables_attach, are filled by a kernel
+ * on the stream of the first call that needs them (no host copy, so a first
+ * call may run inside a stream capture) and are reused by later calls on any
+ * stream.  Calls from several host threads are safe; two calls that share a
+ * workspace must be ordered on one stream.
  *
  * Errors: every argument check runs before anything is enqueued; a failed
  * check returns a negative pm_status and writes nothing.  A device fault is
  * reported as PM_EDEVICE by pm_sync or by a later call.  No C++ exception
- * crosses this interface and the library never aborts the process.
+ * crosses this interface (a failed host allocation is PM_ENOMEM) and the
+ * library never aborts the process.
  */
 #ifndef PM_H
 #define PM_H
@@ -60,18 +63,19 @@ typedef enum pm_status {
   PM_OK = 0,
   PM_EINVAL = -1,        /* bad argument: size < 1, NULL pointer, p < 2, overlap */
   PM_ERANGE = -2,        /* modulus or size outside what this API supports       */
-  PM_ENOMEM = -3,        /* the library could not allocate its tables            */
+  PM_ENOMEM = -3,        /* a host allocation of the library failed              */
   PM_EWORKSPACE = -4,    /* workspace NULL, misaligned or too small              */
   PM_EDEVICE = -5,       /* a HIP call failed                                    */
   PM_EUNSUPPORTED = -6,  /* no prime set covers the requested length/bound       */
-  PM_EBUSY = -7          /* reserved for admission control (serving layer)       */
+  PM_EBUSY = -7,         /* reserved for admission control (serving layer)       */
+  PM_ETABLES = -8        /* no table region attached, or the regions are full    */
 } pm_status;
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 3
+#define PM_ABI_VERSION 4
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -95,9 +99,35 @@ typedef struct pm_plan_info {
 /* Plan the product of an (m x n) by (n x k) matrix of degree < d mod p with
  * elem_bytes-byte residues (4 or 8).  Host only.  Returns PM_EINVAL on sizes
  * < 1, PM_ERANGE if p does not fit elem_bytes (p < 2^32 for 4, p < 2^62 for
- * 8) or if a size product overflows, PM_EUNSUPPORTED if L exceeds 2^24. */
+ * 8) or if a size product overflows, PM_EUNSUPPORTED if L = 2^ceil(log2(2d-1))
+ * exceeds 2^15 (transforms are held in on-chip memory) or no prime set
+ * covers the CRT bound. */
 pm_status pm_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                   int32_t elem_bytes, pm_plan_info* out);
+
+/* Device tables.  pm_tables_attach registers `bytes` of device memory at
+ * dev_ptr (256-byte aligned, owned by the caller, on the current device) as
+ * a region from which the library carves its tables; it must stay allocated
+ * and untouched by the caller until the process ends or pm_tables_reset.
+ * Several regions may be attached; a call whose missing tables do not fit
+ * the free space of the attached regions returns PM_ETABLES before
+ * enqueueing anything (attach another region and call again).  PM_EINVAL on
+ * a NULL or misaligned pointer, fewer than 256 bytes, or overlap with an
+ * attached region.
+ * pm_tables_bytes: an upper bound of the table bytes a pm_mul_* call of this
+ * product carves the first time (every (prime, length) pair it may use,
+ * including the wrapped form and the Vandermonde route); a table shared by
+ * several products is carved once.
+ * pm_tables_reset: forget every table and region of the current device (for
+ * tests and for releasing the regions); no work that reads them may be in
+ * flight or captured in a graph that is still launched.
+ * pm_tables_info: bytes attached, bytes carved and number of tables on the
+ * current device (each output pointer may be NULL). */
+pm_status pm_tables_attach(void* dev_ptr, uint64_t bytes);
+pm_status pm_tables_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                          int32_t elem_bytes, uint64_t* out);
+pm_status pm_tables_reset(void);
+pm_status pm_tables_info(uint64_t* attached_bytes, uint64_t* used_bytes, int32_t* tables);
 
 /* Workspace bytes pm_mul_u32 / pm_mul_u64 need for this product. */
 pm_status pm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k,
@@ -156,8 +186,8 @@ pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da,
  * and workspace rules and result as pm_mul_u32 (workspace size from
  * pm_vdm_workspace_bytes).  Requires p prime, 3 <= p < 2^31, 2d - 1 <= p,
  * 2d - 1 < 4096 and n < 4096 (PM_ERANGE / PM_EINVAL / PM_EUNSUPPORTED
- * otherwise).  The Vandermonde matrices are built on the host and kept on
- * the device per (p, d) on first use.  Asynchronous on `stream`. */
+ * otherwise).  The Vandermonde matrices are tables (pm_tables_attach),
+ * filled on the device per (p, d) on first use.  Asynchronous on `stream`. */
 pm_status pm_vdm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                                  uint64_t* out);
 pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
@@ -276,6 +306,17 @@ pm_status pm_mul_batched_u64(uint64_t p, int32_t count, const pm_product* prods,
                              void* workspace, uint64_t workspace_bytes,
                              void* stream);
 
+/* Y = -X mod p elementwise (Y[i] = (p - X[i]) mod p): the negated operand
+ * that the Newton iteration for truncated inverses keeps (Section 4,
+ * "Lifting techniques": X_2k = X_k - x^k (X_k E mod x^k), computed with -A
+ * so that the update is a concatenation).  X, Y: device memory, `count`
+ * residues in [0, p) of elem_bytes (4 or 8) bytes, aligned to elem_bytes;
+ * Y may equal X (in place), otherwise they must not overlap (PM_EINVAL).
+ * p >= 2 and p < 2^32 (elem_bytes 4) or p < 2^62 (elem_bytes 8), else
+ * PM_ERANGE.  Asynchronous on `stream`. */
+pm_status pm_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int32_t elem_bytes,
+                     void* stream);
+
 /* Count the elements of X (count residues of elem_bytes bytes, device
  * memory) that are >= p and write the count to *n_bad (host pointer).  This
  * call synchronises `stream`.  workspace: at least 8 bytes of device memory,
@@ -312,6 +353,14 @@ pm_status pm_profile_pause(int32_t paused);
 
 /* Wait for `stream` and report any device error raised by earlier calls. */
 pm_status pm_sync(void* stream);
+
+/* Test hook for the error paths: after `countdown` more host allocation
+ * points in the library, the next one fails as if memory ran out (the call
+ * then returns PM_ENOMEM); a negative countdown disarms it.  Allocation
+ * points are where the library's host code allocates (plans, batch
+ * descriptors, table bookkeeping, M-Basis and matrix-inverse work arrays).
+ * Process-wide; not for production use. */
+pm_status pm_debug_fail_alloc(int32_t countdown);
 
 #ifdef __cplusplus
 }

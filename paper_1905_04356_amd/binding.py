@@ -20,6 +20,7 @@ PM_EWORKSPACE = -4
 PM_EDEVICE = -5
 PM_EUNSUPPORTED = -6
 PM_EBUSY = -7
+PM_ETABLES = -8
 
 # Every symbol include/pm.h declares.
 EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
@@ -29,7 +30,9 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_sync", "pm_middle_plan", "pm_middle_u32", "pm_middle_u64", "pm_mbasis_host",
            "pm_matinv_host", "pm_middle_batched_workspace_bytes", "pm_middle_batched_u32",
            "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
-           "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32")
+           "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32",
+           "pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
+           "pm_neg_mod", "pm_debug_fail_alloc")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
@@ -112,6 +115,16 @@ def lib():
     L.pm_profile_pause.argtypes = [i32]
     L.pm_mbasis_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(u64)]
     L.pm_mbasis_u32.argtypes = [u32, i32, i32, i32, i32, vp, u64, vp, vp, vp, vp, u64, vp]
+    L.pm_tables_attach.argtypes = [vp, u64]
+    L.pm_tables_bytes.argtypes = [u64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_tables_reset.argtypes = []
+    L.pm_tables_info.argtypes = [ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                 ctypes.POINTER(i32)]
+    L.pm_neg_mod.argtypes = [u64, vp, vp, u64, i32, vp]
+    L.pm_debug_fail_alloc.argtypes = [i32]
+    for name in ("pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
+                 "pm_neg_mod", "pm_debug_fail_alloc"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
                  "pm_check_residues", "pm_sync", "pm_profile_begin", "pm_profile_end",
@@ -147,6 +160,33 @@ def pm_workspace_bytes(p: int, m: int, n: int, k: int, d: int, elem_bytes: int) 
     _check(lib().pm_workspace_bytes(p, m, n, k, d, elem_bytes, ctypes.byref(out)),
            "pm_workspace_bytes")
     return out.value
+
+
+def pm_tables_attach(ptr: int, nbytes: int) -> int:
+    return lib().pm_tables_attach(ptr, nbytes)
+
+
+def pm_tables_bytes(p: int, m: int, n: int, k: int, d: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().pm_tables_bytes(p, m, n, k, d, elem_bytes, ctypes.byref(out)),
+           "pm_tables_bytes")
+    return out.value
+
+
+def pm_tables_reset() -> None:
+    _check(lib().pm_tables_reset(), "pm_tables_reset")
+
+
+def pm_tables_info() -> tuple[int, int, int]:
+    """(bytes attached, bytes carved, tables) on the current device."""
+    a, u, t = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_int32(0)
+    _check(lib().pm_tables_info(ctypes.byref(a), ctypes.byref(u), ctypes.byref(t)),
+           "pm_tables_info")
+    return a.value, u.value, t.value
+
+
+def pm_neg_mod(p, X, Y, count, elem_bytes, stream) -> int:
+    return lib().pm_neg_mod(p, X, Y, count, elem_bytes, stream)
 
 
 def pm_mul_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:

@@ -22,6 +22,7 @@
 #include "pm_kernels.h"
 #include "pm_plan.h"
 #include "pm_profile.h"
+#include "pm_tables.h"
 #include "pm_vdm.h"
 
 using namespace pm;
@@ -57,11 +58,12 @@ const char* pm_status_str(int status) {
     case PM_OK: return "PM_OK";
     case PM_EINVAL: return "PM_EINVAL: invalid argument";
     case PM_ERANGE: return "PM_ERANGE: modulus or size out of range";
-    case PM_ENOMEM: return "PM_ENOMEM: table allocation failed";
+    case PM_ENOMEM: return "PM_ENOMEM: host allocation failed";
     case PM_EWORKSPACE: return "PM_EWORKSPACE: workspace missing, misaligned or too small";
     case PM_EDEVICE: return "PM_EDEVICE: HIP error";
     case PM_EUNSUPPORTED: return "PM_EUNSUPPORTED: length or bound not supported";
     case PM_EBUSY: return "PM_EBUSY: busy";
+    case PM_ETABLES: return "PM_ETABLES: no table region attached, or the regions are full";
     default: return "unknown pm_status";
   }
 }
@@ -70,22 +72,26 @@ int pm_abi_version(void) { return PM_ABI_VERSION; }
 
 pm_status pm_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int32_t elem_bytes,
                   pm_plan_info* out) {
-  if (!out) return PM_EINVAL;
-  Plan P;
-  int st = make_plan(p, m, n, k, d, elem_bytes, &P);
-  if (st != PM_OK) return (pm_status)st;
-  fill_plan_info(P, out);
-  return PM_OK;
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    Plan P;
+    int st = make_plan(p, m, n, k, d, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    fill_plan_info(P, out);
+    return (int)PM_OK;
+  });
 }
 
 pm_status pm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                              int32_t elem_bytes, uint64_t* out) {
-  if (!out) return PM_EINVAL;
-  Plan P;
-  int st = make_plan(p, m, n, k, d, elem_bytes, &P);
-  if (st != PM_OK) return (pm_status)st;
-  *out = P.ws_bytes;
-  return PM_OK;
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    Plan P;
+    int st = make_plan(p, m, n, k, d, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    *out = P.ws_bytes;
+    return (int)PM_OK;
+  });
 }
 
 }  // extern "C"
@@ -122,10 +128,11 @@ void fill_crt(const Plan& P, CrtLaunch* c) {
   c->r = P.r;
   c->p = P.p;
   c->pinv = 1.0 / (double)P.p;
+  c->mu_p = ~0ull / P.p;
   for (int i = 0; i < P.r; ++i) {
     const uint32_t qi = P.q[i];
     c->q[i] = qi;
-    c->mu[i] = ~0ull / qi;
+    c->mu32[i] = (uint32_t)((1ull << 32) / qi);
     for (int j = 0; j < i; ++j) {
       const uint32_t inv = (uint32_t)powmod_u64(P.q[j] % qi, qi - 2, qi);
       c->inv[i][j] = inv;
@@ -148,7 +155,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   memset(L, 0, sizeof *L);
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
-    int st = get_prime_const(P.q[i], P.logL, &pc[i]);
+    int st = prime_const(P.q[i], P.logL, &pc[i]);
     if (st != PM_OK) return st;
   }
   const int m = P.m, n = P.n, k = P.k;
@@ -227,6 +234,14 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   return PM_OK;
 }
 
+// Twiddle tables of every (prime, length) pair of the plans, on stream s.
+int prepare_plans(const Plan* plans, size_t n, hipStream_t s) {
+  std::vector<TwKey> keys;
+  for (size_t i = 0; i < n; ++i)
+    for (int j = 0; j < plans[i].r; ++j) keys.push_back(TwKey{plans[i].q[j], plans[i].logL});
+  return prepare_twiddles(keys.data(), (int)keys.size(), s);
+}
+
 }  // namespace pm
 
 namespace {
@@ -260,9 +275,11 @@ int launch_product(const Plan& P, const ProductLaunches& L, const bool skip_fwd[
 }
 
 int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
-                hipStream_t s) {
+                hipStream_t s, bool prepared = false) {
+  int st = prepared ? PM_OK : prepare_plans(&P, 1, s);
+  if (st != PM_OK) return st;
   ProductLaunches L;
-  int st = fill_product_launches(P, A, B, C, ws, &L);
+  st = fill_product_launches(P, A, B, C, ws, &L);
   if (st != PM_OK) return st;
   const bool none[2] = {false, false};
   return launch_product(P, L, none, s);
@@ -328,12 +345,15 @@ int run_wrapped(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t eb = (uint64_t)P.elem_bytes;
   const int h = Lp - d + 1;
-  int st = run_product(Pc, A, B, C, ws, s);
+  const Plan both[2] = {Pc, Pt};
+  int st = prepare_plans(both, 2, s);
+  if (st != PM_OK) return st;
+  st = run_product(Pc, A, B, C, ws, s, true);
   if (st != PM_OK) return st;
   const uint8_t* At = (const uint8_t*)A + eb * h * P.m * P.n;
   const uint8_t* Bt = (const uint8_t*)B + eb * h * P.n * P.k;
   uint8_t* Ct = (uint8_t*)C + eb * (uint64_t)Lp * P.m * P.k;
-  st = run_product(Pt, At, Bt, Ct, ws, s);
+  st = run_product(Pt, At, Bt, Ct, ws, s, true);
   if (st != PM_OK) return st;
   const uint64_t mk = (uint64_t)P.m * P.k;
   KernelTimer kt(K_CRT, s);
@@ -387,13 +407,36 @@ extern "C" {
 pm_status pm_mul_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d, const uint32_t* A,
                      const uint32_t* B, uint32_t* C, void* workspace, uint64_t workspace_bytes,
                      void* stream) {
-  return mul_common(p, m, n, k, d, 4, A, B, C, workspace, workspace_bytes, stream);
+  return (pm_status)guarded([&] {
+    return (int)mul_common(p, m, n, k, d, 4, A, B, C, workspace, workspace_bytes, stream);
+  });
 }
 
 pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, const uint64_t* A,
                      const uint64_t* B, uint64_t* C, void* workspace, uint64_t workspace_bytes,
                      void* stream) {
-  return mul_common(p, m, n, k, d, 8, A, B, C, workspace, workspace_bytes, stream);
+  return (pm_status)guarded([&] {
+    return (int)mul_common(p, m, n, k, d, 8, A, B, C, workspace, workspace_bytes, stream);
+  });
+}
+
+pm_status pm_tables_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                          int32_t elem_bytes, uint64_t* out) {
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    Plan P;
+    int st = make_plan(p, m, n, k, d, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    uint64_t b = (uint64_t)P.r * twiddle_table_bytes(P.logL);
+    Plan pc, pt;
+    if (wrap_log_plans(P, &pc, &pt))
+      b += (uint64_t)pc.r * twiddle_table_bytes(pc.logL) +
+           (uint64_t)pt.r * twiddle_table_bytes(pt.logL);
+    if (P.mode == 1 && elem_bytes == 4 && d <= vdm_max_d() && vdm_eligible(p, m, n, k, d))
+      b += vdm_table_bytes(d);
+    *out = b;
+    return (int)PM_OK;
+  });
 }
 
 // ---- evaluation at 0 .. 2d-2 by Vandermonde products -------------------------
@@ -437,9 +480,21 @@ pm_status pm_vdm_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, in
   return PM_OK;
 }
 
+static pm_status vdm_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                          const uint32_t* A, const uint32_t* B, uint32_t* C, void* workspace,
+                          uint64_t workspace_bytes, void* stream);
+
 pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                          const uint32_t* A, const uint32_t* B, uint32_t* C, void* workspace,
                          uint64_t workspace_bytes, void* stream) {
+  return (pm_status)guarded([&] {
+    return (int)vdm_impl(p, m, n, k, d, A, B, C, workspace, workspace_bytes, stream);
+  });
+}
+
+static pm_status vdm_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                          const uint32_t* A, const uint32_t* B, uint32_t* C, void* workspace,
+                          uint64_t workspace_bytes, void* stream) {
   int st = vdm_check(p, m, n, k, d);
   if (st != PM_OK) return (pm_status)st;
   if (p == 2) return PM_EUNSUPPORTED;  // the Montgomery epilogue needs q odd
@@ -452,8 +507,9 @@ pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
   st = check_workspace(workspace, workspace_bytes, need, A, 4ull * d * m * n, B,
                        4ull * d * n * k, C, 4ull * P.nout * m * k);
   if (st != PM_OK) return (pm_status)st;
+  hipStream_t s = (hipStream_t)stream;
   const uint32_t *V = nullptr, *W = nullptr;
-  st = get_vdm_tables(p, d, &V, &W);
+  st = prepare_vdm(p, d, s, &V, &W);
   if (st != PM_OK) return (pm_status)st;
   const int N = 2 * d - 1;
   uint8_t* ws = (uint8_t*)workspace;
@@ -461,7 +517,6 @@ pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
   uint32_t* bhat = (uint32_t*)(ws + align_up(4ull * N * m * n, 256));
   uint32_t* chat = (uint32_t*)(ws + align_up(4ull * N * m * n, 256) +
                                align_up(4ull * N * n * k, 256));
-  hipStream_t s = (hipStream_t)stream;
   {
     KernelTimer kt(K_VDM_EVAL, s);
     GemmLaunch g{};
@@ -505,26 +560,48 @@ pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
 
 pm_status pm_middle_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
                          int32_t lo, int32_t len, int32_t elem_bytes, pm_plan_info* out) {
-  if (!out) return PM_EINVAL;
-  Plan P;
-  int st = make_slice_plan(p, m, n, k, da, db, lo, len, elem_bytes, &P);
-  if (st != PM_OK) return (pm_status)st;
-  fill_plan_info(P, out);
-  return PM_OK;
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    Plan P;
+    int st = make_slice_plan(p, m, n, k, da, db, lo, len, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    fill_plan_info(P, out);
+    return (int)PM_OK;
+  });
 }
 
 pm_status pm_middle_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
                         int32_t lo, int32_t len, const uint32_t* A, const uint32_t* B,
                         uint32_t* C, void* workspace, uint64_t workspace_bytes, void* stream) {
-  return middle_common(p, m, n, k, da, db, lo, len, 4, A, B, C, workspace, workspace_bytes,
-                       stream);
+  return (pm_status)guarded([&] {
+    return (int)middle_common(p, m, n, k, da, db, lo, len, 4, A, B, C, workspace,
+                              workspace_bytes, stream);
+  });
 }
 
 pm_status pm_middle_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
                         int32_t lo, int32_t len, const uint64_t* A, const uint64_t* B,
                         uint64_t* C, void* workspace, uint64_t workspace_bytes, void* stream) {
-  return middle_common(p, m, n, k, da, db, lo, len, 8, A, B, C, workspace, workspace_bytes,
-                       stream);
+  return (pm_status)guarded([&] {
+    return (int)middle_common(p, m, n, k, da, db, lo, len, 8, A, B, C, workspace,
+                              workspace_bytes, stream);
+  });
+}
+
+pm_status pm_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int32_t elem_bytes,
+                     void* stream) {
+  if (!X || !Y || (elem_bytes != 4 && elem_bytes != 8)) return PM_EINVAL;
+  if (p < 2) return PM_EINVAL;
+  if ((elem_bytes == 4 && p > 0xFFFFFFFFull) || (elem_bytes == 8 && p >= (1ull << 62)))
+    return PM_ERANGE;
+  if (((uintptr_t)X | (uintptr_t)Y) & (uintptr_t)(elem_bytes - 1)) return PM_EINVAL;
+  const uint64_t bytes = count * (uint64_t)elem_bytes;
+  if (count && X != Y && overlap(X, bytes, Y, bytes)) return PM_EINVAL;
+  if (!count) return PM_OK;
+  KernelTimer kt(K_CRT, (hipStream_t)stream);
+  return launch_neg_mod(p, X, Y, count, elem_bytes, (hipStream_t)stream) == hipSuccess
+             ? PM_OK
+             : PM_EDEVICE;
 }
 
 pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count, int32_t elem_bytes,
@@ -579,9 +656,12 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   const uint64_t need = eval_prime_stride_bytes(P, rows, cols) * P.r;
   if (xe_bytes < need) return PM_EWORKSPACE;
   if (overlap(X, (uint64_t)eb * d * rows * cols, Xe, need)) return PM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  st = prepare_plans(&P, 1, s);
+  if (st != PM_OK) return (pm_status)st;
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
-    st = get_prime_const(P.q[i], P.logL, &pc[i]);
+    st = prime_const(P.q[i], P.logL, &pc[i]);
     if (st != PM_OK) return (pm_status)st;
   }
   NttLaunch a;
@@ -592,7 +672,6 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   a.out = Xe;
   a.in_prime_stride = 0;
   a.out_prime_stride = eval_prime_stride_bytes(P, rows, cols) / 4;
-  hipStream_t s = (hipStream_t)stream;
   KernelTimer kt(K_NTT_FWD, s);
   if (launch_ntt_fwd(a, eb, P.mode == 1, P.r, s) != hipSuccess) return PM_EDEVICE;
   return PM_OK;
@@ -604,22 +683,28 @@ extern "C" {
 
 pm_status pm_eval_bytes(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
                         int32_t elem_bytes, uint64_t* out) {
-  if (!out) return PM_EINVAL;
-  Plan P;
-  int st = eval_plan(p, role, rows, cols, d, elem_bytes, &P);
-  if (st != PM_OK) return (pm_status)st;
-  *out = eval_prime_stride_bytes(P, rows, cols) * P.r;
-  return PM_OK;
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    Plan P;
+    int st = eval_plan(p, role, rows, cols, d, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    *out = eval_prime_stride_bytes(P, rows, cols) * P.r;
+    return (int)PM_OK;
+  });
 }
 
 pm_status pm_eval_u32(uint32_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
                       const uint32_t* X, void* X_eval, uint64_t eval_bytes, void* stream) {
-  return eval_common(p, role, rows, cols, d, 4, X, X_eval, eval_bytes, stream);
+  return (pm_status)guarded([&] {
+    return (int)eval_common(p, role, rows, cols, d, 4, X, X_eval, eval_bytes, stream);
+  });
 }
 
 pm_status pm_eval_u64(uint64_t p, int32_t role, int32_t rows, int32_t cols, int32_t d,
                       const uint64_t* X, void* X_eval, uint64_t eval_bytes, void* stream) {
-  return eval_common(p, role, rows, cols, d, 8, X, X_eval, eval_bytes, stream);
+  return (pm_status)guarded([&] {
+    return (int)eval_common(p, role, rows, cols, d, 8, X, X_eval, eval_bytes, stream);
+  });
 }
 
 }  // extern "C"
@@ -667,6 +752,7 @@ void layout_batch(const std::vector<Plan>& plans, std::vector<uint64_t>& offs, B
 
 int plan_batch(uint64_t p, int32_t count, const pm_product* prods, int32_t elem_bytes,
                std::vector<Plan>& plans, std::vector<uint64_t>& offs, BatchLayout* lay) {
+  alloc_point();
   plans.resize(count);
   for (int32_t i = 0; i < count; ++i) {
     const pm_product& pr = prods[i];
@@ -721,6 +807,7 @@ void expand_wrapped(const std::vector<Plan>& plans, const pm_product* prods, int
 int plan_window_batch(uint64_t p, int32_t count, const pm_window_product* wins,
                       int32_t elem_bytes, std::vector<Plan>& plans, std::vector<uint64_t>& offs,
                       BatchLayout* lay, std::vector<pm_product>* prods) {
+  alloc_point();
   plans.resize(count);
   if (prods) prods->resize(count);
   for (int32_t i = 0; i < count; ++i) {
@@ -966,6 +1053,7 @@ struct GraphEntry {
   void* pinned = nullptr;
   hipStream_t last = nullptr;
   uint64_t tick = 0;
+  uint64_t epoch = 0;  // tables_epoch() when the entry was made
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
@@ -1022,12 +1110,20 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
     const char* v = getenv("PM_TUNE_BATCH_GRAPH");
     return !(v && *v == '0');
   }();
+  int st = prepare_plans(plans.data(), plans.size(), s);
+  if (st != PM_OK) return st;
   if (count <= direct_max) return run_direct(plans, offs, prods, ws, s);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (!use_graphs || hipStreamIsCapturing(s, &cs) != hipSuccess ||
-      cs != hipStreamCaptureStatusNone) {
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    // The caller is capturing a graph of its own: the phase launches would
+    // record a copy of descriptors from host memory that this call cannot
+    // keep alive for the graph's lifetime, so the products are launched one
+    // by one with their parameters in kernel arguments (same results).
+    return run_direct(plans, offs, prods, ws, s);
+  }
+  if (!use_graphs) {
     BatchBuild B;
-    int st = build_batch(plans, offs, lay, prods, ws, &B);
+    st = build_batch(plans, offs, lay, prods, ws, &B);
     if (st != PM_OK) return st;
     return enqueue_batch(B, B.host.data(), lay, ws, s);
   }
@@ -1038,6 +1134,13 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   GraphEntry* e = nullptr;
   for (auto& g : g_graphs)
     if (g.sig == sig) { e = &g; break; }
+  if (e && e->epoch != tables_epoch()) {
+    // tables were reset since this graph was captured: its table pointers
+    // are stale
+    free_entry(*e);
+    g_graphs.erase(g_graphs.begin() + (e - g_graphs.data()));
+    e = nullptr;
+  }
   if (e && e->exec) {
     e->tick = ++g_tick;
     e->last = s;
@@ -1045,7 +1148,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
     return hipGraphLaunch(e->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
   }
   BatchBuild B;
-  int st = build_batch(plans, offs, lay, prods, ws, &B);
+  st = build_batch(plans, offs, lay, prods, ws, &B);
   if (st != PM_OK) return st;
   if (!e) {
     // first occurrence: remember the signature, run eagerly
@@ -1060,6 +1163,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
     GraphEntry ne;
     ne.sig = std::move(sig);
     ne.seen = 1;
+    ne.epoch = tables_epoch();
     ne.tick = ++g_tick;
     g_graphs.push_back(std::move(ne));
     return enqueue_batch(B, B.host.data(), lay, ws, s);
@@ -1137,11 +1241,8 @@ static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods
 // Host allocation failures of the batch bookkeeping become PM_ENOMEM.
 static pm_status batched_common(uint64_t p, int32_t count, const pm_product* prods,
                                 int elem_bytes, void* ws, uint64_t ws_bytes, void* stream) {
-  try {
-    return batched_impl(p, count, prods, elem_bytes, ws, ws_bytes, stream);
-  } catch (const std::bad_alloc&) {
-    return PM_ENOMEM;
-  }
+  return (pm_status)guarded(
+      [&] { return (int)batched_impl(p, count, prods, elem_bytes, ws, ws_bytes, stream); });
 }
 
 static pm_status batched_impl(uint64_t p, int32_t count, const pm_product* prods,
@@ -1186,11 +1287,8 @@ static pm_status window_batched_impl(uint64_t p, int32_t count,
 static pm_status window_batched_common(uint64_t p, int32_t count,
                                        const pm_window_product* wins, int elem_bytes, void* ws,
                                        uint64_t ws_bytes, void* stream) {
-  try {
-    return window_batched_impl(p, count, wins, elem_bytes, ws, ws_bytes, stream);
-  } catch (const std::bad_alloc&) {
-    return PM_ENOMEM;
-  }
+  return (pm_status)guarded(
+      [&] { return (int)window_batched_impl(p, count, wins, elem_bytes, ws, ws_bytes, stream); });
 }
 
 static pm_status window_batched_impl(uint64_t p, int32_t count,

@@ -58,6 +58,29 @@ __global__ __launch_bounds__(256) void unwrap_kernel(T* C, uint64_t count, uint6
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void neg_mod_kernel(const T* X, T* Y, uint64_t count,
+                                                      uint64_t p) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const T x = X[i];
+    Y[i] = x ? (T)(p - x) : (T)0;
+  }
+}
+
+int launch_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int elem_bytes,
+                   hipStream_t s) {
+  uint64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) return hipSuccess;
+  if (elem_bytes == 8)
+    return launch(neg_mod_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                  (const uint64_t*)X, (uint64_t*)Y, count, p);
+  else
+    return launch(neg_mod_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                  (const uint32_t*)X, (uint32_t*)Y, count, p);
+}
+
 int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,
                   hipStream_t s) {
   uint64_t blocks = (count + 255) / 256;

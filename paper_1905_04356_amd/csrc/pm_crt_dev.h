@@ -28,7 +28,8 @@ __device__ __forceinline__ void crt_range(const CrtLaunch& a, uint64_t i0, uint6
       const uint32_t qi = a.q[i];
       uint32_t t = a.cq[a.prime_stride * i + idx];
       for (int j = 0; j < i; ++j) {
-        const uint32_t yj = reduce_u64(y[j], qi, a.mu[i]);
+        // y_j < q_j < 2^31: Barrett with floor(2^32 / q_i) leaves [0, 2 q_i)
+        const uint32_t yj = reduce_once(y[j] - __umulhi(y[j], a.mu32[i]) * qi, qi);
         t = sub_mod(t, yj, qi);
         t = mul_shoup(t, a.inv[i][j], a.inv_p[i][j], qi);
       }
@@ -36,7 +37,16 @@ __device__ __forceinline__ void crt_range(const CrtLaunch& a, uint64_t i0, uint6
     }
     uint64_t acc = 0;
     if (a.p <= 0xFFFFFFFFull) {
-      for (int i = 0; i < a.r; ++i) acc = (acc + (uint64_t)y[i] * a.radix_mod_p[i] % a.p) % a.p;
+      // y_i (prod_{j<i} q_j mod p) < 2^63: Barrett with floor((2^64-1)/p)
+      // leaves [0, 3p)
+      for (int i = 0; i < a.r; ++i) {
+        const uint64_t x = (uint64_t)y[i] * a.radix_mod_p[i];
+        uint64_t r = x - __umul64hi(x, a.mu_p) * a.p;
+        if (r >= a.p) r -= a.p;
+        if (r >= a.p) r -= a.p;
+        acc += r;
+        if (acc >= a.p) acc -= a.p;
+      }
     } else {
       for (int i = 0; i < a.r; ++i) {
         acc += mulmod_u64_small(y[i], a.radix_mod_p[i], a.p, a.pinv);

@@ -69,7 +69,8 @@ struct CrtLaunch {
   uint64_t p;
   double pinv;
   uint32_t q[kMaxPrimes];
-  uint64_t mu[kMaxPrimes];
+  uint32_t mu32[kMaxPrimes];               // floor(2^32 / q_i)
+  uint64_t mu_p;                           // floor((2^64-1) / p) (p < 2^32)
   uint32_t inv[kMaxPrimes][kMaxPrimes];    // q_j^{-1} mod q_i (j < i)
   uint32_t inv_p[kMaxPrimes][kMaxPrimes];  // Shoup companions
   uint64_t radix_mod_p[kMaxPrimes];        // prod_{j<i} q_j mod p
@@ -83,6 +84,9 @@ int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 // C[i] -= C[off + i] mod p for i < count (elements of elem_bytes bytes).
 int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,
                   hipStream_t s);
+// Y[i] = (p - X[i]) mod p for i < count (elements of elem_bytes bytes).
+int launch_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int elem_bytes,
+                   hipStream_t s);
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 size_t pointwise_mfma_lds(int m, int n, int k);
 // Largest pointwise LDS footprint launched with 256 threads (larger: 512).

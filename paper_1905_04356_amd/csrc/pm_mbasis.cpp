@@ -37,8 +37,16 @@ struct Field {
   bool small;          // p < 2^32
   uint64_t mu;         // floor((2^64 - 1) / p)
   uint64_t r64;        // 2^64 mod p
+  size_t batch;        // products of two residues that a 128-bit sum takes
+                       // after a reduction (< p) without wrapping
   explicit Field(uint64_t q)
-      : p(q), small(q < (1ull << 32)), mu(~0ull / q), r64((uint64_t)(((u128)1 << 64) % q)) {}
+      : p(q), small(q < (1ull << 32)), mu(~0ull / q), r64((uint64_t)(((u128)1 << 64) % q)) {
+    // each product is at most (p-1)^2; after a reduction the sum is below p,
+    // so batch terms keep it below p + batch (p-1)^2 <= (batch + 1) (p-1)^2
+    const u128 sq = (u128)(q - 1) * (q - 1);
+    const u128 cap = sq ? ~(u128)0 / sq : ~(u128)0;
+    batch = cap - 1 > (u128)SIZE_MAX ? SIZE_MAX : (size_t)(cap > 1 ? cap - 1 : 1);
+  }
   uint64_t red64(uint64_t x) const {  // x mod p, p < 2^32
     const uint64_t qt = (uint64_t)(((u128)x * mu) >> 64);
     uint64_t r = x - qt * p;
@@ -82,6 +90,7 @@ void row_degrees(const std::vector<uint64_t>& P, int D, int m, const int64_t* s,
 static pm_status mbasis_impl(uint64_t p, int32_t m, int32_t n, int32_t sigma, const uint64_t* F,
                              const int64_t* shift, uint64_t* Pout, int64_t* rdeg_out) {
   const Field K(p);
+  pm::alloc_point();
   const int D = sigma + 1;                       // coefficients of P (degree <= sigma)
   std::vector<uint64_t> P((size_t)D * m * m, 0), G((size_t)sigma * m * n, 0);
   for (int i = 0; i < m; ++i) P[(size_t)i * m + i] = 1;
@@ -136,18 +145,21 @@ static pm_status mbasis_impl(uint64_t p, int32_t m, int32_t n, int32_t sigma, co
       for (int j = 0; j < m; ++j)
         if (cm[j]) { sup.push_back(j); cf.push_back(cm[j]); }
       const size_t ns = sup.size();
+      // sum_u cf[u] X[row sup[u]][t] mod p, reduced every K.batch terms
+      auto dot = [&](const std::vector<uint64_t>& X, size_t base, size_t row, size_t t) {
+        u128 acc = 0;
+        size_t run = 0;
+        for (size_t u = 0; u < ns; ++u) {
+          if (run == K.batch) { acc = K.red128(acc); run = 0; }
+          acc += (u128)cf[u] * X[base + sup[u] * row + t];
+          ++run;
+        }
+        return K.red128(acc);
+      };
       for (int c = 0; c < dk; ++c)
-        for (int t = 0; t < m; ++t) {
-          u128 acc = 0;
-          for (size_t u = 0; u < ns; ++u) acc += (u128)cf[u] * P[((size_t)c * m + sup[u]) * m + t];
-          newP[(size_t)c * m + t] = K.red128(acc);
-        }
+        for (int t = 0; t < m; ++t) newP[(size_t)c * m + t] = dot(P, (size_t)c * m * m, m, t);
       for (int c = k; c < sigma; ++c)
-        for (int t = 0; t < n; ++t) {
-          u128 acc = 0;
-          for (size_t u = 0; u < ns; ++u) acc += (u128)cf[u] * G[((size_t)c * m + sup[u]) * n + t];
-          newG[(size_t)c * n + t] = K.red128(acc);
-        }
+        for (int t = 0; t < n; ++t) newG[(size_t)c * n + t] = dot(G, (size_t)c * m * n, n, t);
       for (int c = 0; c < dk; ++c)
         for (int t = 0; t < m; ++t) P[((size_t)c * m + i) * m + t] = newP[(size_t)c * m + t];
       for (int c = k; c < sigma; ++c)
@@ -189,6 +201,7 @@ extern "C" pm_status pm_mbasis_host(uint64_t p, int32_t m, int32_t n, int32_t si
 // truncated inverses starts.
 static pm_status matinv_impl(uint64_t p, int32_t n, const uint64_t* M, uint64_t* Minv) {
   const Field K(p);
+  pm::alloc_point();
   const size_t w = 2 * (size_t)n;
   std::vector<uint64_t> a((size_t)n * w, 0);
   for (int i = 0; i < n; ++i) {

@@ -59,10 +59,16 @@ struct alignas(sizeof(T) * V) Vec {
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> load_nt(const Vec<T, V>* p) {
   constexpr int W = sizeof(T) * V / 4;
+  static_assert(W == 1 || W == 2 || W == 4 || W == 8, "load_nt: 4- to 32-byte vectors");
   typedef uint32_t W4 __attribute__((ext_vector_type(4)));
   typedef uint32_t W2 __attribute__((ext_vector_type(2)));
   Vec<T, V> r;
-  if constexpr (W == 4) {
+  if constexpr (W == 8) {  // two 16-byte halves
+    const W4 x0 = __builtin_nontemporal_load((const W4*)p);
+    const W4 x1 = __builtin_nontemporal_load((const W4*)p + 1);
+    __builtin_memcpy(&r, &x0, sizeof x0);
+    __builtin_memcpy((char*)&r + sizeof x0, &x1, sizeof x1);
+  } else if constexpr (W == 4) {
     const W4 x = __builtin_nontemporal_load((const W4*)p);
     __builtin_memcpy(&r, &x, sizeof r);
   } else if constexpr (W == 2) {

@@ -9,14 +9,10 @@
 // coefficients, so L = 2^ceil(log2(2d-1)) points determine it.
 #include "pm_plan.h"
 
-#include <hip/hip_runtime.h>
-
 #include <stdlib.h>
 
 #include <algorithm>
-#include <map>
-#include <mutex>
-#include <tuple>
+#include <atomic>
 #include <vector>
 
 #include "../../include/pm.h"
@@ -24,6 +20,15 @@
 namespace pm {
 
 typedef unsigned __int128 u128;
+
+namespace {
+std::atomic<int> g_fail_countdown{-1};
+}
+
+void alloc_point() {
+  if (g_fail_countdown.load(std::memory_order_relaxed) < 0) return;
+  if (g_fail_countdown.fetch_sub(1) == 0) throw std::bad_alloc();
+}
 
 uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t m) {
   uint64_t r = 1 % m;
@@ -79,26 +84,6 @@ static const uint32_t kCrtPrimes[] = {
     469762049u,   //   7 * 2^26 + 1
     167772161u,   //   5 * 2^25 + 1
 };
-
-// Smallest generator of (Z/qZ)^*.
-static uint32_t primitive_root(uint32_t q) {
-  std::vector<uint64_t> f;
-  uint64_t x = q - 1;
-  for (uint64_t t = 2; t * t <= x; ++t) {
-    if (x % t == 0) {
-      f.push_back(t);
-      while (x % t == 0) x /= t;
-    }
-  }
-  if (x > 1) f.push_back(x);
-  for (uint32_t g = 2; g < q; ++g) {
-    bool ok = true;
-    for (uint64_t t : f)
-      if (powmod_u64(g, (q - 1) / t, q) == 1) { ok = false; break; }
-    if (ok) return g;
-  }
-  return 0;
-}
 
 static int env_int(const char* name, int dflt, int lo, int hi) {
   const char* v = getenv(name);
@@ -222,6 +207,7 @@ int make_cyclic_plan(uint64_t p, int m, int n, int k, int d, int logL, int elem_
 static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
                           int elem_bytes, int force_log, Plan* out) {
   if (!out) return PM_EINVAL;
+  alloc_point();  // the CRT bound below uses heap big integers
   if (elem_bytes != 4 && elem_bytes != 8) return PM_EINVAL;
   if (m < 1 || n < 1 || k < 1 || da < 1 || db < 1 || lo < 0 || nout < 1) return PM_EINVAL;
   if (p < 2) return PM_EINVAL;
@@ -285,76 +271,9 @@ int make_plan(uint64_t p, int m, int n, int k, int d, int elem_bytes, Plan* out)
   return make_slice_plan(p, m, n, k, d, d, 0, 2 * d - 1, elem_bytes, out);
 }
 
-// ---- device tables --------------------------------------------------------
+}  // namespace pm
 
-namespace {
-struct TableEntry {
-  Tw* dev = nullptr;
-  uint32_t linv = 0, linv_p = 0;
-};
-std::mutex g_mu;
-std::map<std::tuple<int, uint32_t, int>, TableEntry> g_tables;
-}  // namespace
-
-static uint32_t shoup_of(uint32_t w, uint32_t q) {
-  return (uint32_t)(((uint64_t)w << 32) / q);
-}
-
-int get_prime_const(uint32_t q, int logL, PrimeConst* out) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
-  const PassPlan PP = make_pass_plan(logL);
-  std::lock_guard<std::mutex> lock(g_mu);
-  auto key = std::make_tuple(dev, q, logL);
-  auto it = g_tables.find(key);
-  if (it == g_tables.end()) {
-    const uint64_t L = 1ull << logL;
-    const uint32_t g = primitive_root(q);
-    if (g == 0 || v2_u64(q - 1) < logL) return PM_EUNSUPPORTED;
-    const uint64_t w = powmod_u64(g, (q - 1) / L, q);
-    const uint64_t winv = powmod_u64(w, L - 1, q);
-    std::vector<uint32_t> pw(L), pwi(L);
-    uint64_t a = 1, b = 1;
-    for (uint64_t e = 0; e < L; ++e) {
-      pw[e] = (uint32_t)a; pwi[e] = (uint32_t)b;
-      a = a * w % q; b = b * winv % q;
-    }
-    const size_t cnt = PP.tw_count ? PP.tw_count : 1;
-    std::vector<Tw> host(2 * cnt);
-    for (int i = 0; i < PP.npass; ++i) {
-      const int r = PP.stages[i], s = PP.stride_log[i];
-      const uint32_t S = 1u << s;
-      for (uint32_t j = 0; j < S; ++j)
-        for (int v = 0; v < r; ++v)
-          for (uint32_t u = 0; u < (1u << v); ++u) {
-            // stage of half-size h = S * 2^v: exponent (j + u*S) * L / (2h)
-            uint64_t e = (uint64_t)(j + u * S) << (logL - s - v - 1);
-            // slot-major: consecutive threads j read consecutive pairs
-            size_t idx = PP.tw_off[i] + (size_t)(((1u << v) - 1) + u) * S + j;
-            host[idx] = Tw{pw[e], shoup_of(pw[e], q)};
-            host[cnt + idx] = Tw{pwi[e], shoup_of(pwi[e], q)};
-          }
-    }
-    TableEntry T;
-    if (hipMalloc(&T.dev, sizeof(Tw) * host.size()) != hipSuccess) return PM_ENOMEM;
-    if (hipMemcpy(T.dev, host.data(), sizeof(Tw) * host.size(), hipMemcpyHostToDevice) !=
-        hipSuccess) {
-      (void)hipFree(T.dev);
-      return PM_EDEVICE;
-    }
-    T.linv = (uint32_t)powmod_u64(L % q, q - 2, q);
-    T.linv_p = shoup_of(T.linv, q);
-    it = g_tables.emplace(key, T).first;
-  }
-  const size_t cnt = PP.tw_count ? PP.tw_count : 1;
-  out->q = q;
-  out->linv = it->second.linv;
-  out->linv_p = it->second.linv_p;
-  out->pad = 0;
-  out->mu = ~0ull / q;
-  out->tw_fwd = it->second.dev;
-  out->tw_inv = it->second.dev + cnt;
+extern "C" pm_status pm_debug_fail_alloc(int32_t countdown) {
+  pm::g_fail_countdown.store(countdown < 0 ? -1 : countdown);
   return PM_OK;
 }
-
-}  // namespace pm

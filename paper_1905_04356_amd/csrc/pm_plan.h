@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <new>
+
 namespace pm {
 
 constexpr int kMaxPrimes = 8;
@@ -105,10 +107,24 @@ bool is_prime_u64(uint64_t n);
 uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t m);
 int v2_u64(uint64_t x);
 
-// Device tables for (q, logL) on the current device: built on first use,
-// cached for the life of the process.  Returns 0 or a pm_status.
-int get_prime_const(uint32_t q, int logL, PrimeConst* out);
-
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// A place where host code of the library is about to allocate: throws
+// std::bad_alloc when the test hook pm_debug_fail_alloc has armed it (every
+// entry point turns that into PM_ENOMEM), else does nothing.
+void alloc_point();
+
+// Run an entry point's body; a host allocation failure becomes PM_ENOMEM and
+// no exception leaves the library.
+template <typename F>
+int guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return -3;  // PM_ENOMEM
+  } catch (...) {
+    return -1;  // PM_EINVAL
+  }
+}
 
 }  // namespace pm

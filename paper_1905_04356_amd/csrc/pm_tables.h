@@ -1,0 +1,63 @@
+// pm_tables.h -- device tables (roots of unity with their Shoup companions,
+// Vandermonde matrices) in device memory that the caller owns.
+//
+// The caller registers one or more regions per device (pm_tables_attach).
+// A table is carved from them the first time a call needs it and filled by a
+// kernel on that call's stream; nothing is copied from the host and the
+// library allocates no device memory.  Later calls reuse it.  A table first
+// filled inside a stream capture is filled again by the captured graph on
+// every replay, and by the next eager call that needs it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm_plan.h"
+
+namespace pm {
+
+// One (prime, transform length) pair whose twiddle tables a launch reads.
+struct TwKey {
+  uint32_t q;
+  int logL;
+};
+
+// Bytes of the forward and inverse twiddle tables for a length-2^logL
+// transform (pass structure of make_pass_plan), 256-byte aligned.
+uint64_t twiddle_table_bytes(int logL);
+// Bytes of the Vandermonde tables for degree bound d (V, W and the helper
+// arrays they are built from), 256-byte aligned.
+uint64_t vdm_table_bytes(int d);
+
+// Make the twiddle tables of keys[0 .. n) available to work enqueued on s
+// after this call: carve and fill missing ones, make s wait for fills
+// enqueued on another stream that may still run.  All or nothing: if the
+// regions cannot hold every missing table, nothing is carved or enqueued and
+// PM_ETABLES is returned.  PM_EDEVICE if a launch fails.
+int prepare_twiddles(const TwKey* keys, int n, hipStream_t s);
+
+// Constants and device table pointers of a prepared pair; PM_EINVAL if the
+// pair was never prepared on the current device.
+int prime_const(uint32_t q, int logL, PrimeConst* out);
+
+// Host part of PrimeConst (q, L^-1 and its companion, Barrett constant).
+void prime_const_host(uint32_t q, int logL, PrimeConst* out);
+// Primitive 2^logL-th root of unity mod q (0 if none).
+uint32_t root_of_unity(uint32_t q, int logL);
+
+// Vandermonde tables for evaluation at 0 .. 2d-2 mod p and interpolation
+// back: prepared like the twiddle tables.
+int prepare_vdm(uint32_t p, int d, hipStream_t s, const uint32_t** V, const uint32_t** W);
+
+// Incremented by pm_tables_reset: table pointers recorded under an older
+// epoch (in captured graphs) are stale.
+uint64_t tables_epoch();
+
+// Device fills (pm_tables.hip).  dst holds max(tw_count, 1) forward entries
+// followed by as many inverse ones.
+int launch_fill_twiddles(uint32_t q, int logL, uint32_t w, uint32_t winv, Tw* dst,
+                         hipStream_t s);
+// V: (2d-1) x d, W: (2d-1) x (2d-1), work: 2(2d-1) + 1 words of helper data.
+int launch_fill_vdm(uint32_t p, int d, uint32_t* V, uint32_t* W, uint32_t* work,
+                    hipStream_t s);
+
+}  // namespace pm

@@ -26,8 +26,4 @@ struct GemmLaunch {
 
 int launch_gemm_modp(const GemmLaunch& g, hipStream_t s);
 
-// Device Vandermonde tables for evaluation at 0 .. 2d-2 mod p (V, (2d-1) x d)
-// and interpolation (W, (2d-1) x (2d-1)); built on first use.  pm_status.
-int get_vdm_tables(uint32_t p, int d, const uint32_t** V, const uint32_t** W);
-
 }  // namespace pm

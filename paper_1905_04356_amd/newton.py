@@ -9,7 +9,8 @@ mod x^{2k}, one doubling step is
 where E is coefficients k .. 2k-1 of A X_k: a middle product (Section 2),
 then a truncated product.  Both run through pm_middle, on transforms of
 about 2k points.  X_1 = A(0)^{-1} comes from pm_matinv_host.  The
-iteration keeps -A so that the update needs no negation on the device.
+iteration keeps -A (negated once by pm_neg_mod) so that each update is a
+concatenation.
 
 Dixon's algorithm then multiplies by S again and again: S is a multiplier
 class (Section 2, "Polynomial matrix multiplication").  `evaluations`
@@ -33,23 +34,25 @@ def truncated_inverse(p: int, A: torch.Tensor, N: int, stream=None) -> torch.Ten
     dev, dt = A.device, A.dtype
     npdt = np.uint64 if dt == torch.uint64 else np.uint32
     A0 = A[0].to("cpu").numpy().astype(np.uint64)
-    X = torch.from_numpy(_b.pm_matinv_host(p, A0).astype(npdt)).to(dev)[None].contiguous()
-    if N == 1:
-        return X
-    n = A.shape[1]
-    # -A mod p, zero-padded to N coefficients (one elementwise pass)
-    negA = torch.zeros((max(N, A.shape[0]), n, n), dtype=torch.int64, device=dev)
-    negA[:A.shape[0]] = (p - A.to(torch.int64)) % p
-    negA = negA[:N].to(dt)
-    ws = polymat.Workspace(dev)
-    k = 1
-    while k < N:
-        k2 = min(2 * k, N)
-        h = k2 - k
-        negE = polymat.middle(p, negA[:k2], X, k, h, workspace=ws, stream=stream)
-        Y = polymat.middle(p, X, negE, 0, h, workspace=ws, stream=stream)
-        X = torch.cat([X, Y], dim=0)
-        k = k2
+    with polymat._on_stream(stream, A):
+        # everything below is ordered on one stream: `stream` or the current one
+        X = torch.from_numpy(_b.pm_matinv_host(p, A0).astype(npdt)).to(dev)[None].contiguous()
+        if N == 1:
+            return X
+        n = A.shape[1]
+        # -A mod p (pm_neg_mod), zero-padded to N coefficients
+        negA = torch.zeros((max(N, A.shape[0]), n, n), dtype=dt, device=dev)
+        polymat.neg(p, A.contiguous(), out=negA[:A.shape[0]])
+        negA = negA[:N]
+        ws = polymat.Workspace(dev)
+        k = 1
+        while k < N:
+            k2 = min(2 * k, N)
+            h = k2 - k
+            negE = polymat.middle(p, negA[:k2], X, k, h, workspace=ws)
+            Y = polymat.middle(p, X, negE, 0, h, workspace=ws)
+            X = torch.cat([X, Y], dim=0)
+            k = k2
     return X
 
 

@@ -7,6 +7,8 @@ torch.uint64 (p < 2^62), on a GPU device.
 """
 from __future__ import annotations
 
+import contextlib
+
 import torch
 
 from . import binding as _b
@@ -15,6 +17,73 @@ from . import binding as _b
 def _stream_ptr(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+@contextlib.contextmanager
+def _on_stream(stream, *inputs):
+    """Launch on `stream` (None: the current stream).  For another stream,
+    that stream first waits for the current stream's work (which produced
+    the inputs), the inputs are marked as in use on it, and tensors
+    allocated inside the block (outputs, workspaces) belong to it."""
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        yield
+        return
+    stream.wait_stream(cur)
+    for t in inputs:
+        if t is not None:
+            t.record_stream(stream)
+    with torch.cuda.stream(stream):
+        yield
+
+
+# ---- device tables -----------------------------------------------------------
+# libpm allocates no device memory: its tables live in regions that PyTorch
+# allocates here and registers once per device (pm_tables_attach), kept
+# alive for the life of the process.
+
+TABLE_REGION_BYTES = 64 << 20
+_regions: dict = {}
+
+
+def _dev_index(device) -> int:
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    return d.index if d.index is not None else torch.cuda.current_device()
+
+
+def attach_tables(device=None, nbytes: int = TABLE_REGION_BYTES) -> None:
+    """Register `nbytes` of device memory on `device` as a table region."""
+    idx = _dev_index(device)
+    nbytes = max(int(nbytes), 256)
+    with torch.cuda.device(idx):
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=torch.device("cuda", idx))
+        st = _b.pm_tables_attach(buf.data_ptr(), nbytes)
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_tables_attach")
+    _regions.setdefault(idx, []).append(buf)
+
+
+def reset_tables(device=None) -> None:
+    """Forget the tables and regions of `device` (no work may be in flight)."""
+    idx = _dev_index(device)
+    with torch.cuda.device(idx):
+        torch.cuda.synchronize()
+        _b.pm_tables_reset()
+    _regions.pop(idx, None)
+
+
+def _with_tables(device, call, need_bytes: int = 0) -> int:
+    """call() -> pm_status, with a table region attached on first use and
+    another one when the attached regions are full (the library enqueues
+    nothing before reporting that)."""
+    idx = _dev_index(device)
+    if idx not in _regions:
+        attach_tables(idx, max(TABLE_REGION_BYTES, need_bytes))
+    st = call()
+    if st == _b.PM_ETABLES:
+        attach_tables(idx, max(TABLE_REGION_BYTES, 2 * need_bytes))
+        st = call()
+    return st
 
 
 def _elem_bytes(t: torch.Tensor) -> int:
@@ -69,13 +138,15 @@ def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = Non
         raise ValueError("A and B must be GPU tensors")
     A = A.contiguous()
     B = B.contiguous()
-    if out is None:
-        out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
-    ws_bytes = _b.pm_workspace_bytes(p, m, n, k, d, eb)
-    ws = (workspace or _workspace(A.device)).get(ws_bytes)
-    fn = _b.pm_mul_u32 if eb == 4 else _b.pm_mul_u64
-    st = fn(p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
-            ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, A, B):
+        if out is None:
+            out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
+        ws_bytes = _b.pm_workspace_bytes(p, m, n, k, d, eb)
+        ws = (workspace or _workspace(A.device)).get(ws_bytes)
+        fn = _b.pm_mul_u32 if eb == 4 else _b.pm_mul_u64
+        st = _with_tables(A.device, lambda: fn(
+            p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream)), _b.pm_tables_bytes(p, m, n, k, d, eb))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_mul")
     return out
@@ -100,13 +171,15 @@ def middle(p: int, A: torch.Tensor, B: torch.Tensor, lo: int, length: int,
         raise ValueError("A and B must be GPU tensors")
     A = A.contiguous()
     B = B.contiguous()
-    if out is None:
-        out = torch.empty((length, m, k), dtype=A.dtype, device=A.device)
-    need = _b.pm_middle_plan(p, m, n, k, da, db, lo, length, eb).workspace_bytes
-    ws = (workspace or _workspace(A.device)).get(need)
-    fn = _b.pm_middle_u32 if eb == 4 else _b.pm_middle_u64
-    st = fn(p, m, n, k, da, db, lo, length, A.data_ptr(), B.data_ptr(), out.data_ptr(),
-            ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, A, B):
+        if out is None:
+            out = torch.empty((length, m, k), dtype=A.dtype, device=A.device)
+        need = _b.pm_middle_plan(p, m, n, k, da, db, lo, length, eb).workspace_bytes
+        ws = (workspace or _workspace(A.device)).get(need)
+        fn = _b.pm_middle_u32 if eb == 4 else _b.pm_middle_u64
+        st = _with_tables(A.device, lambda: fn(
+            p, m, n, k, da, db, lo, length, A.data_ptr(), B.data_ptr(), out.data_ptr(),
+            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_middle")
     return out
@@ -121,23 +194,25 @@ def middle_batched(p: int, As, Bs, windows, outs=None, workspace: Workspace | No
     if not As:
         return []
     eb = _elem_bytes(As[0])
-    if outs is None:
-        outs = [torch.empty((ln, A.shape[1], B.shape[2]), dtype=A.dtype, device=A.device)
-                for A, B, (lo, ln) in zip(As, Bs, windows)]
-    wins = []
     As = [A.contiguous() for A in As]
     Bs = [B.contiguous() for B in Bs]
-    for A, B, C, (lo, ln) in zip(As, Bs, outs, windows):
-        da, m, n = A.shape
-        db, n2, k = B.shape
-        if n2 != n or _elem_bytes(A) != eb or _elem_bytes(B) != eb:
-            raise ValueError("inconsistent batch member")
-        wins.append((m, n, k, da, db, lo, ln, A.data_ptr(), B.data_ptr(), C.data_ptr()))
-    arr = _b.windows_array(wins)
-    need = _b.pm_middle_batched_workspace_bytes(p, arr, len(wins), eb)
-    ws = (workspace or _workspace(As[0].device)).get(need)
-    fn = _b.pm_middle_batched_u32 if eb == 4 else _b.pm_middle_batched_u64
-    st = fn(p, len(wins), arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, *As, *Bs):
+        if outs is None:
+            outs = [torch.empty((ln, A.shape[1], B.shape[2]), dtype=A.dtype, device=A.device)
+                    for A, B, (lo, ln) in zip(As, Bs, windows)]
+        wins = []
+        for A, B, C, (lo, ln) in zip(As, Bs, outs, windows):
+            da, m, n = A.shape
+            db, n2, k = B.shape
+            if n2 != n or _elem_bytes(A) != eb or _elem_bytes(B) != eb:
+                raise ValueError("inconsistent batch member")
+            wins.append((m, n, k, da, db, lo, ln, A.data_ptr(), B.data_ptr(), C.data_ptr()))
+        arr = _b.windows_array(wins)
+        need = _b.pm_middle_batched_workspace_bytes(p, arr, len(wins), eb)
+        ws = (workspace or _workspace(As[0].device)).get(need)
+        fn = _b.pm_middle_batched_u32 if eb == 4 else _b.pm_middle_batched_u64
+        st = _with_tables(As[0].device, lambda: fn(p, len(wins), arr, ws.data_ptr(), ws.numel(),
+                                                   _stream_ptr(stream)))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_middle_batched")
     return outs
@@ -155,12 +230,15 @@ def mul_vdm(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
         raise TypeError("mul_vdm takes torch.uint32 residues")
     A = A.contiguous()
     B = B.contiguous()
-    if out is None:
-        out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
-    need = _b.pm_vdm_workspace_bytes(p, m, n, k, d)
-    ws = (workspace or _workspace(A.device)).get(need)
-    st = _b.pm_mul_vdm_u32(p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(),
-                           ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, A, B):
+        if out is None:
+            out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
+        need = _b.pm_vdm_workspace_bytes(p, m, n, k, d)
+        ws = (workspace or _workspace(A.device)).get(need)
+        N = 2 * d - 1
+        st = _with_tables(A.device, lambda: _b.pm_mul_vdm_u32(
+            p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream)), 4 * N * (d + N + 2) + 1024)
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_mul_vdm")
     return out
@@ -184,15 +262,16 @@ def mbasis(p: int, F: torch.Tensor, sigma: int, shifts: torch.Tensor,
     shifts = shifts.to(device=F.device, dtype=torch.int64).contiguous()
     if tuple(shifts.shape) != (count, m):
         raise ValueError("shifts must be (count, m)")
-    P = torch.empty((count, sigma + 1, m, m), dtype=torch.uint32, device=F.device)
-    rd = torch.empty((count, m), dtype=torch.int64, device=F.device)
     need = _b.pm_mbasis_workspace_bytes(count, m, n, sigma)
     if need is None:
         raise _b.PmError(_b.PM_EUNSUPPORTED, "pm_mbasis_u32")
-    ws = (workspace or _workspace(F.device)).get(need)
-    st = _b.lib().pm_mbasis_u32(p, count, m, n, sigma, F.data_ptr(), sigma * m * n,
-                                shifts.data_ptr(), P.data_ptr(), rd.data_ptr(), ws.data_ptr(),
-                                ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, F, shifts):
+        P = torch.empty((count, sigma + 1, m, m), dtype=torch.uint32, device=F.device)
+        rd = torch.empty((count, m), dtype=torch.int64, device=F.device)
+        ws = (workspace or _workspace(F.device)).get(need)
+        st = _b.lib().pm_mbasis_u32(p, count, m, n, sigma, F.data_ptr(), sigma * m * n,
+                                    shifts.data_ptr(), P.data_ptr(), rd.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream_ptr(stream))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_mbasis_u32")
     return P, rd
@@ -206,9 +285,11 @@ def evaluate(p: int, X: torch.Tensor, role: int, stream=None) -> torch.Tensor:
     eb = _elem_bytes(X)
     X = X.contiguous()
     nbytes = _b.pm_eval_bytes(p, role, rows, cols, d, eb)
-    out = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
-    fn = _b.pm_eval_u32 if eb == 4 else _b.pm_eval_u64
-    st = fn(p, role, rows, cols, d, X.data_ptr(), out.data_ptr(), nbytes, _stream_ptr(stream))
+    with _on_stream(stream, X):
+        out = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        fn = _b.pm_eval_u32 if eb == 4 else _b.pm_eval_u64
+        st = _with_tables(X.device, lambda: fn(p, role, rows, cols, d, X.data_ptr(),
+                                               out.data_ptr(), nbytes, _stream_ptr(stream)))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_eval")
     return out
@@ -223,24 +304,40 @@ def mul_batched(p: int, As, Bs, outs=None, workspace: Workspace | None = None,
     if not As:
         return []
     eb = _elem_bytes(As[0])
-    if outs is None:
-        outs = [torch.empty((2 * A.shape[0] - 1, A.shape[1], B.shape[2]), dtype=A.dtype,
-                            device=A.device) for A, B in zip(As, Bs)]
-    prods = []
     A_evals = A_evals or [None] * len(As)
     B_evals = B_evals or [None] * len(As)
-    for A, B, C, Ae, Be in zip(As, Bs, outs, A_evals, B_evals):
-        d, m, n = A.shape
-        if B.shape[0] != d or B.shape[1] != n or _elem_bytes(B) != eb or _elem_bytes(A) != eb:
-            raise ValueError("inconsistent batch member")
-        prods.append((m, n, B.shape[2], d, A.data_ptr(), B.data_ptr(), C.data_ptr(),
-                      Ae.data_ptr() if Ae is not None else None,
-                      Be.data_ptr() if Be is not None else None))
-    arr = _b.products_array(prods)
-    need = _b.pm_batched_workspace_bytes(p, arr, len(prods), eb)
-    ws = (workspace or _workspace(As[0].device)).get(need)
-    fn = _b.pm_mul_batched_u32 if eb == 4 else _b.pm_mul_batched_u64
-    st = fn(p, len(prods), arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream))
+    with _on_stream(stream, *As, *Bs, *A_evals, *B_evals):
+        if outs is None:
+            outs = [torch.empty((2 * A.shape[0] - 1, A.shape[1], B.shape[2]), dtype=A.dtype,
+                                device=A.device) for A, B in zip(As, Bs)]
+        prods = []
+        for A, B, C, Ae, Be in zip(As, Bs, outs, A_evals, B_evals):
+            d, m, n = A.shape
+            if (B.shape[0] != d or B.shape[1] != n or _elem_bytes(B) != eb
+                    or _elem_bytes(A) != eb):
+                raise ValueError("inconsistent batch member")
+            prods.append((m, n, B.shape[2], d, A.data_ptr(), B.data_ptr(), C.data_ptr(),
+                          Ae.data_ptr() if Ae is not None else None,
+                          Be.data_ptr() if Be is not None else None))
+        arr = _b.products_array(prods)
+        need = _b.pm_batched_workspace_bytes(p, arr, len(prods), eb)
+        ws = (workspace or _workspace(As[0].device)).get(need)
+        fn = _b.pm_mul_batched_u32 if eb == 4 else _b.pm_mul_batched_u64
+        st = _with_tables(As[0].device, lambda: fn(p, len(prods), arr, ws.data_ptr(),
+                                                   ws.numel(), _stream_ptr(stream)))
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_mul_batched")
     return outs
+
+
+def neg(p: int, X: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """-X mod p elementwise on the GPU (pm_neg_mod); out may be X (in place)."""
+    eb = _elem_bytes(X)
+    X = X.contiguous()
+    with _on_stream(stream, X):
+        if out is None:
+            out = torch.empty_like(X)
+        st = _b.pm_neg_mod(p, X.data_ptr(), out.data_ptr(), X.numel(), eb, _stream_ptr(stream))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_neg_mod")
+    return out

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(B.EXPORTS)
-    assert L.pm_abi_version() == 3
+    assert L.pm_abi_version() == 4
     assert B.status_str(B.PM_EWORKSPACE).startswith("PM_EWORKSPACE")
 
 
@@ -241,3 +241,105 @@ def test_device_mbasis_argument_checks():
     # a stride shorter than one instance
     assert lib.pm_mbasis_u32(97, 1, 2, 1, 3, one, 5, one, one, one, ctypes.c_void_p(256),
                              1 << 20, None) == B.PM_EINVAL
+
+
+def test_tables_attach_and_negation_reject_bad_arguments():
+    """Checks that run before the device is touched."""
+    L = B.lib()
+    assert L.pm_tables_attach(None, 1 << 20) == B.PM_EINVAL
+    assert L.pm_tables_attach(ctypes.c_void_p((1 << 20) + 16), 1 << 20) == B.PM_EINVAL
+    assert L.pm_tables_attach(ctypes.c_void_p(1 << 20), 255) == B.PM_EINVAL
+    X, Y = 1 << 20, 2 << 20
+    assert L.pm_neg_mod(97, None, Y, 4, 4, None) == B.PM_EINVAL
+    assert L.pm_neg_mod(97, X, Y, 4, 2, None) == B.PM_EINVAL          # elem_bytes
+    assert L.pm_neg_mod(1, X, Y, 4, 4, None) == B.PM_EINVAL            # p < 2
+    assert L.pm_neg_mod(1 << 32, X, Y, 4, 4, None) == B.PM_ERANGE
+    assert L.pm_neg_mod(1 << 62, X, Y, 4, 8, None) == B.PM_ERANGE
+    assert L.pm_neg_mod(97, X, X + 4, 4, 4, None) == B.PM_EINVAL      # partial overlap
+    assert L.pm_neg_mod(97, X + 4, Y, 4, 8, None) == B.PM_EINVAL      # misaligned
+    assert L.pm_neg_mod(97, X, Y, 0, 4, None) == B.PM_OK               # nothing to do
+
+
+def _enomem_calls():
+    """(name, call) for every entry point whose host code allocates before it
+    touches the device; pointers are never dereferenced."""
+    A, Bp, C, WS = 1 << 20, 2 << 20, 3 << 20, 64 << 20
+    p = 998244353
+    L = B.lib()
+    info = B.pm_plan_info()
+    out = ctypes.c_uint64(0)
+    prods = B.products_array([(4, 4, 4, 16, A, Bp, C), (8, 4, 2, 100, A, Bp, C + (1 << 16)),
+                              (2, 2, 2, 9, A, Bp, C + (2 << 16))])
+    wins = B.windows_array([(4, 4, 4, 16, 32, 16, 16, A, Bp, C),
+                            (2, 3, 2, 5, 9, 5, 4, A, Bp, C + (1 << 16))])
+    F = (ctypes.c_uint64 * 8)(*range(8))
+    sh = (ctypes.c_int64 * 2)(0, 0)
+    P = (ctypes.c_uint64 * 32)()
+    rd = (ctypes.c_int64 * 2)()
+    M = (ctypes.c_uint64 * 4)(1, 2, 3, 5)
+    Mi = (ctypes.c_uint64 * 4)()
+    ws_big = 1 << 40
+    return [
+        ("pm_plan", lambda: L.pm_plan(p, 4, 4, 4, 16, 4, ctypes.byref(info))),
+        ("pm_workspace_bytes", lambda: L.pm_workspace_bytes(p, 4, 4, 4, 16, 4, ctypes.byref(out))),
+        ("pm_tables_bytes", lambda: L.pm_tables_bytes(p, 4, 4, 4, 16, 4, ctypes.byref(out))),
+        ("pm_tables_attach", lambda: L.pm_tables_attach(ctypes.c_void_p(WS), 1 << 20)),
+        ("pm_mul_u32", lambda: L.pm_mul_u32(p, 4, 4, 4, 16, A, Bp, C, WS, ws_big, None)),
+        ("pm_mul_u64", lambda: L.pm_mul_u64(p, 4, 4, 4, 16, A, Bp, C, WS, ws_big, None)),
+        ("pm_middle_plan", lambda: L.pm_middle_plan(p, 2, 2, 2, 5, 9, 5, 4, 4,
+                                                    ctypes.byref(info))),
+        ("pm_middle_u32", lambda: L.pm_middle_u32(p, 2, 2, 2, 5, 9, 5, 4, A, Bp, C, WS, ws_big,
+                                                  None)),
+        ("pm_middle_u64", lambda: L.pm_middle_u64(p, 2, 2, 2, 5, 9, 5, 4, A, Bp, C, WS, ws_big,
+                                                  None)),
+        ("pm_eval_bytes", lambda: L.pm_eval_bytes(p, 0, 4, 4, 16, 4, ctypes.byref(out))),
+        ("pm_eval_u32", lambda: L.pm_eval_u32(p, 0, 4, 4, 16, A, WS, ws_big, None)),
+        ("pm_eval_u64", lambda: L.pm_eval_u64(p, 0, 4, 4, 16, A, WS, ws_big, None)),
+        ("pm_mul_vdm_u32", lambda: L.pm_mul_vdm_u32(1000000007, 4, 4, 4, 16, A, Bp, C, WS,
+                                                    ws_big, None)),
+        ("pm_batched_workspace_bytes", lambda: L.pm_batched_workspace_bytes(
+            p, 3, prods, 4, ctypes.byref(out))),
+        ("pm_mul_batched_u32", lambda: L.pm_mul_batched_u32(p, 3, prods, WS, ws_big, None)),
+        ("pm_mul_batched_u64", lambda: L.pm_mul_batched_u64(p, 3, prods, WS, ws_big, None)),
+        ("pm_middle_batched_workspace_bytes", lambda: L.pm_middle_batched_workspace_bytes(
+            p, 2, wins, 4, ctypes.byref(out))),
+        ("pm_middle_batched_u32", lambda: L.pm_middle_batched_u32(p, 2, wins, WS, ws_big, None)),
+        ("pm_middle_batched_u64", lambda: L.pm_middle_batched_u64(p, 2, wins, WS, ws_big, None)),
+        ("pm_mbasis_host", lambda: L.pm_mbasis_host(97, 2, 1, 4, F, sh, P, rd)),
+        ("pm_matinv_host", lambda: L.pm_matinv_host(97, 2, M, Mi)),
+    ]
+
+
+@pytest.mark.parametrize("name", [n for n, _ in _enomem_calls()])
+def test_entry_points_return_enomem_on_injected_allocation_failure(name):
+    """The library's host allocation points throw std::bad_alloc when the
+    test hook arms them; every entry point must turn that into PM_ENOMEM
+    (no exception crosses the C ABI) and enqueue nothing."""
+    call = dict(_enomem_calls())[name]
+    L = B.lib()
+    assert L.pm_debug_fail_alloc(0) == B.PM_OK
+    try:
+        assert call() == B.PM_ENOMEM
+    finally:
+        L.pm_debug_fail_alloc(-1)
+    # disarmed: host-only entry points succeed again
+    if name in ("pm_plan", "pm_workspace_bytes", "pm_tables_bytes", "pm_middle_plan",
+                "pm_eval_bytes", "pm_batched_workspace_bytes",
+                "pm_middle_batched_workspace_bytes", "pm_mbasis_host", "pm_matinv_host"):
+        assert call() == B.PM_OK
+
+
+def test_tables_bytes_covers_every_route():
+    """pm_tables_bytes counts one twiddle table per (prime, length) of the
+    plan, the wrapped form's two plans, and the Vandermonde tables."""
+    direct = B.pm_tables_bytes(998244353, 8, 8, 8, 256, 4)
+    crt = B.pm_tables_bytes((1 << 62) - 57, 8, 8, 8, 256, 8)
+    assert 0 < direct < crt
+    assert crt == direct * B.pm_plan((1 << 62) - 57, 8, 8, 8, 256, 8).num_primes or crt > direct
+    wrapped = B.pm_tables_bytes(998244353, 128, 8, 128, 4740, 4)
+    plain = B.pm_tables_bytes(998244353, 8, 8, 8, 4096, 4)      # same L = 2^13, not wrapped
+    assert B.pm_plan(998244353, 128, 8, 128, 4740, 4).wrap_log2_len == 13
+    assert wrapped > plain
+    vdm = B.pm_tables_bytes(1000000007, 8, 8, 8, 64, 4)        # routed to Vandermonde
+    N = 2 * 64 - 1
+    assert vdm >= 4 * N * 64 + 4 * N * N

@@ -29,6 +29,23 @@ def test_host_mbasis_equals_oracle(p, sigma, m, n, shift, seed):
     assert rd == X.rdeg(ref, shift)
 
 
+def test_host_mbasis_wide_combinations_62bit():
+    """A 62-bit prime with m = 48 > n = 40: the dependent rows of the first
+    round combine 41 rows, and a 128-bit sum of 41 products of residues near
+    2^62 wraps without the intermediate reductions."""
+    p = (1 << 62) - 57
+    sigma, m, n = 2, 48, 40
+    rng = np.random.default_rng(62)
+    F = np.array([[[int(rng.integers(p - (1 << 40), p)) for _ in range(n)] for _ in range(m)]
+                  for _ in range(sigma)], dtype=object)
+    shift = [0] * m
+    ref = X.mbasis(F, sigma, shift, p)
+    P, rd = B.pm_mbasis_host(p, F.astype(np.uint64), sigma, shift)
+    got = X.trim(P.astype(object))
+    assert got.shape == ref.shape and np.array_equal(got, ref)
+    assert rd == X.rdeg(ref, shift)
+
+
 def test_host_mbasis_rejects_bad_arguments():
     F = np.zeros((2, 2, 1), dtype=np.uint64)
     for p in (1, 91, 1 << 40):               # not prime
