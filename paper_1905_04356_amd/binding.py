@@ -71,6 +71,21 @@ class pm_window_product(ctypes.Structure):
 _lib = None
 
 
+def _start_torch_runtime() -> None:
+    """PyTorch's wheel carries a HIP runtime of its own, while libpm.so links
+    the system one, so a process that uses both holds two.  They cooperate
+    when PyTorch's is loaded and initialised first; when libpm.so (and with
+    it the system runtime) is loaded before PyTorch, libpm's first kernel
+    launch fails with hipErrorOutOfMemory (pinned allocations refused with
+    out-of-resources).  So PyTorch, where it is installed, starts first."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """Load libpm.so (built by paper_1905_04356_amd.build); raise if absent."""
     global _lib
@@ -79,6 +94,7 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1905_04356_amd.build`")
+    _start_torch_runtime()
     L = ctypes.CDLL(LIB_PATH)
     i32, u32, u64, vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
     L.pm_status_str.argtypes = [ctypes.c_int]
