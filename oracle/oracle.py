@@ -30,7 +30,7 @@ import os
 import numpy as np
 
 __all__ = ["lib", "is_prime", "powmod", "polymatmul", "polymatmul_entries",
-           "middle_product", "middle_entries", "eval_at", "matmul", "polymul",
+           "middle_product", "middle_entries", "eval_at", "eval_points", "matmul", "polymul",
            "point_check", "freivalds_check", "host_threads"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -69,6 +69,16 @@ def _load(path: str | None = None):
         f.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                       _u64p, _u64p, _u64p]
         f.restype = None
+    for f in (L.orc_project_left_mt, L.orc_project_right_mt):
+        f.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                      _u64p, _u64p, _u64p, ctypes.c_int]
+        f.restype = None
+    L.orc_eval_points.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  _u64p, ctypes.c_int, _u64p, _u64p, ctypes.c_int]
+    L.orc_eval_points.restype = None
+    L.orc_polymul_sum.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _u64p, _u64p,
+                                  _u64p, ctypes.c_int]
+    L.orc_polymul_sum.restype = None
     return L
 
 
@@ -207,29 +217,49 @@ def _seeded_vectors(seed: int, p: int, count: int, length: int) -> list[np.ndarr
             np.zeros(length, dtype=np.uint64) for _ in range(count)]
 
 
-def point_check(p: int, A, B, C, seed: int = 0, points: int = 4, L=None) -> bool:
+def eval_points(p: int, X, pts, threads: int | None = None, L=None) -> np.ndarray:
+    """X(r) for every entry of a (D, R, S) polynomial matrix and every r in
+    pts, by Horner: shape (len(pts), R, S)."""
+    X = _u64(X)
+    D, R, S = X.shape
+    pts = _u64([int(r) % int(p) for r in pts])
+    out = np.zeros((len(pts), R, S), dtype=np.uint64)
+    (L or lib()).orc_eval_points(int(p), R, S, D, _ptr(X), len(pts), _ptr(pts), _ptr(out),
+                                 threads or host_threads())
+    return out
+
+
+def _seeded_points(seed: int, p: int, count: int) -> list[int]:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [int(rng.integers(0, p, dtype=np.uint64)) if p > 1 else 0 for _ in range(count)]
+
+
+def point_check(p: int, A, B, C, seed: int = 0, points: int = 4, L=None,
+                threads: int | None = None) -> bool:
     """C(r) == A(r) B(r) for `points` seeded r in F_p, on every entry.
 
     A wrong coefficient anywhere in C survives one point with probability at
     most (2d-2)/p (a nonzero polynomial of degree <= 2d-2 has at most 2d-2
     roots)."""
     L = L or lib()
-    rng = np.random.Generator(np.random.PCG64(seed))
-    for _ in range(points):
-        r = int(rng.integers(0, p, dtype=np.uint64)) if p > 1 else 0
-        lhs = eval_at(p, C, r, L)
-        rhs = matmul(p, eval_at(p, A, r, L), eval_at(p, B, r, L), L)
-        if not np.array_equal(lhs, rhs):
+    pts = _seeded_points(seed, p, points)
+    eA = eval_points(p, A, pts, threads, L)
+    eB = eval_points(p, B, pts, threads, L)
+    eC = eval_points(p, C, pts, threads, L)
+    for t in range(len(pts)):
+        if not np.array_equal(eC[t], matmul(p, eA[t], eB[t], L)):
             return False
     return True
 
 
-def freivalds_check(p: int, A, B, C, seed: int = 1, rounds: int = 2, L=None) -> bool:
+def freivalds_check(p: int, A, B, C, seed: int = 1, rounds: int = 2, L=None,
+                    threads: int | None = None) -> bool:
     """u^T C(x) v == sum_l (u^T A)_l(x) * (B v)_l(x) coefficient by coefficient,
     for `rounds` seeded pairs (u, v). A wrong coefficient c of one entry C_ij
     changes coefficient c of the projection unless u_i v_j == 0 (probability
     about 2/p)."""
     L = L or lib()
+    th = threads or host_threads()
     A, B, C = _u64(A), _u64(B), _u64(C)
     d, m, n = A.shape
     k = B.shape[2]
@@ -238,20 +268,18 @@ def freivalds_check(p: int, A, B, C, seed: int = 1, rounds: int = 2, L=None) -> 
         u, v = np.ascontiguousarray(u[:m]), np.ascontiguousarray(v[:k])
         uA = np.zeros((d, n), dtype=np.uint64)
         Bv = np.zeros((d, n), dtype=np.uint64)
-        L.orc_project_left(int(p), m, n, d, _ptr(A), _ptr(u), _ptr(uA))
-        L.orc_project_right(int(p), n, k, d, _ptr(B), _ptr(v), _ptr(Bv))
+        L.orc_project_left_mt(int(p), m, n, d, _ptr(A), _ptr(u), _ptr(uA), th)
+        L.orc_project_right_mt(int(p), n, k, d, _ptr(B), _ptr(v), _ptr(Bv), th)
         uC = np.zeros((2 * d - 1, k), dtype=np.uint64)
-        L.orc_project_left(int(p), m, k, 2 * d - 1, _ptr(C), _ptr(u), _ptr(uC))
+        L.orc_project_left_mt(int(p), m, k, 2 * d - 1, _ptr(C), _ptr(u), _ptr(uC), th)
         uCv = np.zeros((2 * d - 1, 1), dtype=np.uint64)
-        L.orc_project_right(int(p), 1, k, 2 * d - 1,
-                            _ptr(np.ascontiguousarray(uC.reshape(2 * d - 1, 1, k))),
-                            _ptr(v), _ptr(uCv))
+        L.orc_project_right_mt(int(p), 1, k, 2 * d - 1,
+                               _ptr(np.ascontiguousarray(uC.reshape(2 * d - 1, 1, k))),
+                               _ptr(v), _ptr(uCv), th)
+        # sum over l of the univariate products (u^T A)_l (B v)_l
         rhs = np.zeros(2 * d - 1, dtype=np.uint64)
-        pp = np.uint64(p)
-        for l in range(n):
-            prod = polymul(p, np.ascontiguousarray(uA[:, l]),
-                           np.ascontiguousarray(Bv[:, l]), L)
-            rhs = (rhs + prod) % pp  # both < p < 2^63: no wrap
+        L.orc_polymul_sum(int(p), n, d, _ptr(np.ascontiguousarray(uA.T)),
+                          _ptr(np.ascontiguousarray(Bv.T)), _ptr(rhs), th)
         if not np.array_equal(uCv[:, 0], rhs):
             return False
     return True

@@ -274,18 +274,88 @@ int orc_polymatmul_entries(uint64_t p, int m, int n, int k, int d,
 
 /* ---- checkers ------------------------------------------------------------ */
 
-/* out[i*cols + j] = X_ij(r) mod p, X stored (deg, rows, cols) coefficient-major.
- * Horner's rule from the top coefficient down. */
+/* Work split for the checkers: item ranges [lo, hi) handed out to threads. */
+typedef struct {
+    void (*fn)(void* ctx, size_t lo, size_t hi);
+    void* ctx;
+    size_t count, chunk, next;
+    pthread_mutex_t lock;
+} split_t;
+
+static void* split_worker(void* arg) {
+    split_t* S = (split_t*)arg;
+    for (;;) {
+        pthread_mutex_lock(&S->lock);
+        size_t lo = S->next;
+        S->next = lo + S->chunk < S->count ? lo + S->chunk : S->count;
+        size_t hi = S->next;
+        pthread_mutex_unlock(&S->lock);
+        if (lo >= hi) break;
+        S->fn(S->ctx, lo, hi);
+    }
+    return NULL;
+}
+
+static void split_run(void (*fn)(void*, size_t, size_t), void* ctx, size_t count,
+                      size_t chunk, int threads) {
+    split_t S;
+    S.fn = fn; S.ctx = ctx; S.count = count; S.chunk = chunk ? chunk : 1; S.next = 0;
+    pthread_mutex_init(&S.lock, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t tid[256];
+    int started = 0;
+    for (int t = 0; t < threads; ++t)
+        if (pthread_create(&tid[t], NULL, split_worker, &S) == 0) ++started;
+    if (started == 0) split_worker(&S);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    pthread_mutex_destroy(&S.lock);
+}
+
+/* Horner evaluation of every entry at several points. */
+typedef struct {
+    uint64_t p;
+    size_t rc;             /* entries (rows * cols) */
+    int deg, npts;
+    const uint64_t* X;     /* (deg, rows, cols) coefficient-major */
+    const uint64_t* pts;   /* npts points, reduced mod p */
+    uint64_t* out;         /* out[t * rc + e] = X_e(pts[t]) */
+} eval_t;
+
+static void eval_range(void* ctx, size_t lo, size_t hi) {
+    const eval_t* E = (const eval_t*)ctx;
+    const uint64_t p = E->p;
+    for (int t = 0; t < E->npts; ++t) {
+        const uint64_t r = E->pts[t];
+        uint64_t* o = E->out + (size_t)t * E->rc;
+        for (size_t e = lo; e < hi; ++e) o[e] = 0;
+        for (int c = E->deg - 1; c >= 0; --c) {
+            const uint64_t* row = E->X + (size_t)c * E->rc;
+            if (p <= 0xFFFFFFFFull) {
+                /* o r + x <= (p-1)^2 + (p-1) < 2^64 */
+                for (size_t e = lo; e < hi; ++e) o[e] = (o[e] * r + row[e] % p) % p;
+            } else {
+                for (size_t e = lo; e < hi; ++e)
+                    o[e] = (uint64_t)(((u128)o[e] * r + row[e] % p) % p);
+            }
+        }
+    }
+}
+
+/* out[t*rows*cols + i*cols + j] = X_ij(pts[t]) mod p, X stored (deg, rows, cols)
+ * coefficient-major; Horner's rule from the top coefficient down. */
+void orc_eval_points(uint64_t p, int rows, int cols, int deg, const uint64_t* X, int npts,
+                     const uint64_t* pts, uint64_t* out, int threads) {
+    uint64_t* r = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(npts > 0 ? npts : 1));
+    for (int t = 0; t < npts; ++t) r[t] = pts[t] % p;
+    eval_t E = {p, (size_t)rows * cols, deg, npts, X, r, out};
+    split_run(eval_range, &E, E.rc, 4096, threads);
+    free(r);
+}
+
 void orc_eval_at(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
                  uint64_t r, uint64_t* out) {
-    const size_t rc = (size_t)rows * cols;
-    for (size_t e = 0; e < rc; ++e) out[e] = 0;
-    r %= p;
-    for (int c = deg - 1; c >= 0; --c) {
-        const uint64_t* row = X + (size_t)c * rc;
-        for (size_t e = 0; e < rc; ++e)
-            out[e] = (uint64_t)(((u128)out[e] * r + row[e] % p) % p);
-    }
+    orc_eval_points(p, rows, cols, deg, X, 1, &r, out, 1);
 }
 
 /* Plain matrix product mod p: Z (m x k) = X (m x n) * Y (n x k), row-major. */
@@ -300,28 +370,126 @@ void orc_matmul(uint64_t p, int m, int n, int k, const uint64_t* X,
         }
 }
 
+/* Projections over the coefficients c of a (deg, rows, cols) matrix. */
+typedef struct {
+    uint64_t p;
+    int rows, cols, left;
+    const uint64_t* X;
+    const uint64_t* w;     /* u (rows) for left, v (cols) for right; reduced mod p */
+    uint64_t* out;         /* left: (deg, cols); right: (deg, rows) */
+} proj_t;
+
+static void proj_range(void* ctx, size_t lo, size_t hi) {
+    const proj_t* P = (const proj_t*)ctx;
+    const uint64_t p = P->p, lim = safe_terms(p);
+    const int rows = P->rows, cols = P->cols;
+    const int width = P->left ? cols : rows;
+    u128* acc = (u128*)malloc(sizeof(u128) * (size_t)width);
+    for (size_t c = lo; c < hi; ++c) {
+        const uint64_t* Xc = P->X + c * (size_t)rows * cols;
+        for (int t = 0; t < width; ++t) acc[t] = 0;
+        if (P->left) {
+            /* out[c][col] = sum_row u[row] X[c][row][col] */
+            uint64_t cnt = 0;
+            for (int row = 0; row < rows; ++row) {
+                const uint64_t ur = P->w[row];
+                for (int col = 0; col < cols; ++col)
+                    acc[col] += (u128)ur * (Xc[(size_t)row * cols + col] % p);
+                if (++cnt == lim) {
+                    for (int col = 0; col < cols; ++col) acc[col] %= p;
+                    cnt = 0;
+                }
+            }
+        } else {
+            /* out[c][row] = sum_col X[c][row][col] v[col] */
+            for (int row = 0; row < rows; ++row) {
+                u128 a = 0;
+                uint64_t cnt = 0;
+                for (int col = 0; col < cols; ++col) {
+                    a += (u128)(Xc[(size_t)row * cols + col] % p) * P->w[col];
+                    if (++cnt == lim) { a %= p; cnt = 0; }
+                }
+                acc[row] = a;
+            }
+        }
+        for (int t = 0; t < width; ++t) P->out[c * (size_t)width + t] = (uint64_t)(acc[t] % p);
+    }
+    free(acc);
+}
+
+static void project(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
+                    const uint64_t* w, uint64_t* out, int left, int threads) {
+    const int width = left ? rows : cols;
+    uint64_t* wr = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(width > 0 ? width : 1));
+    for (int t = 0; t < width; ++t) wr[t] = w[t] % p;
+    proj_t P = {p, rows, cols, left, X, wr, out};
+    split_run(proj_range, &P, (size_t)deg, 16, threads);
+    free(wr);
+}
+
 /* Left projection: out[c][col] = sum_row u[row] * X[c][row][col] mod p. */
 void orc_project_left(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
                       const uint64_t* u, uint64_t* out) {
-    for (int c = 0; c < deg; ++c)
-        for (int col = 0; col < cols; ++col) {
-            u128 acc = 0;
-            for (int row = 0; row < rows; ++row)
-                acc = (acc + (u128)(u[row] % p) *
-                                 (X[((size_t)c * rows + row) * cols + col] % p)) % p;
-            out[(size_t)c * cols + col] = (uint64_t)acc;
-        }
+    project(p, rows, cols, deg, X, u, out, 1, 1);
 }
 
 /* Right projection: out[c][row] = sum_col X[c][row][col] * v[col] mod p. */
 void orc_project_right(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
                        const uint64_t* v, uint64_t* out) {
-    for (int c = 0; c < deg; ++c)
-        for (int row = 0; row < rows; ++row) {
-            u128 acc = 0;
-            for (int col = 0; col < cols; ++col)
-                acc = (acc + (u128)(X[((size_t)c * rows + row) * cols + col] % p) *
-                                 (v[col] % p)) % p;
-            out[(size_t)c * rows + row] = (uint64_t)acc;
+    project(p, rows, cols, deg, X, v, out, 0, 1);
+}
+
+/* Threaded forms of the two projections. */
+void orc_project_left_mt(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
+                         const uint64_t* u, uint64_t* out, int threads) {
+    project(p, rows, cols, deg, X, u, out, 1, threads);
+}
+
+void orc_project_right_mt(uint64_t p, int rows, int cols, int deg, const uint64_t* X,
+                          const uint64_t* v, uint64_t* out, int threads) {
+    project(p, rows, cols, deg, X, v, out, 0, threads);
+}
+
+/* Sum of n univariate schoolbook products: out[c] = sum_l sum_{a+b=c} U[l][a] V[l][b]
+ * mod p, U and V holding n polynomials of d coefficients each (row l at l*d),
+ * for 0 <= c <= 2d-2; threads split the output coefficients. */
+typedef struct {
+    uint64_t p;
+    int n, d;
+    const uint64_t* U;
+    const uint64_t* V;
+    uint64_t* out;
+} psum_t;
+
+static void psum_range(void* ctx, size_t lo, size_t hi) {
+    const psum_t* S = (const psum_t*)ctx;
+    const uint64_t p = S->p, lim = safe_terms(p);
+    const int d = S->d;
+    for (size_t cc = lo; cc < hi; ++cc) {
+        const int c = (int)cc;
+        const int a0 = c - (d - 1) > 0 ? c - (d - 1) : 0;
+        const int a1 = c < d - 1 ? c : d - 1;
+        u128 acc = 0;
+        uint64_t cnt = 0;
+        for (int l = 0; l < S->n; ++l) {
+            const uint64_t* u = S->U + (size_t)l * d;
+            const uint64_t* v = S->V + (size_t)l * d;
+            for (int a = a0; a <= a1; ++a) {
+                acc += (u128)u[a] * v[c - a];
+                if (++cnt == lim) { acc %= p; cnt = 0; }
+            }
         }
+        S->out[c] = (uint64_t)(acc % p);
+    }
+}
+
+void orc_polymul_sum(uint64_t p, int n, int d, const uint64_t* U, const uint64_t* V,
+                     uint64_t* out, int threads) {
+    const size_t len = (size_t)n * d;
+    uint64_t* u = (uint64_t*)malloc(sizeof(uint64_t) * (len ? len : 1));
+    uint64_t* v = (uint64_t*)malloc(sizeof(uint64_t) * (len ? len : 1));
+    for (size_t t = 0; t < len; ++t) { u[t] = U[t] % p; v[t] = V[t] % p; }
+    psum_t S = {p, n, d, u, v, out};
+    split_run(psum_range, &S, (size_t)(2 * d - 1), 8, threads);
+    free(u); free(v);
 }

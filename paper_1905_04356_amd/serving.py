@@ -18,8 +18,10 @@ instead. The host loop:
 
 Requests that arrive while others run therefore join the next launch and
 overlap them on the device. Latency = completion (observed by the host) -
-scheduled arrival. The baseline server on the same trace issues one pm_mul
-call per request, in arrival order, on one stream.
+scheduled arrival; percentiles skip the requests that arrive during a
+warm-up interval. The baseline server on the same trace launches one product
+per request, in arrival order, on one stream, with the same resident
+evaluations.
 """
 from __future__ import annotations
 
@@ -92,8 +94,9 @@ class Server:
     logic pass a host-side double instead."""
 
     def __init__(self, p: int, pool: list[PoolItem], budget_bytes: int, streams: int = 4,
-                 max_batch: int = 256, keep=(), launcher=None):
+                 max_batch: int = 256, keep=(), launcher=None, warmup_s: float = 0.0):
         self.p, self.pool, self.budget = p, pool, budget_bytes
+        self.warmup_s = warmup_s
         self.max_batch = max_batch
         self.nslots = streams
         self.launch = launcher or self._gpu_launch
@@ -191,19 +194,32 @@ class Server:
         return self._stats(arrivals, items, done_at, wall, batches)
 
     def _stats(self, arrivals, items, done_at, wall, batches):
-        lat = [done_at[r] - arrivals[r] for r in range(len(arrivals))]
-        p50, p99 = _percentiles(lat)
-        work = sum(self.pool[i].m * self.pool[i].n * self.pool[i].k * self.pool[i].d
-                   for i in items)
-        return {"requests": len(arrivals), "wall_s": wall, "batches": batches,
-                "throughput": work / wall, "p50_ms": p50 * 1e3, "p99_ms": p99 * 1e3,
-                "mean_batch": len(arrivals) / max(batches, 1)}
+        st = _stats(self.pool, arrivals, items, done_at, wall, self.warmup_s)
+        st["batches"] = batches
+        st["mean_batch"] = len(arrivals) / max(batches, 1)
+        return st
 
 
-def run_fifo(p: int, pool: list[PoolItem], arrivals, items, keep=()):
-    """Baseline: one pm_mul call per request, issued on one stream as soon as
-    the request has arrived; completions observed through per-request
-    events."""
+def _stats(pool, arrivals, items, done_at, wall, warmup_s):
+    """Latency percentiles over the requests that arrive after `warmup_s`;
+    throughput over the whole run (all requests' work / wall time)."""
+    n = len(arrivals)
+    lat = [done_at[r] - arrivals[r] for r in range(n) if arrivals[r] >= warmup_s]
+    p50, p99 = _percentiles(lat)
+    work = sum(pool[i].m * pool[i].n * pool[i].k * pool[i].d for i in items)
+    return {"requests": n, "measured_requests": len(lat), "warmup_s": warmup_s,
+            "wall_s": wall, "throughput": work / wall,
+            "p50_ms": p50 * 1e3 if p50 is not None else None,
+            "p99_ms": p99 * 1e3 if p99 is not None else None}
+
+
+def run_fifo(p: int, pool: list[PoolItem], arrivals, items, keep=(), warmup_s: float = 0.0):
+    """Baseline: one product per launch, issued on one stream as soon as the
+    request has arrived, in arrival order; completions observed through
+    per-request events. It uses the same resident evaluations as the batching
+    server (a one-product pm_mul_batched call), and wrapped-form products run
+    as pm_mul calls there too, so the two servers differ only in batching and
+    streams."""
     st = torch.cuda.Stream()
     ws = polymat.Workspace()
     n = len(arrivals)
@@ -220,7 +236,11 @@ def run_fifo(p: int, pool: list[PoolItem], arrivals, items, keep=()):
             with torch.cuda.stream(st):
                 C = torch.empty((2 * it.d - 1, it.m, it.k), dtype=torch.uint32,
                                 device=it.A.device)
-                polymat.mul(p, it.A, it.B, out=C, workspace=ws, stream=st)
+                if it.wraps or (it.A_eval is None and it.B_eval is None):
+                    polymat.mul(p, it.A, it.B, out=C, workspace=ws, stream=st)
+                else:
+                    polymat.mul_batched(p, [it.A], [it.B], [C], workspace=ws, stream=st,
+                                        A_evals=[it.A_eval], B_evals=[it.B_eval])
                 ev = torch.cuda.Event()
                 ev.record(st)
             pending.append((nxt, ev, C))
@@ -238,8 +258,4 @@ def run_fifo(p: int, pool: list[PoolItem], arrivals, items, keep=()):
         elif pending:
             time.sleep(20e-6)
     wall = time.perf_counter() - t0
-    lat = [done_at[r] - arrivals[r] for r in range(n)]
-    p50, p99 = _percentiles(lat)
-    work = sum(pool[i].m * pool[i].n * pool[i].k * pool[i].d for i in items)
-    return {"requests": n, "wall_s": wall, "throughput": work / wall, "p50_ms": p50 * 1e3,
-            "p99_ms": p99 * 1e3}, kept
+    return _stats(pool, arrivals, items, done_at, wall, warmup_s), kept

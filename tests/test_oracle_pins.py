@@ -278,6 +278,45 @@ def test_checkers_accept_true_product_and_catch_one_wrong_coefficient():
             assert not O.freivalds_check(p, A, B, bad)
 
 
+def test_checker_pieces_against_python_integers():
+    """The threaded checker pieces against plain Python-integer sums on small
+    inputs: Horner values at several points (both the 64-bit path, p < 2^32,
+    and the 128-bit one), the two Freivalds projections, and the sum of
+    univariate products, with several threads splitting the work."""
+    rng = np.random.default_rng(8)
+    for p in (P31, 4294967291, P62):
+        D, R, S = 7, 5, 3
+        X = rand_pm(rng, p, D, R, S)
+        pts = [0, 1, p - 1, 12345 % p]
+        got = O.eval_points(p, X, pts, threads=3)
+        for t, r in enumerate(pts):
+            for i in range(R):
+                for j in range(S):
+                    want = sum(int(X[c, i, j]) * pow(r, c, p) for c in range(D)) % p
+                    assert int(got[t, i, j]) == want
+        u = rng.integers(0, p, size=R, dtype=np.uint64)
+        v = rng.integers(0, p, size=S, dtype=np.uint64)
+        L = O.lib()
+        uX = np.zeros((D, S), dtype=np.uint64)
+        Xv = np.zeros((D, R), dtype=np.uint64)
+        L.orc_project_left_mt(p, R, S, D, O._ptr(X), O._ptr(u), O._ptr(uX), 2)
+        L.orc_project_right_mt(p, R, S, D, O._ptr(X), O._ptr(v), O._ptr(Xv), 2)
+        for c in range(D):
+            for j in range(S):
+                assert int(uX[c, j]) == sum(int(u[i]) * int(X[c, i, j]) for i in range(R)) % p
+            for i in range(R):
+                assert int(Xv[c, i]) == sum(int(X[c, i, j]) * int(v[j]) for j in range(S)) % p
+        n, d = 4, 9
+        U = rng.integers(0, p, size=(n, d), dtype=np.uint64)
+        V = rng.integers(0, p, size=(n, d), dtype=np.uint64)
+        out = np.zeros(2 * d - 1, dtype=np.uint64)
+        L.orc_polymul_sum(p, n, d, O._ptr(U), O._ptr(V), O._ptr(out), 3)
+        for c in range(2 * d - 1):
+            want = sum(int(U[l, a]) * int(V[l, c - a]) for l in range(n)
+                       for a in range(max(0, c - d + 1), min(c, d - 1) + 1)) % p
+            assert int(out[c]) == want
+
+
 # ---- number theory ---------------------------------------------------------
 
 def test_miller_rabin_against_sympy_and_pseudoprimes():
