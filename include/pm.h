@@ -68,14 +68,15 @@ typedef enum pm_status {
   PM_EDEVICE = -5,       /* a HIP call failed                                    */
   PM_EUNSUPPORTED = -6,  /* no prime set covers the requested length/bound       */
   PM_EBUSY = -7,         /* reserved for admission control (serving layer)       */
-  PM_ETABLES = -8        /* no table region attached, or the regions are full    */
+  PM_ETABLES = -8,       /* no table region attached, or the regions are full    */
+  PM_ESCRATCH = -9       /* pm_mul_noalloc: workspace beyond its static scratch  */
 } pm_status;
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 4
+#define PM_ABI_VERSION 5
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -147,6 +148,24 @@ pm_status pm_mul_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
 pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                      const uint64_t* A, const uint64_t* B, uint64_t* C,
                      void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* pm_mul_u32 (elem_bytes 4) or pm_mul_u64 (elem_bytes 8) without a
+ * workspace and without any allocation, for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The caller passes only inputs and outputs (same
+ * layout, alignment and overlap rules, same result).  The workspace and this
+ * entry point's twiddle and Vandermonde tables live in a static device array
+ * of 64 MiB that each GPU the library runs on holds until the process ends:
+ * 8 MiB of tables and a workspace of at most 56 MiB (58720256 bytes).  A
+ * product whose pm_workspace_bytes exceeds that returns PM_ESCRATCH before
+ * anything is enqueued; PM_ETABLES if its tables no longer fit the 8 MiB.
+ * Calls on one GPU share its array, which keeps the last call's contents
+ * (no call relies on them): calls that overlap on one GPU (other streams,
+ * other threads) race on the workspace, so the caller serialises them.
+ * Asynchronous on `stream`. */
+pm_status pm_mul_noalloc(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         int32_t elem_bytes, const void* A, const void* B, void* C,
+                         void* stream);
 
 /* Middle product, and in general a window of coefficients of a product
  * (Section 2, "Polynomial multiplication": MiddleProduct(F, G, c, d) returns

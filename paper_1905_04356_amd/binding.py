@@ -21,6 +21,7 @@ PM_EDEVICE = -5
 PM_EUNSUPPORTED = -6
 PM_EBUSY = -7
 PM_ETABLES = -8
+PM_ESCRATCH = -9
 
 # Every symbol include/pm.h declares.
 EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
@@ -32,7 +33,7 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
            "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32",
            "pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
-           "pm_neg_mod", "pm_debug_fail_alloc")
+           "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
@@ -138,8 +139,9 @@ def lib():
                                  ctypes.POINTER(i32)]
     L.pm_neg_mod.argtypes = [u64, vp, vp, u64, i32, vp]
     L.pm_debug_fail_alloc.argtypes = [i32]
+    L.pm_mul_noalloc.argtypes = [u64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
     for name in ("pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
-                 "pm_neg_mod", "pm_debug_fail_alloc"):
+                 "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",

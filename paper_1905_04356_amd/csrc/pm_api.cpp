@@ -20,6 +20,7 @@
 #include "../../include/pm.h"
 #include "pm_batch.h"
 #include "pm_kernels.h"
+#include "pm_noalloc.h"
 #include "pm_plan.h"
 #include "pm_profile.h"
 #include "pm_tables.h"
@@ -64,6 +65,8 @@ const char* pm_status_str(int status) {
     case PM_EUNSUPPORTED: return "PM_EUNSUPPORTED: length or bound not supported";
     case PM_EBUSY: return "PM_EBUSY: busy";
     case PM_ETABLES: return "PM_ETABLES: no table region attached, or the regions are full";
+    case PM_ESCRATCH:
+      return "PM_ESCRATCH: the product needs more than the static scratch of pm_mul_noalloc";
     default: return "unknown pm_status";
   }
 }
@@ -417,6 +420,24 @@ pm_status pm_mul_u64(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, con
                      void* stream) {
   return (pm_status)guarded([&] {
     return (int)mul_common(p, m, n, k, d, 8, A, B, C, workspace, workspace_bytes, stream);
+  });
+}
+
+pm_status pm_mul_noalloc(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         int32_t elem_bytes, const void* A, const void* B, void* C,
+                         void* stream) {
+  return (pm_status)guarded([&] {
+    if (elem_bytes != 4 && elem_bytes != 8) return (int)PM_EINVAL;
+    Plan P;
+    int st = make_plan(p, m, n, k, d, elem_bytes, &P);
+    if (st != PM_OK) return st;
+    if (P.ws_bytes > kScratchWorkspaceBytes) return (int)PM_ESCRATCH;
+    uint8_t* base = nullptr;
+    st = noalloc_scratch(&base);
+    if (st != PM_OK) return st;
+    TablePool pool(kPoolStatic);
+    return (int)mul_common(p, m, n, k, d, elem_bytes, A, B, C, base + kScratchTableBytes,
+                           kScratchWorkspaceBytes, stream);
   });
 }
 

@@ -47,8 +47,11 @@ struct DevTables {
 };
 
 std::mutex g_mu;
-std::map<int, DevTables> g_dev;
+std::map<int, DevTables> g_dev;  // keyed by pool_key(pool, device)
 std::atomic<uint64_t> g_epoch{0};
+thread_local int t_pool = kPoolCaller;
+
+int pool_key(int pool, int dev) { return pool * 4096 + dev; }
 
 bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -88,7 +91,7 @@ int prepare(const std::vector<Want>& want, hipStream_t s, Fill fill,
   if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
   const bool capturing = stream_capturing(s);
   std::lock_guard<std::mutex> lock(g_mu);
-  DevTables& D = g_dev[dev];
+  DevTables& D = g_dev[pool_key(t_pool, dev)];
   // 1. carve every missing entry, all or nothing
   std::vector<Region> saved = D.regions;
   std::vector<Key> added;
@@ -166,6 +169,28 @@ uint32_t primitive_root(uint32_t q) {
 
 uint64_t tables_epoch() { return g_epoch.load(); }
 
+TablePool::TablePool(int pool) : prev_(t_pool) { t_pool = pool; }
+TablePool::~TablePool() { t_pool = prev_; }
+
+int tables_attach_pool(int pool, void* dev_ptr, uint64_t bytes) {
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255) || bytes < 256) return PM_EINVAL;
+  try {
+    alloc_point();  // the region list and the device's table map
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_mu);
+    DevTables& D = g_dev[pool_key(pool, dev)];
+    for (const Region& r : D.regions) {
+      const uintptr_t a = (uintptr_t)r.base, b = (uintptr_t)dev_ptr;
+      if (a < b + bytes && b < a + r.bytes) return PM_EINVAL;  // overlaps a region
+    }
+    D.regions.push_back(Region{(uint8_t*)dev_ptr, bytes, 0});
+    return PM_OK;
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
+}
+
 uint64_t twiddle_table_bytes(int logL) {
   const PassPlan PP = make_pass_plan(logL);
   const uint64_t cnt = PP.tw_count ? PP.tw_count : 1;
@@ -233,7 +258,7 @@ int prime_const(uint32_t q, int logL, PrimeConst* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
   std::lock_guard<std::mutex> lock(g_mu);
-  auto d = g_dev.find(dev);
+  auto d = g_dev.find(pool_key(t_pool, dev));
   if (d == g_dev.end()) return PM_EINVAL;
   auto it = d->second.entries.find(Key(0, q, logL, pass_signature(logL)));
   if (it == d->second.entries.end()) return PM_EINVAL;
@@ -280,29 +305,14 @@ int prepare_vdm(uint32_t p, int d, hipStream_t s, const uint32_t** V, const uint
 extern "C" {
 
 pm_status pm_tables_attach(void* dev_ptr, uint64_t bytes) {
-  if (!dev_ptr || ((uintptr_t)dev_ptr & 255) || bytes < 256) return PM_EINVAL;
-  try {
-    pm::alloc_point();  // the region list and the device's table map
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
-    std::lock_guard<std::mutex> lock(pm::g_mu);
-    pm::DevTables& D = pm::g_dev[dev];
-    for (const pm::Region& r : D.regions) {
-      const uintptr_t a = (uintptr_t)r.base, b = (uintptr_t)dev_ptr;
-      if (a < b + bytes && b < a + r.bytes) return PM_EINVAL;  // overlaps a region
-    }
-    D.regions.push_back(pm::Region{(uint8_t*)dev_ptr, bytes, 0});
-    return PM_OK;
-  } catch (const std::bad_alloc&) {
-    return PM_ENOMEM;
-  }
+  return (pm_status)pm::tables_attach_pool(pm::kPoolCaller, dev_ptr, bytes);
 }
 
 pm_status pm_tables_reset(void) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
   std::lock_guard<std::mutex> lock(pm::g_mu);
-  auto it = pm::g_dev.find(dev);
+  auto it = pm::g_dev.find(pm::pool_key(pm::kPoolCaller, dev));
   if (it == pm::g_dev.end()) return PM_OK;
   for (auto& kv : it->second.entries)
     if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
@@ -317,7 +327,7 @@ pm_status pm_tables_info(uint64_t* attached_bytes, uint64_t* used_bytes, int32_t
   std::lock_guard<std::mutex> lock(pm::g_mu);
   uint64_t a = 0, u = 0;
   int32_t t = 0;
-  auto it = pm::g_dev.find(dev);
+  auto it = pm::g_dev.find(pm::pool_key(pm::kPoolCaller, dev));
   if (it != pm::g_dev.end()) {
     for (const pm::Region& r : it->second.regions) {
       a += r.bytes;

@@ -48,6 +48,23 @@ uint32_t root_of_unity(uint32_t q, int logL);
 // back: prepared like the twiddle tables.
 int prepare_vdm(uint32_t p, int d, hipStream_t s, const uint32_t** V, const uint32_t** W);
 
+// Table pools: the regions the caller registers (pm_tables_attach), and the
+// slice of the static scratch array that the no-allocation entry point keeps
+// its tables in.  A TablePool scope selects the pool of this thread's calls.
+constexpr int kPoolCaller = 0, kPoolStatic = 1;
+class TablePool {
+ public:
+  explicit TablePool(int pool);
+  ~TablePool();
+  TablePool(const TablePool&) = delete;
+  TablePool& operator=(const TablePool&) = delete;
+
+ private:
+  int prev_;
+};
+// Register a region of device memory in `pool` on the current device.
+int tables_attach_pool(int pool, void* dev_ptr, uint64_t bytes);
+
 // Incremented by pm_tables_reset: table pointers recorded under an older
 // epoch (in captured graphs) are stale.
 uint64_t tables_epoch();

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(B.EXPORTS)
-    assert L.pm_abi_version() == 4
+    assert L.pm_abi_version() == 5
     assert B.status_str(B.PM_EWORKSPACE).startswith("PM_EWORKSPACE")
 
 
@@ -286,6 +286,7 @@ def _enomem_calls():
         ("pm_tables_attach", lambda: L.pm_tables_attach(ctypes.c_void_p(WS), 1 << 20)),
         ("pm_mul_u32", lambda: L.pm_mul_u32(p, 4, 4, 4, 16, A, Bp, C, WS, ws_big, None)),
         ("pm_mul_u64", lambda: L.pm_mul_u64(p, 4, 4, 4, 16, A, Bp, C, WS, ws_big, None)),
+        ("pm_mul_noalloc", lambda: L.pm_mul_noalloc(p, 4, 4, 4, 16, 4, A, Bp, C, None)),
         ("pm_middle_plan", lambda: L.pm_middle_plan(p, 2, 2, 2, 5, 9, 5, 4, 4,
                                                     ctypes.byref(info))),
         ("pm_middle_u32", lambda: L.pm_middle_u32(p, 2, 2, 2, 5, 9, 5, 4, A, Bp, C, WS, ws_big,
@@ -343,3 +344,16 @@ def test_tables_bytes_covers_every_route():
     vdm = B.pm_tables_bytes(1000000007, 8, 8, 8, 64, 4)        # routed to Vandermonde
     N = 2 * 64 - 1
     assert vdm >= 4 * N * 64 + 4 * N * N
+
+
+def test_noalloc_rejects_products_beyond_its_scratch():
+    """pm_mul_noalloc refuses, before touching a device, a product whose
+    workspace exceeds its 56 MiB static scratch, and bad element sizes."""
+    L = B.lib()
+    A, Bp, C = 1 << 20, 2 << 20, 3 << 20
+    need = B.pm_workspace_bytes(2013265921, 64, 64, 32, 4096, 4)
+    assert need > 56 << 20
+    assert L.pm_mul_noalloc(2013265921, 64, 64, 32, 4096, 4, A, Bp, C, None) == B.PM_ESCRATCH
+    assert L.pm_mul_noalloc(998244353, 4, 4, 4, 16, 2, A, Bp, C, None) == B.PM_EINVAL
+    assert L.pm_mul_noalloc(998244353, 0, 4, 4, 16, 4, A, Bp, C, None) == B.PM_EINVAL
+    assert B.status_str(B.PM_ESCRATCH).startswith("PM_ESCRATCH")
