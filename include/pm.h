@@ -76,11 +76,14 @@ typedef enum pm_status {
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 5
+#define PM_ABI_VERSION 6
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
- * mode: 0 = direct NTT mod p, 1 = CRT over num_primes NTT primes.
+ * mode: 0 = direct NTT mod p, 1 = CRT over num_primes NTT primes, 2 =
+ * evaluation at 0 .. 2d-2 by Vandermonde products (pm_plan only: a CRT-mode
+ * uint32 product that pm_mul_u32 sends through pm_mul_vdm_u32; primes and
+ * log2_len then describe the CRT plan it replaces).
  * pointwise: 0 = VALU Barrett kernel, 1 = int8-MFMA limb kernel. */
 typedef struct pm_plan_info {
   int32_t mode;
@@ -94,8 +97,29 @@ typedef struct pm_plan_info {
                                 top coefficients from a short product (large
                                 products with 2d - 1 a little above 2^j);
                                 0: on 2^log2_len points                     */
-  int32_t reserved;
+  int32_t tune_entry;        /* index of the tuning-table entry whose launch
+                                shapes the product uses; -1: the defaults   */
 } pm_plan_info;
+
+/* Tuning table (Section 2, "Polynomial matrix multiplication": thresholds
+ * between variants are found experimentally, separately for small and large
+ * primes).  Launch shapes per (prime class, log2 L, shape bucket): column-pass
+ * stages, stages per block pass, block-step threads and tile, column item
+ * widths, register or LDS block tile, MFMA or VALU pointwise, pipelined
+ * pointwise slots; and global batch and wrapped-length thresholds.  No
+ * choice changes a result.  The table is JSON (format "pm-tune-1", written by
+ * the tuning driver paper_1905_04356_amd/tune.py); it is read on first use
+ * from $PM_TUNE_TABLE if set (empty: none), else from tune_table.json beside
+ * libpm.so; a missing or invalid file leaves the defaults (PM_TUNE_*
+ * environment variables, else built in).
+ * pm_tune_load installs the table in `json` (NULL: read the default file
+ * again; "": no table).  PM_EINVAL if the text is not a valid table (the
+ * current one stays).  Calls in flight keep the shapes they were planned
+ * with; cached batch graphs are rebuilt.  Host only.
+ * pm_tune_info: number of entries, and where the table came from (0: none,
+ * defaults; 1: the file; 2: pm_tune_load; -1: the file was invalid). */
+pm_status pm_tune_load(const char* json);
+pm_status pm_tune_info(int32_t* entries, int32_t* source);
 
 /* Plan the product of an (m x n) by (n x k) matrix of degree < d mod p with
  * elem_bytes-byte residues (4 or 8).  Host only.  Returns PM_EINVAL on sizes

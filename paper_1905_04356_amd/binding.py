@@ -33,7 +33,8 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_middle_batched_u64", "pm_vdm_workspace_bytes", "pm_mul_vdm_u32",
            "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32",
            "pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
-           "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc")
+           "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
+           "pm_tune_info")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
 
@@ -48,7 +49,7 @@ class pm_plan_info(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("log2_len", ctypes.c_int32),
                 ("num_primes", ctypes.c_int32), ("pointwise", ctypes.c_int32),
                 ("primes", ctypes.c_uint32 * 8), ("workspace_bytes", ctypes.c_uint64),
-                ("wrap_log2_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wrap_log2_len", ctypes.c_int32), ("tune_entry", ctypes.c_int32)]
 
 
 class pm_kernel_stats(ctypes.Structure):
@@ -140,8 +141,11 @@ def lib():
     L.pm_neg_mod.argtypes = [u64, vp, vp, u64, i32, vp]
     L.pm_debug_fail_alloc.argtypes = [i32]
     L.pm_mul_noalloc.argtypes = [u64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
+    L.pm_tune_load.argtypes = [ctypes.c_char_p]
+    L.pm_tune_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for name in ("pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
-                 "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc"):
+                 "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
+                 "pm_tune_info"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
@@ -368,3 +372,20 @@ def pm_vdm_workspace_bytes(p: int, m: int, n: int, k: int, d: int) -> int:
 
 def pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
     return lib().pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
+
+
+def tune_load(text: str | None) -> None:
+    """Install a tuning table (JSON text); None re-reads the default file,
+    "" removes the table (defaults).  Raises on an invalid table."""
+    st = lib().pm_tune_load(None if text is None else text.encode())
+    if st != PM_OK:
+        raise PmError(st, "pm_tune_load")
+
+
+def tune_info() -> tuple[int, int]:
+    """(entries, source) of the installed tuning table."""
+    e, s = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = lib().pm_tune_info(ctypes.byref(e), ctypes.byref(s))
+    if st != PM_OK:
+        raise PmError(st, "pm_tune_info")
+    return e.value, s.value

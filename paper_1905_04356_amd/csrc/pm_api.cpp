@@ -39,6 +39,7 @@ static bool vdm_eligible(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d)
 
 namespace {
 int wrap_log_of(const Plan& P);
+int vdm_max_d();
 }
 
 static void fill_plan_info(const Plan& P, pm_plan_info* out) {
@@ -50,6 +51,7 @@ static void fill_plan_info(const Plan& P, pm_plan_info* out) {
   out->pointwise = P.pointwise;
   for (int i = 0; i < P.r; ++i) out->primes[i] = P.q[i];
   out->workspace_bytes = P.ws_bytes;
+  out->tune_entry = P.tune_entry;
 }
 
 extern "C" {
@@ -81,6 +83,8 @@ pm_status pm_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d, int32_
     int st = make_plan(p, m, n, k, d, elem_bytes, &P);
     if (st != PM_OK) return st;
     fill_plan_info(P, out);
+    if (P.mode == 1 && elem_bytes == 4 && d <= vdm_max_d() && vdm_eligible(p, m, n, k, d))
+      out->mode = 2;  // pm_mul_u32 takes the Vandermonde route
     return (int)PM_OK;
   });
 }
@@ -158,7 +162,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   memset(L, 0, sizeof *L);
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
-    int st = prime_const(P.q[i], P.logL, &pc[i]);
+    int st = prime_const(TwKey{P.q[i], P.logL, P.kn.split, P.kn.maxr}, &pc[i]);
     if (st != PM_OK) return st;
   }
   const int m = P.m, n = P.n, k = P.k;
@@ -174,7 +178,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   L->pw_staged = 4ull * ((uint64_t)m * n + (uint64_t)n * k) <= 128 * 1024;
 
   NttLaunch& fa = L->f[0];
-  fill_ntt_launch(&fa, P.logL, m * n, P.da, P.elem_bytes, false, batched);
+  fill_ntt_launch(&fa, P.logL, m * n, P.da, P.elem_bytes, false, batched, P.kn);
   for (int i = 0; i < P.r; ++i) fa.pc[i] = pc[i];
   fa.in = A;
   fa.out = ahat;
@@ -183,12 +187,14 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 
   NttLaunch& fb = L->f[1];
   fb = fa;
-  fill_ntt_launch(&fb, P.logL, n * k, P.db, P.elem_bytes, false, batched);
+  fill_ntt_launch(&fb, P.logL, n * k, P.db, P.elem_bytes, false, batched, P.kn);
   fb.in = B;
   fb.out = bhat;
 
   PointwiseLaunch& pw = L->pw;
   pw.m = m; pw.n = n; pw.k = k; pw.L = 1 << P.logL;
+  pw.small_lds = P.kn.pw_small_lds;
+  pw.pipe = P.kn.pw_pipe;
   pw.prime_stride = pstride;
   pw.a_prime_stride = pstride;
   pw.b_prime_stride = pstride;
@@ -212,7 +218,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   NttLaunch& ic = L->inv;
   ic = fa;
   fill_ntt_launch(&ic, P.logL, m * k, P.nout, P.mode == 1 ? 4 : P.elem_bytes, true,
-                  batched);
+                  batched, P.kn);
   ic.out_lo = P.lo;
   ic.in = chat;
   ic.in_prime_stride = pstride;
@@ -241,7 +247,8 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
 int prepare_plans(const Plan* plans, size_t n, hipStream_t s) {
   std::vector<TwKey> keys;
   for (size_t i = 0; i < n; ++i)
-    for (int j = 0; j < plans[i].r; ++j) keys.push_back(TwKey{plans[i].q[j], plans[i].logL});
+    for (int j = 0; j < plans[i].r; ++j)
+      keys.push_back(TwKey{plans[i].q[j], plans[i].logL, plans[i].kn.split, plans[i].kn.maxr});
   return prepare_twiddles(keys.data(), (int)keys.size(), s);
 }
 
@@ -290,14 +297,8 @@ int run_product(const Plan& P, const void* A, const void* B, void* C, uint8_t* w
 
 // Largest d for which products mod a prime without the needed roots of unity
 // go through Vandermonde evaluation on the matrix cores instead of CRT
-// (PM_TUNE_VDM_MAXD, default 64: measured faster up to there).
-int vdm_max_d() {
-  static const int v = [] {
-    const char* e = getenv("PM_TUNE_VDM_MAXD");
-    return e ? atoi(e) : 64;
-  }();
-  return v;
-}
+// (global knob vdm_max_d, default 64: measured faster up to there).
+int vdm_max_d() { return global_knobs().vdm_max_d; }
 
 // Products with 2^j < 2d - 1 <= 2^j + 2^(j-1): A B mod (x^(2^j) - 1) on a
 // transform of 2^j points, the t = 2d - 1 - 2^j coefficients at and above
@@ -308,27 +309,22 @@ int vdm_max_d() {
 // small top: t <= 2^j / 4 and (mn + nk + mk) 2^j >= 2^25 (measured: 128x128x64
 // at t = 103..175 0.60-0.84 of the plain time, 64x64x32 at 2^12 + 103 0.74 and
 // 2^12 + 903 0.94; at 2^11 + 151, where (mn + nk + mk) 2^j = 2^24, 1.03; small
-// shapes and tops near 2^(j-1) 1.0-2.3).  PM_TUNE_WRAP=0 turns it off;
-// PM_TUNE_WRAP_MINLOG (default 10) is the least j.  Returns 1 when the
-// product was launched this way, 0 when it does not apply, or a pm_status.
-int wrap_min_log() {
-  static const int v = [] {
-    const char* e = getenv("PM_TUNE_WRAP");
-    if (e && e[0] == '0') return 99;
-    const char* f = getenv("PM_TUNE_WRAP_MINLOG");
-    return f ? atoi(f) : 10;
-  }();
-  return v;
-}
+// shapes and tops near 2^(j-1) 1.0-2.3).  The bounds are global knobs
+// (wrap_min_log, default 10, the least j; wrap_top_div, 4; wrap_min_work_log,
+// 25).  run_wrapped returns 1 when the product was launched this way, 0 when
+// it does not apply, or a pm_status.
 
 // j when a whole product of plan P takes the wrapped form on 2^j points
 // (with P's own workspace), else 0; the cyclic and top plans through pc, pt.
 int wrap_log_plans(const Plan& P, Plan* pc, Plan* pt) {
+  const GlobalKnobs G = global_knobs();
   const int j = P.logL - 1;
-  if (P.da != P.db || P.lo != 0 || j < wrap_min_log()) return 0;
+  if (P.da != P.db || P.lo != 0 || j < G.wrap_min_log) return 0;
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t entries = (uint64_t)P.m * P.n + (uint64_t)P.n * P.k + (uint64_t)P.m * P.k;
-  if (t < 1 || t > Lp / 4 || d > Lp || (entries << j) < (1ull << 25)) return 0;
+  if (t < 1 || t > Lp / G.wrap_top_div || d > Lp ||
+      (entries << j) < (1ull << G.wrap_min_work_log))
+    return 0;
   if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, pc) != PM_OK) return 0;
   if (make_slice_plan(P.p, P.m, P.n, P.k, t, t, t - 1, t, P.elem_bytes, pt) != PM_OK) return 0;
   if (pc->ws_bytes > P.ws_bytes || pt->ws_bytes > P.ws_bytes) return 0;
@@ -448,11 +444,11 @@ pm_status pm_tables_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d
     Plan P;
     int st = make_plan(p, m, n, k, d, elem_bytes, &P);
     if (st != PM_OK) return st;
-    uint64_t b = (uint64_t)P.r * twiddle_table_bytes(P.logL);
+    uint64_t b = (uint64_t)P.r * twiddle_table_bytes(P.logL, P.kn.split, P.kn.maxr);
     Plan pc, pt;
     if (wrap_log_plans(P, &pc, &pt))
-      b += (uint64_t)pc.r * twiddle_table_bytes(pc.logL) +
-           (uint64_t)pt.r * twiddle_table_bytes(pt.logL);
+      b += (uint64_t)pc.r * twiddle_table_bytes(pc.logL, pc.kn.split, pc.kn.maxr) +
+           (uint64_t)pt.r * twiddle_table_bytes(pt.logL, pt.kn.split, pt.kn.maxr);
     if (P.mode == 1 && elem_bytes == 4 && d <= vdm_max_d() && vdm_eligible(p, m, n, k, d))
       b += vdm_table_bytes(d);
     *out = b;
@@ -552,7 +548,10 @@ static pm_status vdm_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d
     // one m x n by n x k product per point, no scaling (interpolation is W)
     PointwiseLaunch pw;
     memset(&pw, 0, sizeof pw);
+    const Knobs kn = base_knobs();
     pw.m = m; pw.n = n; pw.k = k; pw.L = N;
+    pw.small_lds = kn.pw_small_lds;
+    pw.pipe = kn.pw_pipe;
     pw.ahat = ahat; pw.bhat = bhat; pw.chat = chat;
     pw.pc[0].q = p;
     pw.pc[0].linv = 1;
@@ -564,8 +563,8 @@ static pm_status vdm_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d
     pw.bias[0] = c.bias;
     pw.qninv[0] = c.qninv;
     KernelTimer kt(K_POINTWISE, s);
-    const int ok = choose_pointwise(m, n, k) == 1 ? launch_pointwise_mfma(pw, 1, s)
-                                                  : launch_pointwise(pw, 1, s);
+    const int ok = choose_pointwise(m, n, k, kn.pointwise) == 1 ? launch_pointwise_mfma(pw, 1, s)
+                                                                : launch_pointwise(pw, 1, s);
     if (ok != hipSuccess) return PM_EDEVICE;
   }
   {
@@ -682,12 +681,14 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   if (st != PM_OK) return (pm_status)st;
   PrimeConst pc[kMaxPrimes];
   for (int i = 0; i < P.r; ++i) {
-    st = prime_const(P.q[i], P.logL, &pc[i]);
+    st = prime_const(TwKey{P.q[i], P.logL, P.kn.split, P.kn.maxr}, &pc[i]);
     if (st != PM_OK) return (pm_status)st;
   }
+  // Evaluations come out in bit-reversed point order whatever the pass
+  // structure, so a product planned with other knobs can consume them.
   NttLaunch a;
   memset(&a, 0, sizeof a);
-  fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false, false);
+  fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false, false, P.kn);
   for (int i = 0; i < P.r; ++i) a.pc[i] = pc[i];
   a.in = X;
   a.out = Xe;
@@ -736,7 +737,7 @@ namespace {
 
 // Segments a product contributes to the six phases (see pm_batch.h).
 int count_segments(const Plan& P) {
-  const int split = split_stages(P.logL) ? 1 : 0;
+  const int split = P.kn.split ? 1 : 0;
   return 2 * P.r                 // forward first pass / unsplit forward
          + 2 * P.r * split       // forward blocks
          + P.r                   // pointwise
@@ -898,26 +899,19 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
     }
   }
   {
-    // points per tile: about PM_TUNE_BATCH_PW_WORK (default 8192) MACs of work
-    static const double pw_work = [] {
-      const char* v = getenv("PM_TUNE_BATCH_PW_WORK");
-      const double x = v && *v ? atof(v) : 8192.0;
-      return x < 1.0 ? 1.0 : x;
-    }();
+    // points per tile: about batch_pw_work (default 8192) MACs of work;
     // pipelined tiles (limb planes above the 256-thread limit): about
-    // PM_TUNE_BATCH_PW_PIPE_PTS (default 16) points each, so that a
-    // workgroup's loads run ahead of its products
-    static const double pipe_pts = [] {
-      const char* v = getenv("PM_TUNE_BATCH_PW_PIPE_PTS");
-      const double x = v && *v ? atof(v) : 16.0;
-      return x < 1.0 ? 1.0 : x;
-    }();
+    // batch_pw_pipe_pts (default 16) points each, so that a workgroup's loads
+    // run ahead of its products
+    const GlobalKnobs G = global_knobs();
+    const double pw_work = (double)G.batch_pw_work;
+    const double pipe_pts = (double)G.batch_pw_pipe_pts;
     const double mnk = (double)P.m * P.n * P.k;
     size_t need = 0;
     if (L.pointwise == 1) need = pointwise_mfma_lds(P.m, P.n, P.k);
     else if (L.pw_staged) need = 4ull * ((uint64_t)P.m * P.n + (uint64_t)P.n * P.k);
-    const int pipe = L.pointwise == 1 && need > pointwise_small_lds()
-                         ? pointwise_pipe_variant(P.m, P.n, P.k) : 0;
+    const int pipe = L.pointwise == 1 && need > (size_t)base_knobs().pw_small_lds
+                         ? pointwise_pipe_variant(P.m, P.n, P.k, P.kn.pw_pipe) : 0;
     uint32_t z = (uint32_t)(pw_work / mnk);
     if (pipe && z < (uint32_t)pipe_pts) z = (uint32_t)pipe_pts;
     if (z < 1) z = 1;
@@ -1074,12 +1068,15 @@ struct GraphEntry {
   void* pinned = nullptr;
   hipStream_t last = nullptr;
   uint64_t tick = 0;
-  uint64_t epoch = 0;  // tables_epoch() when the entry was made
+  uint64_t epoch = 0;  // cache_epoch() when the entry was made
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 uint64_t g_tick = 0;
 constexpr size_t kGraphCacheMax = 16;
+// Graphs embed table pointers and launch shapes: a table reset or a new
+// tuning table makes them stale.
+uint64_t cache_epoch() { return (tables_epoch() << 32) ^ tune_epoch(); }
 
 void free_entry(GraphEntry& e) {
   if (e.last) (void)hipStreamSynchronize(e.last);  // a replay may still read `pinned`
@@ -1121,16 +1118,11 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
               const std::vector<uint64_t>& offs, const BatchLayout& lay, const pm_product* prods,
               uint8_t* ws, uint64_t ws_bytes, hipStream_t s) {
   const int count = (int)plans.size();
-  // Tuning knobs: PM_TUNE_BATCH_DIRECT_MAX (default 2) is the largest batch
-  // launched per product; PM_TUNE_BATCH_GRAPH=0 turns graph replay off.
-  static const int direct_max = [] {
-    const char* v = getenv("PM_TUNE_BATCH_DIRECT_MAX");
-    return v && *v ? atoi(v) : 2;
-  }();
-  static const bool use_graphs = [] {
-    const char* v = getenv("PM_TUNE_BATCH_GRAPH");
-    return !(v && *v == '0');
-  }();
+  // Global knobs: batch_direct_max (default 2) is the largest batch launched
+  // per product; batch_graph 0 turns graph replay off.
+  const GlobalKnobs G = global_knobs();
+  const int direct_max = G.batch_direct_max;
+  const bool use_graphs = G.batch_graph != 0;
   int st = prepare_plans(plans.data(), plans.size(), s);
   if (st != PM_OK) return st;
   if (count <= direct_max) return run_direct(plans, offs, prods, ws, s);
@@ -1155,7 +1147,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   GraphEntry* e = nullptr;
   for (auto& g : g_graphs)
     if (g.sig == sig) { e = &g; break; }
-  if (e && e->epoch != tables_epoch()) {
+  if (e && e->epoch != cache_epoch()) {
     // tables were reset since this graph was captured: its table pointers
     // are stale
     free_entry(*e);
@@ -1184,7 +1176,7 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
     GraphEntry ne;
     ne.sig = std::move(sig);
     ne.seen = 1;
-    ne.epoch = tables_epoch();
+    ne.epoch = cache_epoch();
     ne.tick = ++g_tick;
     g_graphs.push_back(std::move(ne));
     return enqueue_batch(B, B.host.data(), lay, ws, s);

@@ -180,7 +180,7 @@ int launch_batch_phase(int phase, const ProductLaunches* prods, const BatchSeg* 
     case 0: return launch_phase_t<0, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 1: return launch_phase_t<1, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 2:
-      if (lds <= pointwise_small_lds())
+      if (lds <= (size_t)base_knobs().pw_small_lds)
         return launch_phase_t<2, 256>(prods, segs, nseg, ntiles, lds, s);
       return launch_phase_t<2, kBatchNT>(prods, segs, nseg, ntiles, lds, s);
     case 3: return launch_phase_t<3, kBatchNT>(prods, segs, nseg, ntiles, lds, s);

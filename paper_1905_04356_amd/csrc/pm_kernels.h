@@ -35,6 +35,7 @@ struct NttLaunch {
                              // tile with block passes {3,3,3}, {4,3}, {4,4}, {4,3,3},
                              // {4,4,3} (set for the thread count that runs the step)
   int lds_stride;            // 32-bit words between entries in LDS
+  int blk_nt;                // single-product block step: threads (256 or 512)
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers
   const void* in;
@@ -46,6 +47,8 @@ struct NttLaunch {
 // (m x n times n x k), all point-major u32.
 struct PointwiseLaunch {
   int m, n, k, L;
+  int small_lds;             // limb planes up to this many bytes: 256 threads
+  int pipe;                  // pipelined variant: -1 where it fits, 0 never, 1/2 force
   uint64_t prime_stride;     // elements between primes' evaluations of C
   uint64_t a_prime_stride;   // ... of A
   uint64_t b_prime_stride;   // ... of B
@@ -90,8 +93,10 @@ int launch_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int elem_
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 size_t pointwise_mfma_lds(int m, int n, int k);
 // Largest pointwise LDS footprint launched with 256 threads (larger: 512).
-size_t pointwise_small_lds();
-int pointwise_pipe_variant(int m, int n, int k);
+// Pipelined variant for a shape run with 512 threads: 1 (four register
+// slots), 2 (eight) or 0 (none); `knob` -1 where one fits, 0 never, 1 or 2
+// that variant where it suffices.
+int pointwise_pipe_variant(int m, int n, int k, int knob);
 int launch_crt(const CrtLaunch& a, int out_elem_bytes, hipStream_t s);
 int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_bytes,
                           unsigned long long* counter, hipStream_t s);
@@ -100,8 +105,9 @@ int launch_check_residues(uint64_t p, const void* x, uint64_t count, int elem_by
 // io_bytes: bytes per element of the coefficient-major side (the input of a
 // forward transform, the output of an inverse one).
 // batched: parameters for the batched phase kernels (512-thread block tiles).
+// kn: the product's launch shapes (pass structure, tiles, item widths).
 void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse,
-                     bool batched);
+                     bool batched, const Knobs& kn);
 
 // LDS bytes of one block-step tile (2^blk_log positions, position-major).
 __host__ __device__ inline size_t block_lds_bytes(const NttLaunch& a) {

@@ -48,8 +48,8 @@ __global__ __launch_bounds__(kColNT) void ntt_col_inv_kernel(NttLaunch a) {
 // ---- host side ---------------------------------------------------------------
 
 void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool inverse,
-                     bool batched) {
-  const PassPlan PP = make_pass_plan(logL);
+                     bool batched, const Knobs& kn) {
+  const PassPlan PP = make_pass_plan(logL, kn.split, kn.maxr);
   a->logL = logL;
   a->npass = PP.npass;
   a->split = PP.split;
@@ -64,8 +64,8 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   a->E = E;
   // about 2^lds_log residues of LDS per workgroup, at least one entry, no
   // more slots than entries
-  const NttTune& T = ntt_tune();
-  int eb = (PP.split ? (batched ? T.batch_tile_log : T.blk_tile_log) : T.lds_log) - a->blk_log;
+  const GlobalKnobs G = global_knobs();
+  int eb = (PP.split ? (batched ? G.batch_tile_log : kn.blk_tile_log) : G.lds_log) - a->blk_log;
   if (eb < 0) eb = 0;
   while (eb > 0 && (1 << (eb - 1)) >= E) --eb;
   a->eb_log = eb;
@@ -74,7 +74,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   while (v > 1 && ((E % v) != 0 || (1 << eb) % v != 0)) v >>= 1;
   a->vec = v;
   // column items move at most 16 bytes per row access
-  int cv = inverse ? ntt_tune().colvec_inv : ntt_tune().colvec_fwd;
+  int cv = inverse ? kn.colvec_inv : kn.colvec_fwd;
   if (cv == 3) cv = 2;
   // inputs longer than L/2 take the one-entry full-load column pass
   if (!inverse && 2 * nin > (1 << logL)) cv = 1;
@@ -82,11 +82,12 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   a->col_vec = cv;
   const int B = 1 << a->blk_log;
   a->lds_stride = B + (B >> 5) + 1;
-  a->blk_pitch = ((1 << eb) + 3) / 4 * 4 + ntt_tune().blk_pad;
+  a->blk_pitch = ((1 << eb) + 3) / 4 * 4 + G.blk_pad;
   // the register tile, for the threads that run the block step: kBatchNT in
   // the batched phase kernels, blk_nt in the single-product kernel
-  const int nt_log = batched ? (kBatchNT == 512 ? 9 : 8) : (T.blk_nt == 512 ? 9 : 8);
-  a->reg_kind = T.reg_tile ? reg_kind_of(*a, nt_log) : 0;
+  a->blk_nt = batched ? kBatchNT : kn.blk_nt;
+  const int nt_log = a->blk_nt == 512 ? 9 : 8;
+  a->reg_kind = kn.reg_tile ? reg_kind_of(*a, nt_log) : 0;
 }
 
 static size_t lds_bytes(const NttLaunch& a) {
@@ -151,9 +152,9 @@ static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
   const int zb = 1 << a.split;
   const size_t lds = block_lds_bytes(a);
   if (a.reg_kind)
-    return ntt_tune().blk_nt == 256 ? launch_reg<DIF, 256>(a, nprimes, zb, s, lds)
-                                    : launch_reg<DIF, kNT>(a, nprimes, zb, s, lds);
-  if (ntt_tune().blk_nt == 256) {
+    return a.blk_nt == 256 ? launch_reg<DIF, 256>(a, nprimes, zb, s, lds)
+                           : launch_reg<DIF, kNT>(a, nprimes, zb, s, lds);
+  if (a.blk_nt == 256) {
     if (a.vec == 4) return launch_lds(ntt_block_kernel<DIF, 4, 256>, a, nprimes, zb, s, lds, 256);
     if (a.vec == 2) return launch_lds(ntt_block_kernel<DIF, 2, 256>, a, nprimes, zb, s, lds, 256);
     return launch_lds(ntt_block_kernel<DIF, 1, 256>, a, nprimes, zb, s, lds, 256);

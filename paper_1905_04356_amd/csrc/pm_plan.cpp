@@ -85,46 +85,22 @@ static const uint32_t kCrtPrimes[] = {
     167772161u,   //   5 * 2^25 + 1
 };
 
-static int env_int(const char* name, int dflt, int lo, int hi) {
-  const char* v = getenv(name);
-  if (!v || !*v) return dflt;
-  int x = atoi(v);
-  return x < lo ? lo : x > hi ? hi : x;
-}
-
-const NttTune& ntt_tune() {
-  static const NttTune T = {env_int("PM_TUNE_NTT_MAXR", 4, 2, 4),
-                            env_int("PM_TUNE_NTT_LDS_LOG", 14, 11, 15),
-                            env_int("PM_TUNE_NTT_SPLIT", 4, 0, 4),
-                            env_int("PM_TUNE_NTT_SPLIT_MINLOG", 11, 2, 16),
-                            env_int("PM_TUNE_NTT_COLVEC_FWD", 4, 1, 4),
-                            env_int("PM_TUNE_NTT_COLVEC_INV", 4, 1, 4),
-                            env_int("PM_TUNE_NTT_BLK_PAD", 0, 0, 64) & ~3,
-                            env_int("PM_TUNE_NTT_BLK_NT", 256, 256, 512) > 256 ? 512 : 256,
-                            env_int("PM_TUNE_NTT_BLK_TILE_LOG", 13, 11, 15),
-                            env_int("PM_TUNE_BATCH_TILE_LOG", 14, 11, 15),
-                            env_int("PM_TUNE_NTT_REG_TILE", 1, 0, 1)};
-  return T;
-}
-
-int split_stages(int logL) {
-  const NttTune& T = ntt_tune();
-  if (T.split_r1 < 2 || logL < T.split_min_log || T.split_r1 >= logL) return 0;
-  return T.split_r1;
-}
-
-PassPlan make_pass_plan(int logL) {
-  const NttTune& T = ntt_tune();
+// split: stages of the column pass (0: none; kept below logL by the
+// planner); maxr: most stages per later pass.
+PassPlan make_pass_plan(int logL, int split, int maxr) {
   PassPlan P{};
   P.logL = logL;
-  P.split = split_stages(logL);
+  P.split = split;
   int rest = logL, first = 0;
   if (P.split) {
     P.stages[0] = P.split;
     rest -= P.split;
     first = 1;
   }
-  const int nrest = (rest + T.maxr - 1) / T.maxr;  // at most maxr stages per pass
+  if (maxr < 2) maxr = 2;
+  // at most maxr stages per pass, and at most kMaxPasses passes
+  while (maxr < 4 && first + (rest + maxr - 1) / maxr > kMaxPasses) ++maxr;
+  const int nrest = (rest + maxr - 1) / maxr;
   P.npass = first + nrest;
   for (int i = 0; i < nrest; ++i)
     P.stages[first + i] = rest / nrest + (i < rest % nrest ? 1 : 0);
@@ -179,14 +155,11 @@ static int ceil_log2(uint64_t x) {
 
 // Pointwise variant: int8-MFMA limbs where the shape allows (contraction
 // length a multiple of 4 and below 2^12, both matrices' limb planes within
-// the 160 KiB of LDS of a CU), else the VALU kernel.  Tuning knob
-// PM_TUNE_POINTWISE=0 forces the VALU kernel.
-int choose_pointwise(int m, int n, int k) {
+// the 160 KiB of LDS of a CU) and `want` is 1, else the VALU kernel.
+int choose_pointwise(int m, int n, int k, int want) {
   const uint64_t mp = (m + 15) & ~15, kp = (k + 15) & ~15, np = (n + 63) & ~63;
   const bool mfma_ok = n % 4 == 0 && n < 4096 && 4 * (mp + kp) * (np + 16) <= 160 * 1024;
-  const char* env = getenv("PM_TUNE_POINTWISE");
-  if (env && *env == '0') return 0;
-  return mfma_ok ? 1 : 0;
+  return want && mfma_ok ? 1 : 0;
 }
 
 static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int lo, int nout,
@@ -253,7 +226,12 @@ static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int l
     }
     if (big_cmp(prod, bound) <= 0) return PM_EUNSUPPORTED;
   }
-  P.pointwise = choose_pointwise(m, n, k);
+  const int pclass = P.mode == 1 ? kClassCrt : P.q[0] < (1u << 30) ? kClassDirectLt30
+                                                                     : kClassDirectGe30;
+  P.kn = tuned_knobs(pclass, logL, m, n, k, &P.tune_entry);
+  const GlobalKnobs& G = global_knobs();
+  if (P.kn.split < 2 || logL < G.split_min_log || P.kn.split >= logL) P.kn.split = 0;
+  P.pointwise = choose_pointwise(m, n, k, P.kn.pointwise);
   uint64_t off = 0;
   P.off_ahat = off; off = align_up(off + 4 * L * mn, 256);
   P.off_bhat = off; off = align_up(off + 4 * L * nk, 256);

@@ -35,25 +35,53 @@ struct PassPlan {
   uint32_t tw_count;           // total Tw entries of one direction
 };
 
-PassPlan make_pass_plan(int logL);
-
-// Tuning of the transform kernels, read from the environment once:
-// PM_TUNE_NTT_MAXR (largest stages per LDS pass, 2..4, default 4),
-// PM_TUNE_NTT_LDS_LOG (log2 residues of LDS per workgroup, 11..15, default 14),
-// PM_TUNE_NTT_SPLIT (stages of the streaming column pass, 0 = none, else
-// 2..4, default 4),
-// PM_TUNE_NTT_SPLIT_MINLOG (smallest log2 L that is split, default 11).
-struct NttTune {
-  int maxr, lds_log, split_r1, split_min_log;
-  int colvec_fwd, colvec_inv;  // most entries per column-pass item
-  int blk_pad;                 // block step: LDS words of padding per position
-  int blk_nt;                  // block step: threads per workgroup (256 or 512)
-  int blk_tile_log;            // block step: log2 residues per tile
-  int batch_tile_log;          // ... in the batched phase kernels
-  int reg_tile;                // block step: register-resident tile where it fits (1)
+// Launch-shape choices for one product.  None of them changes a result:
+// every combination computes the same residues.  Defaults come from the
+// environment (PM_TUNE_*, read once); the tuning table (pm_tune.cpp) may
+// override them per (prime class, log2 L, shape bucket).
+struct Knobs {
+  int split;         // stages of the streaming column pass (0 none, 2..4)
+  int maxr;          // most stages per LDS pass (2..4)
+  int blk_nt;        // single-product block step: threads (256 or 512)
+  int blk_tile_log;  // single-product block step: log2 residues per tile
+  int colvec_fwd;    // most entries per column-pass item (1, 2, 4), forward
+  int colvec_inv;    // ... inverse
+  int reg_tile;      // register-resident block tile where it fits (1) or LDS (0)
+  int pointwise;     // 1: int8-MFMA where the shape fits, 0: VALU
+  int pw_small_lds;  // largest limb-plane footprint run with 256 threads (bytes)
+  int pw_pipe;       // pipelined MFMA pointwise: -1 where it fits, 0 never, 1/2 force
 };
-const NttTune& ntt_tune();
-int split_stages(int logL);
+
+// Choices that are not per product.
+struct GlobalKnobs {
+  int lds_log;           // unsplit transforms: log2 residues of LDS per workgroup
+  int split_min_log;     // smallest log2 L that is split
+  int blk_pad;           // block step: LDS words of padding per position
+  int batch_tile_log;    // batched phase kernels: log2 residues per block tile
+  int batch_pw_work;     // batched pointwise tiles: multiply-adds per tile
+  int batch_pw_pipe_pts; // batched pipelined pointwise tiles: points per tile
+  int batch_direct_max;  // batches of at most this many products launch per product
+  int batch_graph;       // repeated batches replay as HIP graphs (1)
+  int wrap_min_log;      // wrapped form: least j (2^j points)
+  int wrap_top_div;      // ... top t <= 2^j / wrap_top_div
+  int wrap_min_work_log; // ... (mn + nk + mk) 2^j >= 2^wrap_min_work_log
+  int vdm_max_d;         // CRT-mode u32 products with d <= this go through Vandermonde
+};
+
+// Prime classes of the tuning table: direct mode with q < 2^30, direct mode
+// with q >= 2^30, CRT mode.
+enum { kClassDirectLt30 = 0, kClassDirectGe30 = 1, kClassCrt = 2 };
+
+// The knobs of a product (entry: index of the tuning-table entry used, -1
+// for the defaults).
+Knobs tuned_knobs(int pclass, int logL, int m, int n, int k, int* entry);
+// The defaults (no table entry) and the global choices of the current table.
+Knobs base_knobs();
+GlobalKnobs global_knobs();
+// Incremented whenever a tuning table is installed.
+uint64_t tune_epoch();
+
+PassPlan make_pass_plan(int logL, int split, int maxr);
 
 // Per-prime constants shared by all kernels.
 struct PrimeConst {
@@ -71,6 +99,8 @@ struct Plan {
   int r;                 // number of primes
   uint32_t q[kMaxPrimes];
   int pointwise;         // 0 VALU, 1 MFMA
+  Knobs kn;              // launch shapes (tuning table or defaults)
+  int tune_entry;        // tuning-table entry of kn, -1 for the defaults
   int m, n, k, d;
   // coefficient counts of A and B, and the window [lo, lo + nout) of the
   // product's coefficients that is computed (full product: d, d, 0, 2d-1)
@@ -99,8 +129,14 @@ int make_slice_plan(uint64_t p, int m, int n, int k, int da, int db, int lo, int
 int make_cyclic_plan(uint64_t p, int m, int n, int k, int d, int logL, int elem_bytes,
                      Plan* out);
 
-// Pointwise kernel for an m x n by n x k product per point: 1 int8-MFMA, 0 VALU.
-int choose_pointwise(int m, int n, int k);
+// Pointwise kernel for an m x n by n x k product per point: 1 int8-MFMA
+// (where `want` asks for it and the shape fits), 0 VALU.
+int choose_pointwise(int m, int n, int k, int want);
+
+// Pass structure of a plan's transforms.
+inline PassPlan plan_passes(const Plan& P) {
+  return make_pass_plan(P.logL, P.kn.split, P.kn.maxr);
+}
 
 // Host number theory (the library's own; the test oracle has separate code).
 bool is_prime_u64(uint64_t n);

@@ -48,30 +48,12 @@ size_t pointwise_mfma_lds(int m, int n, int k) {
   return 4 * (mp + kp) * (np + 16);
 }
 
-// Up to 44 KiB of limb planes: 256 threads, so that several workgroups share
-// a CU.  Above it, 512 threads: each thread stages half as many items and
-// so waits for fewer load round trips (measured on single products: 128x64x8
-// 44 -> 40 us, 64x128x32 70 -> 53 us, 128x32x64 109 -> 78 us, while 41 KiB
-// and below lose).  Tuning knob PM_TUNE_PW_SMALL_LDS (bytes).
-size_t pointwise_small_lds() {
-  static const size_t v = [] {
-    const char* e = getenv("PM_TUNE_PW_SMALL_LDS");
-    return e && *e ? (size_t)strtoull(e, nullptr, 10) : (size_t)44 * 1024;
-  }();
-  return v;
-}
-
 // Pipelined-kernel variant for a shape with 512 threads: 1 (4 A groups and
 // one B block per thread: 122 VGPRs, two workgroups per CU), 2 (8 and 2:
 // 154 VGPRs, one), or 0 when the shape needs more registers, k is not a
-// multiple of 4 or n <= 16 (packed contraction).  Tuning knob
-// PM_TUNE_PW_PIPE: 0 never pipelines, 1 or 2 forces that variant where it
-// suffices.
-int pointwise_pipe_variant(int m, int n, int k) {
-  static const int knob = [] {
-    const char* e = getenv("PM_TUNE_PW_PIPE");
-    return e && *e ? atoi(e) : -1;
-  }();
+// multiple of 4 or n <= 16 (packed contraction).  knob 0 never pipelines,
+// 1 or 2 forces that variant where it suffices.
+int pointwise_pipe_variant(int m, int n, int k, int knob) {
   if (knob == 0 || k % 4 != 0 || n <= 16) return 0;  // n <= 16: packed contraction
   const long mp = (m + 15) & ~15, kp = (k + 15) & ~15, ng = ((n + 63) & ~63) >> 2;
   const long need_a = (mp * ng + 511) / 512, need_b = (ng * (kp / 4) + 511) / 512;
@@ -111,10 +93,12 @@ int launch_pipe(const PointwiseLaunch& a, int nprimes, size_t lds, hipStream_t s
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s) {
   const size_t lds = pointwise_mfma_lds(a.m, a.n, a.k);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds <= pointwise_small_lds()) {
+  // small limb planes: 256 threads, so that several workgroups share a CU;
+  // larger ones: 512 threads, each waiting for fewer load round trips
+  if (lds <= (size_t)a.small_lds) {
     return launch(pointwise_mfma_kernel<256>, dim3(a.L, nprimes), dim3(256), lds, s, a);
   }
-  switch (pointwise_pipe_variant(a.m, a.n, a.k)) {
+  switch (pointwise_pipe_variant(a.m, a.n, a.k, a.pipe)) {
     case 1: return launch_pipe<4, 1>(a, nprimes, lds, s);
     case 2: return launch_pipe<8, 2>(a, nprimes, lds, s);
     default: break;

@@ -19,7 +19,7 @@ namespace pm {
 
 namespace {
 
-// kind 0: twiddles (a = q, b = logL, c = pass-structure signature);
+// kind 0: twiddles (a = q, b = logL, c = pass structure: split, maxr);
 // kind 1: Vandermonde (a = p, b = d).
 typedef std::tuple<int, uint32_t, int, uint64_t> Key;
 
@@ -58,12 +58,7 @@ bool stream_capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
-uint64_t pass_signature(int logL) {
-  const PassPlan P = make_pass_plan(logL);
-  uint64_t h = (uint64_t)P.split;
-  for (int i = 0; i < P.npass; ++i) h = h * 8 + (uint64_t)P.stages[i];
-  return h * 16 + (uint64_t)P.npass;
-}
+uint64_t pass_signature(const TwKey& k) { return (uint64_t)k.split * 16 + (uint64_t)k.maxr; }
 
 // Carve `bytes` from the device's regions (first fit, bump allocation).
 uint8_t* carve(DevTables& D, uint64_t bytes) {
@@ -191,8 +186,8 @@ int tables_attach_pool(int pool, void* dev_ptr, uint64_t bytes) {
   }
 }
 
-uint64_t twiddle_table_bytes(int logL) {
-  const PassPlan PP = make_pass_plan(logL);
+uint64_t twiddle_table_bytes(int logL, int split, int maxr) {
+  const PassPlan PP = make_pass_plan(logL, split, maxr);
   const uint64_t cnt = PP.tw_count ? PP.tw_count : 1;
   return align_up(2 * cnt * sizeof(Tw), 256);
 }
@@ -231,22 +226,22 @@ int prepare_twiddles(const TwKey* keys, int n, hipStream_t s) {
     alloc_point();  // the key list here, the table map and regions in prepare()
     std::vector<Want> want;
     for (int i = 0; i < n; ++i) {
-      const Key k(0, keys[i].q, keys[i].logL, pass_signature(keys[i].logL));
+      const Key k(0, keys[i].q, keys[i].logL, pass_signature(keys[i]));
       bool dup = false;
       for (const Want& w : want) dup = dup || w.key == k;
       if (dup) continue;
       if (!root_of_unity(keys[i].q, keys[i].logL)) return PM_EUNSUPPORTED;
-      want.push_back(Want{k, twiddle_table_bytes(keys[i].logL)});
+      want.push_back(Want{k, twiddle_table_bytes(keys[i].logL, keys[i].split, keys[i].maxr)});
     }
     std::vector<uint8_t*> ptrs;
     return prepare(
         want, s,
         [&](const Key& k, uint8_t* p) {
-          const uint32_t q = std::get<1>(k);
-          const int logL = std::get<2>(k);
-          const uint32_t w = root_of_unity(q, logL);
-          const uint32_t winv = (uint32_t)powmod_u64(w, (1ull << logL) - 1, q);
-          return launch_fill_twiddles(q, logL, w, winv, (Tw*)p, s);
+          const uint64_t sig = std::get<3>(k);
+          const TwKey key{std::get<1>(k), std::get<2>(k), (int)(sig / 16), (int)(sig % 16)};
+          const uint32_t w = root_of_unity(key.q, key.logL);
+          const uint32_t winv = (uint32_t)powmod_u64(w, (1ull << key.logL) - 1, key.q);
+          return launch_fill_twiddles(key, w, winv, (Tw*)p, s);
         },
         &ptrs);
   } catch (const std::bad_alloc&) {
@@ -254,16 +249,16 @@ int prepare_twiddles(const TwKey* keys, int n, hipStream_t s) {
   }
 }
 
-int prime_const(uint32_t q, int logL, PrimeConst* out) {
+int prime_const(const TwKey& key, PrimeConst* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PM_EDEVICE;
   std::lock_guard<std::mutex> lock(g_mu);
   auto d = g_dev.find(pool_key(t_pool, dev));
   if (d == g_dev.end()) return PM_EINVAL;
-  auto it = d->second.entries.find(Key(0, q, logL, pass_signature(logL)));
+  auto it = d->second.entries.find(Key(0, key.q, key.logL, pass_signature(key)));
   if (it == d->second.entries.end()) return PM_EINVAL;
-  prime_const_host(q, logL, out);
-  const PassPlan PP = make_pass_plan(logL);
+  prime_const_host(key.q, key.logL, out);
+  const PassPlan PP = make_pass_plan(key.logL, key.split, key.maxr);
   const size_t cnt = PP.tw_count ? PP.tw_count : 1;
   out->tw_fwd = (const Tw*)it->second.ptr;
   out->tw_inv = (const Tw*)it->second.ptr + cnt;

@@ -15,15 +15,17 @@
 
 namespace pm {
 
-// One (prime, transform length) pair whose twiddle tables a launch reads.
+// One (prime, transform length, pass structure) whose twiddle tables a
+// launch reads.
 struct TwKey {
   uint32_t q;
-  int logL;
+  int logL, split, maxr;
 };
 
 // Bytes of the forward and inverse twiddle tables for a length-2^logL
-// transform (pass structure of make_pass_plan), 256-byte aligned.
-uint64_t twiddle_table_bytes(int logL);
+// transform with the pass structure make_pass_plan(logL, split, maxr),
+// 256-byte aligned.
+uint64_t twiddle_table_bytes(int logL, int split, int maxr);
 // Bytes of the Vandermonde tables for degree bound d (V, W and the helper
 // arrays they are built from), 256-byte aligned.
 uint64_t vdm_table_bytes(int d);
@@ -35,9 +37,9 @@ uint64_t vdm_table_bytes(int d);
 // PM_ETABLES is returned.  PM_EDEVICE if a launch fails.
 int prepare_twiddles(const TwKey* keys, int n, hipStream_t s);
 
-// Constants and device table pointers of a prepared pair; PM_EINVAL if the
-// pair was never prepared on the current device.
-int prime_const(uint32_t q, int logL, PrimeConst* out);
+// Constants and device table pointers of a prepared key; PM_EINVAL if the
+// key was never prepared on the current device.
+int prime_const(const TwKey& key, PrimeConst* out);
 
 // Host part of PrimeConst (q, L^-1 and its companion, Barrett constant).
 void prime_const_host(uint32_t q, int logL, PrimeConst* out);
@@ -71,8 +73,7 @@ uint64_t tables_epoch();
 
 // Device fills (pm_tables.hip).  dst holds max(tw_count, 1) forward entries
 // followed by as many inverse ones.
-int launch_fill_twiddles(uint32_t q, int logL, uint32_t w, uint32_t winv, Tw* dst,
-                         hipStream_t s);
+int launch_fill_twiddles(const TwKey& key, uint32_t w, uint32_t winv, Tw* dst, hipStream_t s);
 // V: (2d-1) x d, W: (2d-1) x (2d-1), work: 2(2d-1) + 1 words of helper data.
 int launch_fill_vdm(uint32_t p, int d, uint32_t* V, uint32_t* W, uint32_t* work,
                     hipStream_t s);

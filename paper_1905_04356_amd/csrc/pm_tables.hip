@@ -126,14 +126,13 @@ __global__ __launch_bounds__(256) void vdm_w_kernel(uint32_t p, int N, const uin
 
 }  // namespace
 
-int launch_fill_twiddles(uint32_t q, int logL, uint32_t w, uint32_t winv, Tw* dst,
-                         hipStream_t s) {
-  const PassPlan PP = make_pass_plan(logL);
+int launch_fill_twiddles(const TwKey& key, uint32_t w, uint32_t winv, Tw* dst, hipStream_t s) {
+  const PassPlan PP = make_pass_plan(key.logL, key.split, key.maxr);
   TwFill f{};
-  f.q = q;
+  f.q = key.q;
   f.w = w;
   f.winv = winv;
-  f.logL = logL;
+  f.logL = key.logL;
   f.npass = PP.npass;
   for (int i = 0; i < PP.npass; ++i) {
     f.stride_log[i] = PP.stride_log[i];

@@ -196,14 +196,19 @@ def test_check_residues():
                                      (32, 68, 48, 9), (128, 128, 128, 6), (128, 64, 96, 5),
                                      (20, 252, 3, 2)])
 @pytest.mark.parametrize("p", [P30, P31, P32])
-def test_pointwise_variants_match_oracle(p, m, n, k, d, monkeypatch):
+def test_pointwise_variants_match_oracle(p, m, n, k, d):
     """Both pointwise kernels (int8-MFMA limbs and VALU) against the oracle."""
-    info = Bd.pm_plan(p, m, n, k, d, 4)
-    assert info.pointwise == 1, "shape expected on the MFMA path"
-    full_check(p, m, n, k, d, seed=11)
-    monkeypatch.setenv("PM_TUNE_POINTWISE", "0")
-    assert Bd.pm_plan(p, m, n, k, d, 4).pointwise == 0
-    full_check(p, m, n, k, d, seed=11)
+    Bd.tune_load("")
+    try:
+        info = Bd.pm_plan(p, m, n, k, d, 4)
+        assert info.pointwise == 1, "shape expected on the MFMA path"
+        full_check(p, m, n, k, d, seed=11)
+        Bd.tune_load('{"format": "pm-tune-1", "entries": [{"knobs": {"pointwise": 0}}]}')
+        assert Bd.pm_plan(p, m, n, k, d, 4).pointwise == 0
+        full_check(p, m, n, k, d, seed=11)
+    finally:
+        torch.cuda.synchronize()
+        Bd.tune_load(None)
 
 
 @pytest.mark.parametrize("p,m,n,k,d", [

@@ -1,0 +1,145 @@
+"""Launch shapes from the tuning table never change a result: products under
+tables that force other pass structures, block-step threads and tiles,
+column item widths, LDS instead of register tiles, VALU pointwise and
+pipelined pointwise slots equal the oracle coefficient by coefficient, single
+and batched, direct and CRT moduli; evaluations made under one table feed
+products planned under another. Wrapped lengths with the size bound lowered
+(a global knob) are compared with the oracle on small products, including
+the extreme tops t = 1 and t = 2^j / 4."""
+from __future__ import annotations
+
+import json
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1905_04356_amd import binding as Bd  # noqa: E402
+from paper_1905_04356_amd import inputs as I  # noqa: E402
+from paper_1905_04356_amd import polymat  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+P30 = 998244353
+P31 = 2013265921
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _restore_table():
+    yield
+    torch.cuda.synchronize()
+    Bd.tune_load(None)
+
+
+def table(knobs, glob=None):
+    t = {"format": "pm-tune-1", "entries": [{"knobs": knobs}]}
+    if glob:
+        t["global"] = glob
+    return json.dumps(t)
+
+
+TABLES = [
+    {"split": 3, "maxr": 3, "blk_nt": 512, "colvec_fwd": 2, "colvec_inv": 1},
+    {"split": 2, "maxr": 2, "reg_tile": 0, "pointwise": 0},
+    {"blk_tile_log": 12, "colvec_fwd": 1, "pw_pipe": 2, "pw_small_lds": 0},
+    {"blk_tile_log": 14, "blk_nt": 512, "maxr": 3, "pw_pipe": 0, "pw_small_lds": 0},
+    {"split": 0, "maxr": 4, "pw_pipe": 1, "pw_small_lds": 0},
+]
+GLOBAL = {"batch_tile_log": 13, "batch_pw_work": 2048, "batch_direct_max": 0,
+          "batch_graph": 0}
+
+SHAPES = [  # (p, m, n, k, d, dtype): lengths 2^11 .. 2^13, odd entry counts
+    (P31, 16, 16, 16, 1500, np.uint32),
+    (P30, 8, 12, 4, 3000, np.uint32),
+    (P31, 5, 7, 3, 600, np.uint32),
+    (P30, 3, 5, 7, 2000, np.uint32),
+    (1152921504606846883, 4, 8, 4, 700, np.uint64),
+]
+
+
+def operands(p, m, n, k, d, dtype, seed):
+    A = I.polymat(seed, 0, I.TENSOR_A, p, d, m, n, dtype)
+    B = I.polymat(seed, 0, I.TENSOR_B, p, d, n, k, dtype)
+    return A, B
+
+
+@pytest.mark.parametrize("ti", range(len(TABLES)))
+def test_products_under_forced_knobs_equal_the_oracle(ti):
+    knobs = TABLES[ti]
+    if knobs.get("split") == 0:
+        shapes = [s for s in SHAPES if 2 * s[4] - 1 <= 4096]   # unsplit: L <= 2^12
+    else:
+        shapes = SHAPES
+    say(f"[tune] table {ti}: {knobs}")
+    Bd.tune_load(table(knobs, GLOBAL))
+    refs, As, Bs = [], [], []
+    for idx, (p, m, n, k, d, dt) in enumerate(shapes):
+        A, B = operands(p, m, n, k, d, dt, seed=40 + idx)
+        assert Bd.pm_plan(p, m, n, k, d, 4 if dt == np.uint32 else 8).tune_entry == 0
+        ref = O.polymatmul(p, A, B)
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = polymat.mul(p, tA, tB)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy().astype(np.uint64), ref), (ti, idx)
+        refs.append(ref)
+        As.append(tA)
+        Bs.append(tB)
+    # the same products in one batched call per modulus and element size
+    groups = {}
+    for idx, s in enumerate(shapes):
+        groups.setdefault((s[0], s[5]), []).append(idx)
+    for (p, dt), ids in groups.items():
+        outs = polymat.mul_batched(p, [As[i] for i in ids], [Bs[i] for i in ids])
+        torch.cuda.synchronize()
+        for i, C in zip(ids, outs):
+            assert np.array_equal(C.cpu().numpy().astype(np.uint64), refs[i]), (ti, i)
+
+
+def test_evaluations_under_one_table_feed_products_under_another():
+    """The point order of evaluations does not depend on the pass structure."""
+    p, m, n, k, d = P31, 8, 16, 4, 1800
+    A, B = operands(p, m, n, k, d, np.uint32, seed=50)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = O.polymatmul(p, A, B)
+    Bd.tune_load(table({"split": 3, "maxr": 2}))
+    Ae = polymat.evaluate(p, tA, 0)
+    torch.cuda.synchronize()
+    Bd.tune_load(table({"split": 4, "maxr": 4, "reg_tile": 0}))
+    Be = polymat.evaluate(p, tB, 1)
+    torch.cuda.synchronize()
+    Bd.tune_load(table({"split": 2, "maxr": 3}))
+    (C,) = polymat.mul_batched(p, [tA], [tB], A_evals=[Ae], B_evals=[Be])
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.uint64), ref)
+
+
+@pytest.mark.parametrize("p,m,n,k,d,j", [
+    (P30, 3, 4, 2, 513, 10),       # 2d - 1 = 1025 = 2^10 + 1: top t = 1
+    (P30, 2, 3, 2, 640, 10),       # 1279 = 2^10 + 255: t = 2^10 / 4 - 1
+    (P30, 4, 4, 4, 641, 10),       # 1281 = 2^10 + 257 > 2^10 + 2^10 / 4: plain
+    (P31, 5, 2, 3, 1025, 11),      # 2049 = 2^11 + 1
+    (P31, 3, 3, 3, 1280, 11),      # 2559 = 2^11 + 511 = 2^11 + 2^11 / 4 - 1
+    (P30, 2, 2, 2, 4097, 13),      # 8193 = 2^13 + 1
+])
+def test_small_wrapped_products_equal_the_oracle(p, m, n, k, d, j):
+    """The wrapped form (cyclic product on 2^j points, short top product,
+    correction) on small products, every coefficient against the oracle."""
+    Bd.tune_load(json.dumps({"format": "pm-tune-1", "global": {"wrap_min_work_log": 0}}))
+    t = 2 * d - 1 - (1 << j)
+    want_j = j if t <= (1 << j) // 4 else 0
+    assert Bd.pm_plan(p, m, n, k, d, 4).wrap_log2_len == want_j
+    A, B = operands(p, m, n, k, d, np.uint32, seed=60 + d)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = polymat.mul(p, tA, tB)
+    torch.cuda.synchronize()
+    ref = O.polymatmul(p, A, B)
+    bad = np.argwhere(C.cpu().numpy().astype(np.uint64) != ref)
+    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
