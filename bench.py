@@ -544,7 +544,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
             traffic[kind_of(name)] += v * wscale / pmc_total_steps
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
-              "--no-batched --no-middle --no-pmbasis --serving-seconds 0")
+              "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           f"`avg us` is rocprofv3's --stats average over all calls ({warmup_stats} warm-up "
@@ -565,7 +565,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
-                  "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --serving-seconds 0")
+                  "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0")
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
@@ -649,10 +649,13 @@ def load_traffic(workload):
 
 
 def bench_serving(seconds, seed=5, rate=2000.0, pool_size=64, p=998244353,
-                  budget_gb=64.0, streams=4):
+                  budget_gb=64.0, streams=4, warmup_s=5.0, sweep="", sweep_seconds=10.0):
     """Config 5: Poisson arrivals (`rate` per second) of products with the
     batched shape rule, operands and their evaluations resident in a pool;
-    continuous batching vs one pm_mul call per request on the same trace."""
+    continuous batching against one product per launch in arrival order
+    (same resident evaluations) on the same trace. Latency percentiles leave
+    out the requests that arrive in the first `warmup_s` seconds. A sweep
+    over further rates (shorter traces) follows."""
     import torch
 
     from paper_1905_04356_amd import serving as S
@@ -664,18 +667,253 @@ def bench_serving(seconds, seed=5, rate=2000.0, pool_size=64, p=998244353,
     S.Server(p, pool, int(budget_gb * 2 ** 30), streams=streams).run(wa, wi)
     S.run_fifo(p, pool, wa, wi)
     torch.cuda.synchronize()
-    arrivals, items = S.trace(seed, rate, seconds, pool_size)
-    srv = S.Server(p, pool, int(budget_gb * 2 ** 30), streams=streams)
-    cb = srv.run(arrivals, items)
+
+    def one(r, secs, skip, tseed):
+        arrivals, items = S.trace(tseed, r, secs, pool_size)
+        progress(f"serving: {r:g} req/s for {secs:g} s, continuous batching")
+        srv = S.Server(p, pool, int(budget_gb * 2 ** 30), streams=streams, warmup_s=skip)
+        cb = srv.run(arrivals, items)
+        torch.cuda.synchronize()
+        progress(f"serving: {r:g} req/s for {secs:g} s, one product per launch")
+        fifo, _ = S.run_fifo(p, pool, arrivals, items, warmup_s=skip)
+        torch.cuda.synchronize()
+        offered = sum(pool[i].m * pool[i].n * pool[i].k * pool[i].d for i in items) / secs
+        return {"rate": r, "seconds": secs, "offered_coef_mac_per_s": offered,
+                "continuous_batching": cb, "one_product_per_launch": fifo}
+
+    main = one(rate, seconds, warmup_s, seed)
+    out = {"workload": f"Poisson {rate:g} req/s for {seconds:g} s, {pool_size} resident operand "
+                       f"pairs (batched shape rule, seed {seed}), mod {p}; percentiles over "
+                       f"arrivals after {warmup_s:g} s",
+           "offered_coef_mac_per_s": main["offered_coef_mac_per_s"],
+           "continuous_batching": main["continuous_batching"],
+           "one_call_per_request": main["one_product_per_launch"],
+           "baseline": "one product per launch on one stream, in arrival order, with the same "
+                       "resident evaluations",
+           "budget_GB": budget_gb, "streams": streams}
+    rates = [float(x) for x in sweep.split(",") if x.strip()] if sweep else []
+    if rates:
+        out["sweep"] = [one(r, sweep_seconds, min(2.0, sweep_seconds / 5), seed + 17 + i)
+                        for i, r in enumerate(rates)]
+    return out
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_single(workload, steps, warmup):
+    """One product per step (pm_mul on resident operands): throughput, the
+    per-step device time distribution, per-kernel device times and their
+    rooflines, and the whole path's roofline fraction."""
+    import numpy as np
+    import torch
+
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+
+    p, m, n, k, d, dt = workload_params(workload)
+    npdt = np.uint32 if dt == "u32" else np.uint64
+    eb = 4 if dt == "u32" else 8
+    plan = Bd.pm_plan(p, m, n, k, d, eb)
+    A = I.polymat(2, 0, I.TENSOR_A, p, d, m, n, npdt)
+    B = I.polymat(2, 0, I.TENSOR_B, p, d, n, k, npdt)
+    dev = torch.device("cuda:0")
+    tA = torch.from_numpy(A).to(dev)
+    tB = torch.from_numpy(B).to(dev)
+    tC = torch.empty((2 * d - 1, m, k), dtype=tA.dtype, device=dev)
+    ws = polymat.Workspace(dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(warmup):
+        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
     torch.cuda.synchronize()
-    fifo, _ = S.run_fifo(p, pool, arrivals, items)
+
+    # Kernel durations come from the dispatch events of every
+    # PROFILE_EVERY-th step of the timed loop (each timed launch costs a few
+    # microseconds of dispatch work, so not every step carries them).
+    Bd.pm_profile_begin()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    offered = sum(pool[i].m * pool[i].n * pool[i].k * pool[i].d for i in items) / seconds
-    return {"workload": f"Poisson {rate:g} req/s for {seconds:g} s, {pool_size} resident operand "
-                        f"pairs (batched shape rule, seed {seed}), mod {p}",
-            "offered_coef_mac_per_s": offered,
-            "continuous_batching": cb, "one_call_per_request": fifo,
-            "budget_GB": budget_gb, "streams": streams}
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(steps):
+        Bd.pm_profile_pause(i % PROFILE_EVERY != 0)
+        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = Bd.pm_profile_end()
+    timed_steps = len(range(0, steps, PROFILE_EVERY))
+
+    # Distribution of single-step device times, from a separate loop of the
+    # same length with an event between consecutive steps (so these events
+    # stay out of the timed loop above).
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for i in range(steps):
+        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    dist = {"median": per_step[len(per_step) // 2] if len(per_step) % 2 else
+            0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2]),
+            "min": per_step[0],
+            "p90": per_step[max(0, -(-9 * len(per_step) // 10) - 1)],   # nearest rank
+            "steps": steps}
+
+    wall = t1 - t0
+    work = float(m) * n * k * d
+    value = work * steps / wall
+    kernels = {}
+    for kind, (ms, launches) in kstats.items():
+        if launches == 0:
+            continue
+        byts, ops = kernel_work(kind, plan, p, m, n, k, d, eb)
+        sec = ms / 1e3 / timed_steps          # device seconds per product
+        kernels[kind] = {"ms_per_step": ms / timed_steps, "launches_per_step":
+                         launches / timed_steps, "algorithmic_bytes": byts,
+                         "ops": ops}
+        kernels[kind]["roofline"] = roofline_for(kind, byts, ops, sec, plan)
+    traffic = load_traffic(workload)
+    for kind in kernels:
+        kernels[kind]["roofline"]["traffic"] = traffic.get(kind) if traffic else None
+    dominant = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
+    roof = dict(kernels[dominant]["roofline"])
+    # the path's fraction against the median per-step device time (the
+    # measurement's definition), and against the timed loop's mean
+    mean_ms = ev0.elapsed_time(ev1) / steps
+    roof["path"] = path_roofline(kernels, plan, dist["median"])
+    roof["path"]["measured"] = "median per-step device time"
+    roof["path"]["mean_us"] = mean_ms * 1e3
+    roof["path"]["frac_mean"] = roof["path"]["floor_us"] / (mean_ms * 1e3)
+
+    out = {
+        "metric": "polymatrix mul mod p: m*n*k*d coefficient-MACs/s",
+        "value": value,
+        "unit": "coefficient-MAC/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "device_ms_per_step": mean_ms,
+        "device_ms_per_step_dist": dist,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic: seeded uniform residues in [0, p) (splitmix64)",
+        "config": {"workload": f"{m}x{n}.{n}x{k} polynomial matrices, degree<{d}, mod {p}",
+                   "p": p, "m": m, "n": n, "k": k, "d": d,
+                   "L": 1 << plan.log2_len, "mode": "direct" if plan.mode == 0 else "crt",
+                   "primes": plan.num_primes,
+                   "pointwise": "mfma_int8" if plan.pointwise == 1 else "valu",
+                   "tune_entry": plan.tune_entry},
+        "roofline": roof,
+        "kernels": kernels,
+        "kernel_timing": f"dispatch start/stop events on {timed_steps} of the {steps} "
+                         f"timed steps (every {PROFILE_EVERY}th)",
+    }
+    del tA, tB, tC, ws
+    return {"_out": out, "p": p, "m": m, "n": n, "k": k, "d": d, "A": A, "B": B}
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def bench_tuned_vs_default(workload, rounds=5, steps=10):
+    """The product timed under the tuning table and with no table (the
+    defaults), alternately: median device ms per product of each."""
+    import torch
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+    p, m, n, k, d, dt = workload_params(workload)
+    dev = torch.device("cuda:0")
+    tdt = torch.uint32 if dt == "u32" else torch.uint64
+    A = I.polymat_torch(2, 0, I.TENSOR_A, p, d, m, n, dev, tdt)
+    B = I.polymat_torch(2, 0, I.TENSOR_B, p, d, n, k, dev, tdt)
+    C = torch.empty((2 * d - 1, m, k), dtype=tdt, device=dev)
+    ws = polymat.Workspace(dev)
+    stream = torch.cuda.current_stream()
+    info = Bd.tune_info()
+    entry = Bd.pm_plan(p, m, n, k, d, 4 if dt == "u32" else 8).tune_entry
+
+    def once():
+        for _ in range(3):
+            polymat.mul(p, A, B, out=C, workspace=ws, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            polymat.mul(p, A, B, out=C, workspace=ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    tuned, dflt = [], []
+    try:
+        for _ in range(rounds):
+            Bd.tune_load(None)
+            tuned.append(once())
+            Bd.tune_load("")
+            dflt.append(once())
+    finally:
+        torch.cuda.synchronize()
+        Bd.tune_load(None)
+    del A, B, C, ws
+    return {"table_entries": info[0], "table_source": info[1], "tune_entry": entry,
+            "tuned_ms": _median(tuned), "default_ms": _median(dflt),
+            "speedup": _median(dflt) / _median(tuned)}
+
+
+def bench_batched_tuned_vs_default(seed=3, count=512, p=998244353, rounds=3):
+    """The batched workload under the tuning table and with no table
+    (defaults), alternately: median wall ms per batched call (graph replays)."""
+    import torch
+    from paper_1905_04356_amd import binding as Bd
+    from paper_1905_04356_amd import inputs as I
+    from paper_1905_04356_amd import polymat
+    dev = torch.device("cuda:0")
+    shapes = I.batched_shapes(seed, count)
+    As = [I.polymat_torch(seed, i, I.TENSOR_A, p, d, m, n, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    Bs = [I.polymat_torch(seed, i, I.TENSOR_B, p, d, n, k, dev) for i, (m, n, k, d) in
+          enumerate(shapes)]
+    outs = [torch.empty((2 * d - 1, m, k), dtype=torch.uint32, device=dev)
+            for (m, n, k, d) in shapes]
+    ws = polymat.Workspace(dev)
+    stream = torch.cuda.current_stream()
+    used = sum(Bd.pm_plan(p, m, n, k, d, 4).tune_entry >= 0 for (m, n, k, d) in shapes)
+
+    def once():
+        for _ in range(2):          # eager, then graph capture
+            polymat.mul_batched(p, As, Bs, outs, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            polymat.mul_batched(p, As, Bs, outs, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 3 * 1e3
+
+    tuned, dflt = [], []
+    try:
+        for _ in range(rounds):
+            Bd.tune_load(None)
+            tuned.append(once())
+            Bd.tune_load("")
+            dflt.append(once())
+    finally:
+        torch.cuda.synchronize()
+        Bd.tune_load(None)
+    del As, Bs, outs, ws
+    return {"products_with_table_entries": int(used), "tuned_ms": _median(tuned),
+            "default_ms": _median(dflt), "speedup": _median(dflt) / _median(tuned)}
 
 
 def calibration_copy():
@@ -702,9 +940,15 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-middle", action="store_true")
     ap.add_argument("--no-pmbasis", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=3)
-    ap.add_argument("--serving-seconds", type=float, default=10.0,
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the tuned-vs-default comparisons and the c1/c4 products")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the serving trace (0: skip)")
+    ap.add_argument("--serving-warmup", type=float, default=5.0,
+                    help="seconds at the start of each trace left out of the percentiles")
+    ap.add_argument("--serving-sweep", default="4000,8000",
+                    help="further arrival rates (req/s), 10 s each ('' : none)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run only the 1 GiB copy used to calibrate HBM byte counters")
     ap.add_argument("--only-batched", action="store_true",
@@ -721,7 +965,7 @@ def main():
         summarize_profiles(args.summarize_profiles, 20, 100, 3, args.workload)
         return
     if args.summarize_batched:
-        summarize_batched(args.summarize_batched, 1 + args.batched_steps, 1 + args.batched_steps)
+        summarize_batched(args.summarize_batched, 2 + args.batched_steps, 2 + args.batched_steps)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs every product on a single "
@@ -729,118 +973,42 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
-        print(json.dumps(bench_batched(args.batched_steps, 1)), flush=True)
+        print(json.dumps(bench_batched(args.batched_steps, 2)), flush=True)
         return
 
-    import numpy as np
     import torch
 
-    from paper_1905_04356_amd import binding as Bd
-    from paper_1905_04356_amd import inputs as I
-    from paper_1905_04356_amd import polymat
-
-    p, m, n, k, d, dt = workload_params(args.workload)
-    npdt = np.uint32 if dt == "u32" else np.uint64
-    eb = 4 if dt == "u32" else 8
-    plan = Bd.pm_plan(p, m, n, k, d, eb)
-    A = I.polymat(2, 0, I.TENSOR_A, p, d, m, n, npdt)
-    B = I.polymat(2, 0, I.TENSOR_B, p, d, n, k, npdt)
-    dev = torch.device("cuda:0")
-    tA = torch.from_numpy(A).to(dev)
-    tB = torch.from_numpy(B).to(dev)
-    tC = torch.empty((2 * d - 1, m, k), dtype=tA.dtype, device=dev)
-    ws = polymat.Workspace(dev)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-
-    # Kernel durations come from the dispatch events of every
-    # PROFILE_EVERY-th step of the timed loop (each timed launch costs a few
-    # microseconds of dispatch work, so not every step carries them).
-    Bd.pm_profile_begin()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        Bd.pm_profile_pause(i % PROFILE_EVERY != 0)
-        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kstats = Bd.pm_profile_end()
-    timed_steps = len(range(0, args.steps, PROFILE_EVERY))
-
-    # Distribution of single-step device times, from a separate loop of the
-    # same length with an event between consecutive steps (so these events
-    # stay out of the timed loop above).
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    evs[0].record(stream)
-    for i in range(args.steps):
-        polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
-    dist = {"median": per_step[len(per_step) // 2] if len(per_step) % 2 else
-            0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2]),
-            "min": per_step[0],
-            "p90": per_step[max(0, -(-9 * len(per_step) // 10) - 1)],   # nearest rank
-            "steps": args.steps}
-
-    wall = t1 - t0
-    work = float(m) * n * k * d
-    value = work * args.steps / wall
-    kernels = {}
-    for kind, (ms, launches) in kstats.items():
-        if launches == 0:
-            continue
-        byts, ops = kernel_work(kind, plan, p, m, n, k, d, eb)
-        sec = ms / 1e3 / timed_steps          # device seconds per product
-        kernels[kind] = {"ms_per_step": ms / timed_steps, "launches_per_step":
-                         launches / timed_steps, "algorithmic_bytes": byts,
-                         "ops": ops}
-        kernels[kind]["roofline"] = roofline_for(kind, byts, ops, sec, plan)
-    traffic = load_traffic(args.workload)
-    for kind in kernels:
-        kernels[kind]["roofline"]["traffic"] = traffic.get(kind) if traffic else None
-    dominant = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
-    roof = dict(kernels[dominant]["roofline"])
-    roof["path"] = path_roofline(kernels, plan, ev0.elapsed_time(ev1) / args.steps)
-
-    out = {
-        "metric": "polymatrix mul mod p: m*n*k*d coefficient-MACs/s",
-        "value": value,
-        "unit": "coefficient-MAC/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "device_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
-        "device_ms_per_step_dist": dist,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dt,
-        "data": "synthetic: seeded uniform residues in [0, p) (splitmix64)",
-        "config": {"workload": f"{m}x{n}.{n}x{k} polynomial matrices, degree<{d}, mod {p}",
-                   "p": p, "m": m, "n": n, "k": k, "d": d,
-                   "L": 1 << plan.log2_len, "mode": "direct" if plan.mode == 0 else "crt",
-                   "primes": plan.num_primes,
-                   "pointwise": "mfma_int8" if plan.pointwise == 1 else "valu"},
-        "roofline": roof,
-        "kernels": kernels,
-        "kernel_timing": f"dispatch start/stop events on {timed_steps} of the {args.steps} "
-                         f"timed steps (every {PROFILE_EVERY}th)",
-    }
-    del tA, tB, tC, ws
+    progress(f"single product {args.workload}: {args.warmup} warm-up, {args.steps} timed steps")
+    res = bench_single(args.workload, args.steps, args.warmup)
+    out = res.pop("_out")
+    p, m, n, k, d = res["p"], res["m"], res["n"], res["k"], res["d"]
+    A, B = res["A"], res["B"]
+    out["tuning"] = {}
+    if not args.no_extra:
+        progress("tuning table against the defaults")
+        out["tuning"]["single"] = bench_tuned_vs_default(args.workload)
+    for w in () if args.no_extra else ("c1", "c4"):
+        if w != args.workload:
+            progress(f"single product {w}")
+            r = bench_single(w, 20, 20)
+            o = r.pop("_out")
+            keep = {kk: o[kk] for kk in ("value", "unit", "ms_per_step", "device_ms_per_step",
+                                         "device_ms_per_step_dist", "dtype", "config",
+                                         "roofline", "kernels", "steps", "warmup")}
+            if not args.no_cpu_baseline:
+                keep["cpu_baseline"] = cpu_baseline(r["p"], r["A"], r["B"], r["m"], r["n"],
+                                                    r["k"], r["d"], 5.0)
+            out[w] = keep
+            torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     if not args.no_batched:
-        out["batched"] = bench_batched(args.batched_steps, 1)
+        progress("batched: 512 products")
+        out["batched"] = bench_batched(args.batched_steps, 2)
+        if not args.no_extra:
+            out["tuning"]["batched"] = bench_batched_tuned_vs_default()
         torch.cuda.empty_cache()
     if not args.no_middle:
+        progress("middle product, PM-Basis, Newton, Vandermonde, wrapped lengths")
         out["middle"] = bench_middle()
         torch.cuda.empty_cache()
     if not args.no_pmbasis:
@@ -853,9 +1021,11 @@ def main():
         out["wrapped_lengths"] = bench_wrap()
         torch.cuda.empty_cache()
     if args.serving_seconds > 0:
-        out["serving"] = bench_serving(args.serving_seconds)
+        out["serving"] = bench_serving(args.serving_seconds, warmup_s=args.serving_warmup,
+                                       sweep=args.serving_sweep, sweep_seconds=10.0)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, A, B, m, n, k, d, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -68,6 +68,15 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   int eb = (PP.split ? (batched ? G.batch_tile_log : kn.blk_tile_log) : G.lds_log) - a->blk_log;
   if (eb < 0) eb = 0;
   while (eb > 0 && (1 << (eb - 1)) >= E) --eb;
+  // A single product with few entries takes fewer entries per workgroup,
+  // down to one, while its launch would have fewer than min_wg workgroups:
+  // such transforms are latency-bound (a full-size register tile is kept).
+  if (!batched && G.min_wg > 0) {
+    const int nt_log = kn.blk_nt == 512 ? 9 : 8;
+    const bool full_reg = PP.split && kn.reg_tile && a->blk_log + eb == nt_log + 5;
+    const long zb = PP.split ? 1L << PP.split : 1;
+    while (eb > 0 && !full_reg && ((E + (1L << eb) - 1) >> eb) * zb < G.min_wg) --eb;
+  }
   a->eb_log = eb;
   // entries move between HBM and LDS in vectors of V consecutive residues
   int v = 4;

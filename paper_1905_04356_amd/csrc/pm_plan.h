@@ -66,6 +66,8 @@ struct GlobalKnobs {
   int wrap_top_div;      // ... top t <= 2^j / wrap_top_div
   int wrap_min_work_log; // ... (mn + nk + mk) 2^j >= 2^wrap_min_work_log
   int vdm_max_d;         // CRT-mode u32 products with d <= this go through Vandermonde
+  int min_wg;            // single-product transforms: fewer entries per workgroup
+                         // while a launch has fewer workgroups than this (0: off)
 };
 
 // Prime classes of the tuning table: direct mode with q < 2^30, direct mode
