@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 INT8_MFMA_PEAK_TOPS = 5000.0          # dense int8, 5.0 POP/s
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
+XCDS = 8
 VALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # 39.3 T 32-bit lane-ops/s
 
 PROFILE_EVERY = 4        # kernel timing on every 4th step of the timed loop
@@ -588,6 +589,90 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     print("wrote profiles for", workload)
 
 
+COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS",
+            "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_SALU", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def summarize_counters(root, workload, steps_pmc=3):
+    """profiles/<workload>_counters.md from one rocprofv3 --pmc run of
+    bench.py under root/vc/ (the COUNTERS above): per kernel and per step,
+    waves, VALU and LDS instructions, LDS bank conflicts, and the derived
+    VALU busy fraction (SQ_ACTIVE_INST_VALU x 4 cycles per wave-instruction
+    over the SIMDs' busy cycles) and VALU lane-operations per butterfly for
+    the transform kernels."""
+    import collections
+    import csv
+    import glob
+    from paper_1905_04356_amd import binding as Bd
+    files = glob.glob(os.path.join(root, "vc", "*counter_collection*.csv"))
+    rows = list(csv.DictReader(open(files[0])))
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    dur = collections.defaultdict(float)
+    seen = set()
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "pm::" not in name:
+            continue
+        per[name][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[name].add(r["Dispatch_Id"])
+        key = (name, r["Dispatch_Id"])
+        if key not in seen and r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            seen.add(key)
+            dur[name] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    steps = 1 + 2 * (steps_pmc - 1)
+    p, m, n, k, d, dt = workload_params(workload)
+    plan = Bd.pm_plan(p, m, n, k, d, 4 if dt == "u32" else 8)
+    L, logL, r_ = 1 << plan.log2_len, plan.log2_len, plan.num_primes
+    split = 4 if logL >= 11 else 0
+    bfly = {"col_fwd": split * (L // 2) * (m * n + n * k) * r_,
+            "block_fwd": (logL - split) * (L // 2) * (m * n + n * k) * r_,
+            "block_inv": (logL - split) * (L // 2) * m * k * r_,
+            "col_inv": split * (L // 2) * m * k * r_}
+
+    def role(name):
+        if "ntt_col_fwd" in name:
+            return "col_fwd"
+        if "ntt_col_inv" in name:
+            return "col_inv"
+        if "ntt_block" in name:
+            return "block_fwd" if "<true" in name else "block_inv"
+        return None
+
+    simds = CUS * 4
+    cmd = ("timeout -s KILL 90 rocprofv3 --pmc " + " ".join(COUNTERS) +
+           " --output-format csv -d gpurun_out/vc -o vc -- python3 bench.py --steps "
+           f"{steps_pmc - 1} --warmup 1 --workload {workload} --no-cpu-baseline --no-batched "
+           "--no-middle --no-pmbasis --no-extra --serving-seconds 0")
+    md = [f"# Instruction counters: {workload}", "",
+          "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
+          f"Sums over the {steps} steps of the run, divided by {steps} (per step). "
+          "GRBM_GUI_ACTIVE is summed over the 8 XCDs (it reads about 8 x 2.4 GHz x "
+          "duration), so one XCD's busy cycles are GRBM_GUI_ACTIVE / 8. "
+          "VALU busy = SQ_ACTIVE_INST_VALU x 4 / (SIMDs x GRBM_GUI_ACTIVE / 8), SIMDs = "
+          f"{simds} (a wave's VALU instruction holds its SIMD for 4 cycles); the clock "
+          "column is GRBM_GUI_ACTIVE / 8 / duration. "
+          "VALU lane-ops per butterfly = SQ_INSTS_VALU x 64 / butterflies (transform "
+          "kernels; the butterflies of both operands, or of C, per step).", "",
+          "| kernel | dispatches/step | waves | VALU insts | LDS insts | LDS bank conflicts "
+          "| GRBM_GUI_ACTIVE / 8 | clock GHz | VALU busy | lane-ops/butterfly |",
+          "|---|---|---|---|---|---|---|---|---|---|"]
+    for name, c in sorted(per.items(), key=lambda x: -x[1]["GRBM_GUI_ACTIVE"]):
+        g = c["GRBM_GUI_ACTIVE"] / XCDS
+        busy = c["SQ_ACTIVE_INST_VALU"] * 4 / (simds * g) if g else float("nan")
+        clock = g / dur[name] / 1e9 if dur[name] else float("nan")
+        rl = role(name)
+        opb = (c["SQ_INSTS_VALU"] * 64 / steps / bfly[rl]) if rl and bfly.get(rl) else None
+        short = name.split("(")[0].replace("void ", "")
+        md.append(f"| `{short}` | {len(disp[name]) / steps:.0f} | {c['SQ_WAVES'] / steps:.0f} | "
+                  f"{c['SQ_INSTS_VALU'] / steps:.3g} | {c['SQ_INSTS_LDS'] / steps:.3g} | "
+                  f"{c['SQ_LDS_BANK_CONFLICT'] / steps:.3g} | {g / steps:.3g} | {clock:.2f} | "
+                  f"{busy:.3f} | {'' if opb is None else f'{opb:.2f}'} |")
+    with open(os.path.join(ROOT, "profiles", f"{workload}_counters.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(f"wrote profiles/{workload}_counters.md")
+
+
 def summarize_batched(root, batched_calls, single_rounds):
     """profiles/c3_batched_kernels.md from a rocprofv3 --kernel-trace run of
     `bench.py --only-batched` under root/sb/: the batched calls' kernels (the
@@ -955,11 +1040,16 @@ def main():
                     help="run only the batched comparison (configuration 3) and print it")
     ap.add_argument("--summarize-batched", metavar="DIR",
                     help="write profiles/c3_batched_kernels.md from DIR/sb (rocprofv3 trace)")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write profiles/<workload>_counters.md from DIR/vc (rocprofv3 --pmc)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 CSV output in DIR")
     args = ap.parse_args()
     if args.calibration_copy:
         calibration_copy()
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload)
         return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, 20, 100, 3, args.workload)
