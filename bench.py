@@ -305,9 +305,11 @@ def bench_newton(p=2013265921, n=32, da=2049, N=4096, rhs=64, seed=8):
 def bench_vdm(p=1000000007, seed=9, reps=10):
     """Products mod a prime without roots of unity of the needed order
     (10^9 + 7: 2 is the only power of 2 dividing p - 1): Vandermonde
-    evaluation/interpolation on the matrix cores (pm_mul_vdm_u32) against
-    the three-prime CRT transforms (a one-product pm_mul_batched call, which
-    always takes the transforms), same operands, outputs compared."""
+    evaluation/interpolation on the matrix cores (pm_mul_vdm_u32) and
+    evaluation/interpolation at a geometric progression (pm_mul_geo_u32)
+    against the three-prime CRT transforms (a one-product pm_mul_batched
+    call, which always takes the transforms), same operands, outputs
+    compared."""
     import torch
     from paper_1905_04356_amd import binding as Bd
     from paper_1905_04356_amd import inputs as I
@@ -316,12 +318,14 @@ def bench_vdm(p=1000000007, seed=9, reps=10):
     stream = torch.cuda.current_stream()
     rows = []
     for (m, n, k, d) in [(32, 32, 32, 16), (32, 32, 32, 64), (128, 128, 128, 64),
-                         (32, 32, 32, 256)]:
+                         (32, 32, 32, 256), (128, 128, 128, 256), (32, 32, 32, 1024),
+                         (128, 128, 128, 1024)]:
         A = I.polymat_torch(seed, 0, I.TENSOR_A, p, d, m, n, dev)
         B = I.polymat_torch(seed, 0, I.TENSOR_B, p, d, n, k, dev)
         ws = polymat.Workspace(dev)
         outv = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=dev)
         outc = torch.empty_like(outv)
+        outg = torch.empty_like(outv)
         plan = Bd.pm_plan(p, m, n, k, d, 4)
 
         def timed(fn):
@@ -339,12 +343,15 @@ def bench_vdm(p=1000000007, seed=9, reps=10):
         t_v = timed(lambda: polymat.mul_vdm(p, A, B, out=outv, workspace=ws, stream=stream))
         t_c = timed(lambda: polymat.mul_batched(p, [A], [B], [outc], workspace=ws,
                                                 stream=stream))
+        t_g = timed(lambda: polymat.mul_geo(p, A, B, out=outg, workspace=ws, stream=stream))
         rows.append({"m": m, "n": n, "k": k, "d": d, "vandermonde_ms": t_v, "crt_ms": t_c,
+                     "geometric_ms": t_g,
                      "crt_primes": plan.num_primes, "crt_L": 1 << plan.log2_len,
-                     "outputs_equal": bool(torch.equal(outv, outc))})
-        del A, B, ws, outv, outc
+                     "outputs_equal": bool(torch.equal(outv, outc) and torch.equal(outg, outc))})
+        del A, B, ws, outv, outc, outg
     return {"workload": f"products mod {p} (no 2^k-th roots of unity for k > 1): Vandermonde "
-                        "evaluation on the matrix cores vs three-prime CRT", "runs": rows}
+                        "evaluation on the matrix cores and evaluation at a geometric "
+                        "progression vs three-prime CRT", "runs": rows}
 
 
 def bench_wrap(p=998244353, seed=10, reps=10):

@@ -76,7 +76,7 @@ typedef enum pm_status {
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 6
+#define PM_ABI_VERSION 7
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -237,6 +237,31 @@ pm_status pm_mul_vdm_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
                          const uint32_t* A, const uint32_t* B, uint32_t* C,
                          void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* Evaluation and interpolation at a geometric progression (Section 2,
+ * "Polynomial multiplication": with an element a of order at least N, both
+ * take O(M(N)) operations; "Polynomial matrix multiplication" uses them for
+ * general primes): A and B are evaluated at 1, a, ..., a^(N-1), N = 2d - 1,
+ * a the least primitive root of p, the m x n by n x k products are taken at
+ * each point, and C is interpolated back.  With C2(t) = t (t - 1) / 2 and
+ * i c = C2(i + c) - C2(i) - C2(c), each evaluation is a chirp transform: a
+ * middle product of the rows scaled by a^-C2(c) with the fixed polynomial
+ * sum a^C2(t) x^t; interpolation is (Q S) mod x^N with Q = prod (x - a^j)
+ * and the power series S = sum_i (v_i / Q'(a^i)) / (x - a^i), whose
+ * coefficients are another chirp transform.  The four polynomial products
+ * run on the transforms of pm_middle_* (modulo word-size NTT primes, since
+ * p need not have roots of unity of 2-power order); the tables (chirps,
+ * Q, 1/Q'(a^i)) are filled on the device per (p, d) in the table regions.
+ * Same layout, pointer, overlap and workspace rules and result as
+ * pm_mul_u32 (workspace size from pm_geo_workspace_bytes).  Requires p
+ * prime, 3 <= p < 2^31, 2d - 1 <= p - 1 and n < 4096 (PM_ERANGE / PM_EINVAL
+ * / PM_EUNSUPPORTED otherwise) and 2(2d - 1) - 1 <= 2^15.  Asynchronous on
+ * `stream`. */
+pm_status pm_geo_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                                 uint64_t* out);
+pm_status pm_mul_geo_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         const uint32_t* A, const uint32_t* B, uint32_t* C,
+                         void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* A batch of coefficient windows (pm_middle_* products): each product follows
  * the pm_middle_* rules for its own (m, n, k, da, db, lo, len) and pointers. */
 typedef struct pm_window_product {
@@ -376,7 +401,8 @@ pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count,
  * per kernel kind, the summed device time and the launch count.  Kinds
  * (index into the arrays): 0 forward transform, 1 pointwise products,
  * 2 inverse transform, 3 Chinese remaindering, 5 evaluation and
- * 6 interpolation by Vandermonde products; 4 is a whole batched call of
+ * 6 interpolation by Vandermonde products, 7 the row scalings of the
+ * geometric-progression products; 4 is a whole batched call of
  * more than two products, timed by an event pair around it (an eager one
  * also reports its phase kernels under 0-3; a replayed graph does not).
  * Launches inside a stream capture are not timed.  Returns PM_EDEVICE if

@@ -34,9 +34,10 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32",
            "pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
            "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
-           "pm_tune_info")
+           "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32")
 
-KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp")
+KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp",
+                "geo")
 
 
 class PmError(RuntimeError):
@@ -143,9 +144,11 @@ def lib():
     L.pm_mul_noalloc.argtypes = [u64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
     L.pm_tune_load.argtypes = [ctypes.c_char_p]
     L.pm_tune_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.pm_geo_workspace_bytes.argtypes = [u64, i32, i32, i32, i32, ctypes.POINTER(u64)]
+    L.pm_mul_geo_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
     for name in ("pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
                  "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
-                 "pm_tune_info"):
+                 "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
@@ -374,6 +377,10 @@ def pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
     return lib().pm_mul_vdm_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
 
 
+def pm_mul_geo_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
+    return lib().pm_mul_geo_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
+
+
 def tune_load(text: str | None) -> None:
     """Install a tuning table (JSON text); None re-reads the default file,
     "" removes the table (defaults).  Raises on an invalid table."""
@@ -389,3 +396,10 @@ def tune_info() -> tuple[int, int]:
     if st != PM_OK:
         raise PmError(st, "pm_tune_info")
     return e.value, s.value
+
+
+def pm_geo_workspace_bytes(p: int, m: int, n: int, k: int, d: int) -> int | None:
+    """Workspace of pm_mul_geo_u32, or None when the product is not eligible."""
+    out = ctypes.c_uint64(0)
+    st = lib().pm_geo_workspace_bytes(p, m, n, k, d, ctypes.byref(out))
+    return out.value if st == PM_OK else None

@@ -578,6 +578,166 @@ static pm_status vdm_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d
   return PM_OK;
 }
 
+// ---- evaluation at a geometric progression -------------------------------------
+
+namespace {
+
+// The four middle products of a geometric-progression product: the
+// evaluations of A and B (chirp transforms), the chirp transform of the
+// interpolation and the truncated product by Q.
+struct GeoPlans {
+  Plan a, b, i, q;
+  uint64_t off_ra, off_rb, off_ah, off_bh, off_ch, off_y, off_s, off_w, total;
+};
+
+int geo_plans(uint64_t p, int m, int n, int k, int d, GeoPlans* G) {
+  if (m < 1 || n < 1 || k < 1 || d < 1) return PM_EINVAL;
+  if (p < 3 || p >= (1ull << 31)) return PM_ERANGE;
+  if (!is_prime_u64(p)) return PM_EINVAL;
+  if (n >= 4096) return PM_EUNSUPPORTED;  // the pointwise epilogue's bound
+  const uint64_t N = 2ull * d - 1;
+  if (N > p - 1) return PM_EUNSUPPORTED;  // no element of order >= N
+  const int Ni = (int)N;
+  int st = make_slice_plan(p, m * n, 1, 1, d, Ni + d - 1, d - 1, Ni, 4, &G->a);
+  if (st != PM_OK) return st;
+  st = make_slice_plan(p, n * k, 1, 1, d, Ni + d - 1, d - 1, Ni, 4, &G->b);
+  if (st != PM_OK) return st;
+  st = make_slice_plan(p, m * k, 1, 1, Ni, 2 * Ni - 1, Ni - 1, Ni, 4, &G->i);
+  if (st != PM_OK) return st;
+  st = make_slice_plan(p, m * k, 1, 1, Ni, Ni + 1, 0, Ni, 4, &G->q);
+  if (st != PM_OK) return st;
+  const uint64_t mn = (uint64_t)m * n, nk = (uint64_t)n * k, mk = (uint64_t)m * k;
+  uint64_t off = 0;
+  G->off_ra = off; off = align_up(off + 4 * d * mn, 256);
+  G->off_rb = off; off = align_up(off + 4 * d * nk, 256);
+  G->off_ah = off; off = align_up(off + 4 * N * mn, 256);
+  G->off_bh = off; off = align_up(off + 4 * N * nk, 256);
+  G->off_ch = off; off = align_up(off + 4 * N * mk, 256);
+  G->off_y = off; off = align_up(off + 4 * N * mk, 256);
+  G->off_s = off; off = align_up(off + 4 * N * mk, 256);
+  G->off_w = off;
+  off += std::max(std::max(G->a.ws_bytes, G->b.ws_bytes), std::max(G->i.ws_bytes, G->q.ws_bytes));
+  G->total = align_up(off, 256);
+  return PM_OK;
+}
+
+pm_status geo_impl(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d, const uint32_t* A,
+                   const uint32_t* B, uint32_t* C, void* workspace, uint64_t workspace_bytes,
+                   void* stream) {
+  GeoPlans G;
+  int st = geo_plans(p, m, n, k, d, &G);
+  if (st != PM_OK) return (pm_status)st;
+  Plan P{};
+  P.m = m; P.n = n; P.k = k; P.d = d; P.da = d; P.db = d; P.lo = 0; P.nout = 2 * d - 1;
+  P.elem_bytes = 4;
+  st = check_operands(P, A, B, C);
+  if (st != PM_OK) return (pm_status)st;
+  st = check_workspace(workspace, workspace_bytes, G.total, A, 4ull * d * m * n, B,
+                       4ull * d * n * k, C, 4ull * P.nout * m * k);
+  if (st != PM_OK) return (pm_status)st;
+  hipStream_t s = (hipStream_t)stream;
+  GeoTables T;
+  st = prepare_geo(p, d, s, &T);
+  if (st != PM_OK) return (pm_status)st;
+  const Plan all[4] = {G.a, G.b, G.i, G.q};
+  st = prepare_plans(all, 4, s);
+  if (st != PM_OK) return (pm_status)st;
+  uint8_t* ws = (uint8_t*)workspace;
+  uint32_t* ra = (uint32_t*)(ws + G.off_ra);
+  uint32_t* rb = (uint32_t*)(ws + G.off_rb);
+  uint32_t* ah = (uint32_t*)(ws + G.off_ah);
+  uint32_t* bh = (uint32_t*)(ws + G.off_bh);
+  uint32_t* ch = (uint32_t*)(ws + G.off_ch);
+  uint32_t* y = (uint32_t*)(ws + G.off_y);
+  uint32_t* sv = (uint32_t*)(ws + G.off_s);
+  uint8_t* wp = ws + G.off_w;
+  const uint32_t N = T.N;
+  const uint64_t mn = (uint64_t)m * n, nk = (uint64_t)n * k, mk = (uint64_t)m * k;
+  // evaluations: rows of A scaled by a^-C2(c) and reversed, the chirp
+  // transform (coefficients d-1 .. d+N-2 of the product with a^C2(t)), the
+  // values scaled by a^-C2(i)
+  {
+    KernelTimer kt(K_GEO, s);
+    if (launch_geo_scale(A, ra, (uint32_t)d, mn, T.sneg, 1, p, s) != hipSuccess ||
+        launch_geo_scale(B, rb, (uint32_t)d, nk, T.sneg, 1, p, s) != hipSuccess)
+      return PM_EDEVICE;
+  }
+  st = run_product(G.a, ra, T.spos, ah, wp, s, true);
+  if (st != PM_OK) return (pm_status)st;
+  st = run_product(G.b, rb, T.spos, bh, wp, s, true);
+  if (st != PM_OK) return (pm_status)st;
+  {
+    KernelTimer kt(K_GEO, s);
+    if (launch_geo_scale(ah, ah, N, mn, T.sneg, 0, p, s) != hipSuccess ||
+        launch_geo_scale(bh, bh, N, nk, T.sneg, 0, p, s) != hipSuccess)
+      return PM_EDEVICE;
+  }
+  {
+    // one m x n by n x k product per point, no scaling
+    PointwiseLaunch pw;
+    memset(&pw, 0, sizeof pw);
+    const Knobs kn = base_knobs();
+    pw.m = m; pw.n = n; pw.k = k; pw.L = (int)N;
+    pw.small_lds = kn.pw_small_lds;
+    pw.pipe = kn.pw_pipe;
+    pw.ahat = ah; pw.bhat = bh; pw.chat = ch;
+    pw.pc[0].q = p;
+    pw.pc[0].linv = 1;
+    pw.pc[0].linv_p = (uint32_t)((1ull << 32) / p);
+    pw.pc[0].mu = ~0ull / p;
+    GemmLaunch c{};
+    gemm_consts(p, n, &c);
+    for (int t = 0; t < 7; ++t) pw.cs[0][t] = c.cs[t];
+    pw.bias[0] = c.bias;
+    pw.qninv[0] = c.qninv;
+    KernelTimer kt(K_POINTWISE, s);
+    const int ok = choose_pointwise(m, n, k, kn.pointwise) == 1 ? launch_pointwise_mfma(pw, 1, s)
+                                                                : launch_pointwise(pw, 1, s);
+    if (ok != hipSuccess) return PM_EDEVICE;
+  }
+  // interpolation: values scaled by a^(C2(i) - i) / Q'(a^i) and reversed,
+  // the chirp transform with a^-C2(t), scaled by -a^C2(k): the power series
+  // S mod x^N; then C = (Q S) mod x^N
+  {
+    KernelTimer kt(K_GEO, s);
+    if (launch_geo_scale(ch, y, N, mk, T.fc, 1, p, s) != hipSuccess) return PM_EDEVICE;
+  }
+  st = run_product(G.i, y, T.sneg, sv, wp, s, true);
+  if (st != PM_OK) return (pm_status)st;
+  {
+    KernelTimer kt(K_GEO, s);
+    if (launch_geo_scale(sv, sv, N, mk, T.nspos, 0, p, s) != hipSuccess) return PM_EDEVICE;
+  }
+  st = run_product(G.q, sv, T.q, C, wp, s, true);
+  return (pm_status)st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_geo_workspace_bytes(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                                 uint64_t* out) {
+  return (pm_status)guarded([&] {
+    if (!out) return (int)PM_EINVAL;
+    GeoPlans G;
+    const int st = geo_plans(p, m, n, k, d, &G);
+    if (st != PM_OK) return st;
+    *out = G.total;
+    return (int)PM_OK;
+  });
+}
+
+pm_status pm_mul_geo_u32(uint32_t p, int32_t m, int32_t n, int32_t k, int32_t d,
+                         const uint32_t* A, const uint32_t* B, uint32_t* C, void* workspace,
+                         uint64_t workspace_bytes, void* stream) {
+  return (pm_status)guarded([&] {
+    return (int)geo_impl(p, m, n, k, d, A, B, C, workspace, workspace_bytes, stream);
+  });
+}
+
+}  // extern "C"
+
 pm_status pm_middle_plan(uint64_t p, int32_t m, int32_t n, int32_t k, int32_t da, int32_t db,
                          int32_t lo, int32_t len, int32_t elem_bytes, pm_plan_info* out) {
   return (pm_status)guarded([&] {

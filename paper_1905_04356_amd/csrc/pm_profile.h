@@ -11,7 +11,7 @@ namespace pm {
 
 enum KernelKind {
   K_NTT_FWD = 0, K_POINTWISE = 1, K_NTT_INV = 2, K_CRT = 3, K_BATCHED = 4,
-  K_VDM_EVAL = 5, K_VDM_INTERP = 6
+  K_VDM_EVAL = 5, K_VDM_INTERP = 6, K_GEO = 7
 };
 
 bool profiling();

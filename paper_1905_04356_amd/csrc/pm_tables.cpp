@@ -20,7 +20,8 @@ namespace pm {
 namespace {
 
 // kind 0: twiddles (a = q, b = logL, c = pass structure: split, maxr);
-// kind 1: Vandermonde (a = p, b = d).
+// kind 1: Vandermonde (a = p, b = d); kind 2: geometric progression (a = p,
+// b = d).
 typedef std::tuple<int, uint32_t, int, uint64_t> Key;
 
 enum FillState {
@@ -289,6 +290,45 @@ int prepare_vdm(uint32_t p, int d, hipStream_t s, const uint32_t** V, const uint
     split(ptrs[0], &v, &w, &work);
     *V = v;
     *W = w;
+    return PM_OK;
+  } catch (const std::bad_alloc&) {
+    return PM_ENOMEM;
+  }
+}
+
+uint64_t geo_table_bytes(int d) {
+  const uint64_t N = 2ull * d - 1, T = 2 * N - 1;
+  return 2 * align_up(4 * T, 256) + 2 * align_up(4 * N, 256) + align_up(4 * (N + 1), 256);
+}
+
+int prepare_geo(uint32_t p, int d, hipStream_t s, GeoTables* out) {
+  try {
+    alloc_point();  // as in prepare_twiddles
+    const uint32_t N = 2u * (uint32_t)d - 1, T = 2 * N - 1;
+    if (p < 3 || (uint64_t)N > (uint64_t)p - 1) return PM_EUNSUPPORTED;
+    const uint32_t a = primitive_root(p);
+    if (!a) return PM_EUNSUPPORTED;
+    std::vector<Want> want{Want{Key(2, p, d, 0), geo_table_bytes(d)}};
+    auto split = [&](uint8_t* base, GeoTables* g) {
+      g->p = p; g->a = a; g->N = N; g->T = T;
+      uint64_t off = 0;
+      g->spos = (uint32_t*)(base + off); off += align_up(4ull * T, 256);
+      g->sneg = (uint32_t*)(base + off); off += align_up(4ull * T, 256);
+      g->nspos = (uint32_t*)(base + off); off += align_up(4ull * N, 256);
+      g->fc = (uint32_t*)(base + off); off += align_up(4ull * N, 256);
+      g->q = (uint32_t*)(base + off);
+    };
+    std::vector<uint8_t*> ptrs;
+    const int st = prepare(
+        want, s,
+        [&](const Key&, uint8_t* base) {
+          GeoTables g;
+          split(base, &g);
+          return launch_fill_geo(g, s);
+        },
+        &ptrs);
+    if (st != PM_OK) return st;
+    split(ptrs[0], out);
     return PM_OK;
   } catch (const std::bad_alloc&) {
     return PM_ENOMEM;

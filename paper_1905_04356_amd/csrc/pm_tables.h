@@ -50,6 +50,25 @@ uint32_t root_of_unity(uint32_t q, int logL);
 // back: prepared like the twiddle tables.
 int prepare_vdm(uint32_t p, int d, hipStream_t s, const uint32_t** V, const uint32_t** W);
 
+// Tables of the evaluation/interpolation at the geometric progression
+// a^0 .. a^(N-1) mod p (N = 2d - 1, a the least primitive root of p):
+// spos[t] = a^C2(t) and sneg[t] = a^-C2(t) for t < T = 2N - 1, with
+// C2(t) = t (t - 1) / 2; nspos[t] = -a^C2(t) and fc[t] = a^(C2(t) - t) /
+// Q'(a^t) for t < N; q: the N + 1 coefficients of Q(x) = prod_j (x - a^j).
+struct GeoTables {
+  uint32_t p, a, N, T;
+  uint32_t *spos, *sneg, *nspos, *fc, *q;
+};
+uint64_t geo_table_bytes(int d);
+// Prepared like the twiddle tables; PM_EUNSUPPORTED if p has no element of
+// order at least N (p - 1 < N).
+int prepare_geo(uint32_t p, int d, hipStream_t s, GeoTables* out);
+int launch_fill_geo(const GeoTables& g, hipStream_t s);
+// Y[r] = X[src] f[src] mod p row by row (src = r, or rows - 1 - r when
+// reverse), rows of E residues.
+int launch_geo_scale(const uint32_t* X, uint32_t* Y, uint32_t rows, uint64_t E,
+                     const uint32_t* f, int reverse, uint32_t p, hipStream_t s);
+
 // Table pools: the regions the caller registers (pm_tables_attach), and the
 // slice of the static scratch array that the no-allocation entry point keeps
 // its tables in.  A TablePool scope selects the pool of this thread's calls.

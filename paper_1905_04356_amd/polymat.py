@@ -244,6 +244,34 @@ def mul_vdm(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
     return out
 
 
+def mul_geo(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+            workspace: Workspace | None = None, stream=None) -> torch.Tensor:
+    """C = A B mod p by evaluation and interpolation at a geometric
+    progression (uint32, p prime below 2^31, 2d - 1 <= p - 1)."""
+    d, m, n = A.shape
+    d2, n2, k = B.shape
+    if d2 != d or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if A.dtype != torch.uint32 or B.dtype != torch.uint32:
+        raise TypeError("mul_geo takes torch.uint32 residues")
+    A = A.contiguous()
+    B = B.contiguous()
+    need = _b.pm_geo_workspace_bytes(p, m, n, k, d)
+    if need is None:
+        raise _b.PmError(_b.PM_EUNSUPPORTED, "pm_mul_geo_u32")
+    with _on_stream(stream, A, B):
+        if out is None:
+            out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
+        ws = (workspace or _workspace(A.device)).get(need)
+        N = 2 * d - 1
+        st = _with_tables(A.device, lambda: _b.pm_mul_geo_u32(
+            p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream)), 32 * N + (4 << 20))
+    if st != _b.PM_OK:
+        raise _b.PmError(st, "pm_mul_geo")
+    return out
+
+
 def mbasis_fits(p: int, m: int, n: int, sigma: int) -> bool:
     """Whether pm_mbasis_u32 takes this shape and modulus."""
     return 2 <= p < (1 << 31) and _b.pm_mbasis_workspace_bytes(1, m, n, sigma) is not None
