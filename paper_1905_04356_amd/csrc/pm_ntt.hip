@@ -65,14 +65,16 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   // about 2^lds_log residues of LDS per workgroup, at least one entry, no
   // more slots than entries
   const GlobalKnobs G = global_knobs();
-  int eb = (PP.split ? (batched ? G.batch_tile_log : kn.blk_tile_log) : G.lds_log) - a->blk_log;
+  const int tile_log = inverse && kn.blk_tile_log_inv ? kn.blk_tile_log_inv : kn.blk_tile_log;
+  const int blk_nt = inverse && kn.blk_nt_inv ? kn.blk_nt_inv : kn.blk_nt;
+  int eb = (PP.split ? (batched ? G.batch_tile_log : tile_log) : G.lds_log) - a->blk_log;
   if (eb < 0) eb = 0;
   while (eb > 0 && (1 << (eb - 1)) >= E) --eb;
   // A single product with few entries takes fewer entries per workgroup,
   // down to one, while its launch would have fewer than min_wg workgroups:
   // such transforms are latency-bound (a full-size register tile is kept).
   if (!batched && G.min_wg > 0) {
-    const int nt_log = kn.blk_nt == 512 ? 9 : 8;
+    const int nt_log = blk_nt == 512 ? 9 : 8;
     const bool full_reg = PP.split && kn.reg_tile && a->blk_log + eb == nt_log + 5;
     const long zb = PP.split ? 1L << PP.split : 1;
     while (eb > 0 && !full_reg && ((E + (1L << eb) - 1) >> eb) * zb < G.min_wg) --eb;
@@ -94,7 +96,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   a->blk_pitch = ((1 << eb) + 3) / 4 * 4 + G.blk_pad;
   // the register tile, for the threads that run the block step: kBatchNT in
   // the batched phase kernels, blk_nt in the single-product kernel
-  a->blk_nt = batched ? kBatchNT : kn.blk_nt;
+  a->blk_nt = batched ? kBatchNT : blk_nt;
   const int nt_log = a->blk_nt == 512 ? 9 : 8;
   a->reg_kind = kn.reg_tile ? reg_kind_of(*a, nt_log) : 0;
 }

@@ -50,6 +50,8 @@ struct Knobs {
   int pointwise;     // 1: int8-MFMA where the shape fits, 0: VALU
   int pw_small_lds;  // largest limb-plane footprint run with 256 threads (bytes)
   int pw_pipe;       // pipelined MFMA pointwise: -1 where it fits, 0 never, 1/2 force
+  int blk_nt_inv;    // inverse block step: threads (0: as blk_nt)
+  int blk_tile_log_inv;  // inverse block step: log2 residues per tile (0: as blk_tile_log)
 };
 
 // Choices that are not per product.

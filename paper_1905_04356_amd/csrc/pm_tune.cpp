@@ -66,6 +66,8 @@ Knobs env_knobs() {
   // share a CU; above, 512 threads wait for fewer load round trips each
   k.pw_small_lds = env_int("PM_TUNE_PW_SMALL_LDS", 44 * 1024, 0, 1 << 30);
   k.pw_pipe = env_int("PM_TUNE_PW_PIPE", -1, -1, 2);
+  k.blk_nt_inv = 0;
+  k.blk_tile_log_inv = 0;
   return k;
 }
 
@@ -244,7 +246,7 @@ const KnobDef kKnobs[] = {
     {"split", 0, 4},        {"maxr", 2, 4},        {"blk_nt", 256, 512},
     {"blk_tile_log", 11, 15}, {"colvec_fwd", 1, 4}, {"colvec_inv", 1, 4},
     {"reg_tile", 0, 1},     {"pointwise", 0, 1},   {"pw_small_lds", 0, 1 << 30},
-    {"pw_pipe", -1, 2},
+    {"pw_pipe", -1, 2},     {"blk_nt_inv", 0, 512}, {"blk_tile_log_inv", 0, 15},
 };
 const KnobDef kGlobals[] = {
     {"lds_log", 11, 15},          {"split_min_log", 2, 16},    {"blk_pad", 0, 64},
@@ -256,7 +258,8 @@ const KnobDef kGlobals[] = {
 
 int* knob_slot(Knobs& k, int i) {
   int* f[] = {&k.split, &k.maxr, &k.blk_nt, &k.blk_tile_log, &k.colvec_fwd, &k.colvec_inv,
-              &k.reg_tile, &k.pointwise, &k.pw_small_lds, &k.pw_pipe};
+              &k.reg_tile, &k.pointwise, &k.pw_small_lds, &k.pw_pipe, &k.blk_nt_inv,
+              &k.blk_tile_log_inv};
   return f[i];
 }
 int* global_slot(GlobalKnobs& g, int i) {
@@ -271,6 +274,8 @@ bool valid_knob(int i, int v) {
   const std::string n = kKnobs[i].name;
   if (n == "split") return v == 0 || v >= 2;
   if (n == "blk_nt") return v == 256 || v == 512;
+  if (n == "blk_nt_inv") return v == 0 || v == 256 || v == 512;
+  if (n == "blk_tile_log_inv") return v == 0 || v >= 11;
   if (n == "colvec_fwd" || n == "colvec_inv") return v == 1 || v == 2 || v == 4;
   return true;
 }

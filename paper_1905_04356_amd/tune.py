@@ -40,22 +40,28 @@ DEFAULT_OUT = os.path.join(HERE, "tune_table.json")
 P_LT30 = 998244353        # 119 2^23 + 1
 P_GE30 = 2013265921       # 15 2^27 + 1
 
-# Admissible values tried per knob (the defaults are among them).
-KNOB_VALUES = {
-    "split": [4, 3],
-    "maxr": [4, 3],
-    "blk_nt": [256, 512],
-    "blk_tile_log": [13, 12, 14],
-    "colvec_fwd": [4, 2],
-    "colvec_inv": [4, 2],
-    "reg_tile": [1, 0],
-    "pointwise": [1, 0],
-    "pw_small_lds": [45056, 0, 98304],
-    "pw_pipe": [-1, 0, 1, 2],
-}
+# Moves of the search: each sets one knob, or a pair that only makes sense
+# together (threads and tile size of a block step); the defaults are among
+# the values.
+MOVES = [
+    [{"split": 4}, {"split": 3}],
+    [{"maxr": 4}, {"maxr": 3}],
+    [{"blk_nt": 256, "blk_tile_log": 13}, {"blk_nt": 512, "blk_tile_log": 14},
+     {"blk_nt": 512, "blk_tile_log": 13}, {"blk_nt": 256, "blk_tile_log": 12},
+     {"blk_nt": 256, "blk_tile_log": 14}],
+    [{"blk_nt_inv": 0, "blk_tile_log_inv": 0}, {"blk_nt_inv": 512, "blk_tile_log_inv": 14},
+     {"blk_nt_inv": 512, "blk_tile_log_inv": 13}, {"blk_nt_inv": 256, "blk_tile_log_inv": 12},
+     {"blk_nt_inv": 256, "blk_tile_log_inv": 14}],
+    [{"colvec_fwd": 4}, {"colvec_fwd": 2}],
+    [{"colvec_inv": 4}, {"colvec_inv": 2}],
+    [{"reg_tile": 1}, {"reg_tile": 0}],
+    [{"pointwise": 1}, {"pointwise": 0}],
+    [{"pw_small_lds": 45056}, {"pw_small_lds": 0}, {"pw_small_lds": 98304}],
+    [{"pw_pipe": -1}, {"pw_pipe": 0}, {"pw_pipe": 1}, {"pw_pipe": 2}],
+]
 DEFAULTS = {"split": 4, "maxr": 4, "blk_nt": 256, "blk_tile_log": 13, "colvec_fwd": 4,
             "colvec_inv": 4, "reg_tile": 1, "pointwise": 1, "pw_small_lds": 45056,
-            "pw_pipe": -1}
+            "pw_pipe": -1, "blk_nt_inv": 0, "blk_tile_log_inv": 0}
 CLASS_NAME = {0: "direct_lt30", 1: "direct_ge30", 2: "crt"}
 
 
@@ -126,11 +132,11 @@ def tune_bucket(prod: Product, margin: float, passes: int, reps: int):
     tried = 1
     for _ in range(passes):
         improved = False
-        for name, values in KNOB_VALUES.items():
-            for v in values:
-                if v == knobs[name]:
+        for values in MOVES:
+            for move in values:
+                if all(knobs[k] == v for k, v in move.items()):
                     continue
-                cand = dict(knobs, **{name: v})
+                cand = dict(knobs, **move)
                 t = time_with(prod, {k: x for k, x in cand.items() if x != DEFAULTS[k]}, reps)
                 tried += 1
                 if t < best * (1 - margin):
@@ -160,7 +166,7 @@ def buckets(quick: bool):
         (P_LT30, 8, 8, 8, 256, torch.uint32),         # small product
         (I.seeded_prime_60(4), 32, 32, 32, 2048, torch.uint64),   # 60-bit, CRT
     ]
-    ds = [500, 2000] if quick else [300, 1500, 6000]
+    ds = [500, 2000] if quick else [100, 300, 700, 1500, 3000, 6000, 12000]
     for d in ds:
         for (m, k) in ((16, 16), (64, 64), (128, 64), (128, 128)):
             for n in (8, 32, 128):
@@ -168,7 +174,30 @@ def buckets(quick: bool):
     return out
 
 
-def tune_batch_globals(entries, margin, quick):
+def tune_min_wg(entries, margin):
+    """The global min_wg (fewest workgroups per transform launch before a
+    single product takes fewer entries per workgroup) on small products:
+    the sum of their median times per candidate value."""
+    shapes = [(P_LT30, 8, 8, 8, 256), (P_LT30, 16, 16, 16, 300), (P_LT30, 32, 32, 32, 500),
+              (P_LT30, 4, 8, 4, 100), (P_LT30, 128, 8, 64, 200), (P_GE30, 16, 8, 16, 900)]
+    prods = [Product(p, m, n, k, d) for (p, m, n, k, d) in shapes]
+
+    def total(glob):
+        B.tune_load(table_json(entries, glob))
+        return sum(pr.time_us() for pr in prods)
+
+    base = total({})
+    best, glob = base, {}
+    for v in (0, 256, 1024, 2048):
+        g = {"min_wg": v}
+        t = total(g)
+        if t < best * (1 - margin):
+            best, glob = t, g
+    del prods
+    return glob, best, base
+
+
+def tune_batch_globals(entries, margin, quick, glob0=None):
     """batch_pw_work and batch_tile_log on the batched workload (512
     products, batched shape rule, seed 3), with the entries found."""
     p, seed = P_LT30, 3
@@ -183,7 +212,7 @@ def tune_batch_globals(entries, margin, quick):
     ws = polymat.Workspace()
 
     def run(glob):
-        B.tune_load(table_json(entries, glob))
+        B.tune_load(table_json(entries, dict(glob0 or {}, **glob)))
         for _ in range(2):    # first call eager, second captures the graph
             polymat.mul_batched(p, As, Bs, outs, workspace=ws)
         torch.cuda.synchronize()
@@ -240,7 +269,10 @@ def main(argv=None):
             entries.append(e)
         del prod
         torch.cuda.empty_cache()
-    glob, t_b, t_b0 = tune_batch_globals(entries, args.margin, args.quick)
+    gmin, t_s, t_s0 = tune_min_wg(entries, args.margin)
+    say(f"[tune] min_wg {json.dumps(gmin)}: small products {t_s0:.1f} -> {t_s:.1f} us")
+    glob, t_b, t_b0 = tune_batch_globals(entries, args.margin, args.quick, gmin)
+    glob = dict(gmin, **glob)
     say(f"[tune] batched globals {json.dumps(glob)}: {t_b0:.2f} -> {t_b:.2f} ms")
     table = {"format": "pm-tune-1",
              "device": torch.cuda.get_device_name(0),
