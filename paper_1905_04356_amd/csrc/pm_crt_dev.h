@@ -17,43 +17,100 @@
 
 namespace pm {
 
-// Outputs idx = i0, i0 + step, ... below min(i1, count).
-template <typename TOut>
-__device__ __forceinline__ void crt_range(const CrtLaunch& a, uint64_t i0, uint64_t i1,
-                                          uint64_t step) {
+// Outputs idx = i0, i0 + step, ... below min(i1, count), for R primes known
+// at compile time: the constants are read once, before the loop, and the
+// loops over primes unroll.
+template <typename TOut, int R>
+__device__ __forceinline__ void crt_range_r(const CrtLaunch& a, uint64_t i0, uint64_t i1,
+                                            uint64_t step) {
   if (i1 > a.count) i1 = a.count;
+  uint32_t q[R], mu32[R], inv[R][R], invp[R][R];
+  uint64_t radix[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    q[i] = a.q[i];
+    mu32[i] = a.mu32[i];
+    radix[i] = a.radix_mod_p[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      inv[i][j] = a.inv[i][j];
+      invp[i][j] = a.inv_p[i][j];
+    }
+  }
+  const uint64_t p = a.p, mu_p = a.mu_p, pstride = a.prime_stride;
+  const double pinv = a.pinv;
   for (uint64_t idx = i0; idx < i1; idx += step) {
-    uint32_t y[kMaxPrimes];
-    for (int i = 0; i < a.r; ++i) {
-      const uint32_t qi = a.q[i];
-      uint32_t t = a.cq[a.prime_stride * i + idx];
+    uint32_t v[R], y[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = a.cq[pstride * i + idx];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      uint32_t t = v[i];
+#pragma unroll
       for (int j = 0; j < i; ++j) {
         // y_j < q_j < 2^31: Barrett with floor(2^32 / q_i) leaves [0, 2 q_i)
-        const uint32_t yj = reduce_once(y[j] - __umulhi(y[j], a.mu32[i]) * qi, qi);
-        t = sub_mod(t, yj, qi);
-        t = mul_shoup(t, a.inv[i][j], a.inv_p[i][j], qi);
+        const uint32_t yj = reduce_once(y[j] - __umulhi(y[j], mu32[i]) * q[i], q[i]);
+        t = sub_mod(t, yj, q[i]);
+        t = mul_shoup(t, inv[i][j], invp[i][j], q[i]);
       }
       y[i] = t;
     }
     uint64_t acc = 0;
-    if (a.p <= 0xFFFFFFFFull) {
+    if (p <= 0xFFFFFFFFull) {
       // y_i (prod_{j<i} q_j mod p) < 2^63: Barrett with floor((2^64-1)/p)
       // leaves [0, 3p)
-      for (int i = 0; i < a.r; ++i) {
-        const uint64_t x = (uint64_t)y[i] * a.radix_mod_p[i];
-        uint64_t r = x - __umul64hi(x, a.mu_p) * a.p;
-        if (r >= a.p) r -= a.p;
-        if (r >= a.p) r -= a.p;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const uint64_t x = (uint64_t)y[i] * radix[i];
+        uint64_t r = x - __umul64hi(x, mu_p) * p;
+        if (r >= p) r -= p;
+        if (r >= p) r -= p;
         acc += r;
-        if (acc >= a.p) acc -= a.p;
+        if (acc >= p) acc -= p;
       }
     } else {
-      for (int i = 0; i < a.r; ++i) {
-        acc += mulmod_u64_small(y[i], a.radix_mod_p[i], a.p, a.pinv);
-        if (acc >= a.p) acc -= a.p;
+      // S = sum_i y_i R_i with R_i = prod_{j<i} q_j mod p < 2^62 and
+      // y_i < 2^31 is below 8 2^93 = 2^96: accumulate it exactly in 96 bits
+      // (lo: 64, hi: 32), then reduce once.  S / p < r 2^31 <= 2^34 (each
+      // R_i < p), and S and 1/p carry relative rounding errors near 2^-53,
+      // so the double-precision quotient estimate is within one of the true
+      // quotient and the remainder computed mod 2^64 needs one signed
+      // correction.
+      uint64_t lo = 0;
+      uint32_t hi = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const uint64_t pl = (uint64_t)y[i] * (uint32_t)radix[i];          // < 2^63
+        const uint64_t ph = (uint64_t)y[i] * (uint32_t)(radix[i] >> 32);  // < 2^61
+        const uint64_t t = lo + pl;
+        hi += t < pl;
+        const uint64_t sh = ph << 32;
+        lo = t + sh;
+        hi += (uint32_t)(ph >> 32) + (lo < sh);
       }
+      const double sd = (double)hi * 18446744073709551616.0 + (double)lo;
+      const uint64_t qt = (uint64_t)(sd * pinv);
+      int64_t r = (int64_t)(lo - qt * p);  // exact mod 2^64, |r| < 2p < 2^63
+      if (r < 0) r += (int64_t)p;
+      if (r >= (int64_t)p) r -= (int64_t)p;
+      acc = (uint64_t)r;
     }
     ((TOut*)a.out)[idx] = (TOut)acc;
+  }
+}
+
+template <typename TOut>
+__device__ __forceinline__ void crt_range(const CrtLaunch& a, uint64_t i0, uint64_t i1,
+                                          uint64_t step) {
+  switch (a.r) {
+    case 1: crt_range_r<TOut, 1>(a, i0, i1, step); break;
+    case 2: crt_range_r<TOut, 2>(a, i0, i1, step); break;
+    case 3: crt_range_r<TOut, 3>(a, i0, i1, step); break;
+    case 4: crt_range_r<TOut, 4>(a, i0, i1, step); break;
+    case 5: crt_range_r<TOut, 5>(a, i0, i1, step); break;
+    case 6: crt_range_r<TOut, 6>(a, i0, i1, step); break;
+    case 7: crt_range_r<TOut, 7>(a, i0, i1, step); break;
+    default: crt_range_r<TOut, 8>(a, i0, i1, step); break;
   }
 }
 
