@@ -76,7 +76,7 @@ typedef enum pm_status {
 const char* pm_status_str(int status);
 
 /* ABI version of this header; bumped on incompatible change. */
-#define PM_ABI_VERSION 7
+#define PM_ABI_VERSION 8
 int pm_abi_version(void);
 
 /* Plan of one product, computed on the host without touching the device.
@@ -99,6 +99,10 @@ typedef struct pm_plan_info {
                                 0: on 2^log2_len points                     */
   int32_t tune_entry;        /* index of the tuning-table entry whose launch
                                 shapes the product uses; -1: the defaults   */
+  int32_t num_points;        /* points the product is evaluated at: L, or
+                                3L/4 when 2d - 1 <= 3L/4 (the roots of
+                                (x^(L/2) - 1)(x^(L/4) - w^(L/4)), enough for
+                                a product of fewer than 3L/4 coefficients) */
 } pm_plan_info;
 
 /* Tuning table (Section 2, "Polynomial matrix multiplication": thresholds

@@ -50,7 +50,8 @@ class pm_plan_info(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("log2_len", ctypes.c_int32),
                 ("num_primes", ctypes.c_int32), ("pointwise", ctypes.c_int32),
                 ("primes", ctypes.c_uint32 * 8), ("workspace_bytes", ctypes.c_uint64),
-                ("wrap_log2_len", ctypes.c_int32), ("tune_entry", ctypes.c_int32)]
+                ("wrap_log2_len", ctypes.c_int32), ("tune_entry", ctypes.c_int32),
+                ("num_points", ctypes.c_int32)]
 
 
 class pm_kernel_stats(ctypes.Structure):

@@ -52,6 +52,7 @@ static void fill_plan_info(const Plan& P, pm_plan_info* out) {
   for (int i = 0; i < P.r; ++i) out->primes[i] = P.q[i];
   out->workspace_bytes = P.ws_bytes;
   out->tune_entry = P.tune_entry;
+  out->num_points = P.npts;
 }
 
 extern "C" {
@@ -190,9 +191,10 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   fill_ntt_launch(&fb, P.logL, n * k, P.db, P.elem_bytes, false, batched, P.kn);
   fb.in = B;
   fb.out = bhat;
+  fa.keep = fb.keep = P.keep;
 
   PointwiseLaunch& pw = L->pw;
-  pw.m = m; pw.n = n; pw.k = k; pw.L = 1 << P.logL;
+  pw.m = m; pw.n = n; pw.k = k; pw.L = P.npts;
   pw.small_lds = P.kn.pw_small_lds;
   pw.pipe = P.kn.pw_pipe;
   pw.prime_stride = pstride;
@@ -219,6 +221,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   ic = fa;
   fill_ntt_launch(&ic, P.logL, m * k, P.nout, P.mode == 1 ? 4 : P.elem_bytes, true,
                   batched, P.kn);
+  ic.keep = P.keep;
   ic.out_lo = P.lo;
   ic.in = chat;
   ic.in_prime_stride = pstride;
@@ -320,6 +323,7 @@ int wrap_log_plans(const Plan& P, Plan* pc, Plan* pt) {
   const GlobalKnobs G = global_knobs();
   const int j = P.logL - 1;
   if (P.da != P.db || P.lo != 0 || j < G.wrap_min_log) return 0;
+  if (P.trunc && G.trunc34 == 2) return 0;  // the three-quarter transform instead
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t entries = (uint64_t)P.m * P.n + (uint64_t)P.n * P.k + (uint64_t)P.m * P.k;
   if (t < 1 || t > Lp / G.wrap_top_div || d > Lp ||
@@ -1051,7 +1055,7 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
         const uint32_t n0 = (items + kColChunk - 1) / kColChunk;
         add(0, BK_COL_FWD, op, q, n0, n0, (double)(items < kColChunk ? items : kColChunk) *
                                               a.col_vec * (1 << a.split), 0, 0);
-        add(1, BK_BLOCK_FWD, op, q, neb, neb << a.split,
+        add(1, BK_BLOCK_FWD, op, q, neb, neb * a.keep,
             (double)EB * (1u << a.blk_log) * (a.logL - a.split), block_lds_bytes(a), 0);
       } else {
         add(0, BK_FWD_LDS, op, q, neb, neb, (double)EB * L_ * (P.logL + 1), ntt_lds_bytes(a), 0);
@@ -1075,9 +1079,10 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
     uint32_t z = (uint32_t)(pw_work / mnk);
     if (pipe && z < (uint32_t)pipe_pts) z = (uint32_t)pipe_pts;
     if (z < 1) z = 1;
-    if (z > L_) z = L_;
+    const uint32_t npts = (uint32_t)P.npts;
+    if (z > npts) z = npts;
     if (z > 65535) z = 65535;
-    const uint32_t nt = (L_ + z - 1) / z;
+    const uint32_t nt = (npts + z - 1) / z;
     for (int q = 0; q < P.r; ++q)
       add(pipe == 2 ? 6 : 2, BK_PW, pipe == 1 ? 1 : 0, q, nt, nt, z * mnk, need, (uint16_t)z);
   }
@@ -1087,7 +1092,7 @@ void product_segments(uint32_t idx, const Plan& P, const ProductLaunches& L, boo
     const uint32_t neb = ((uint32_t)a.E + EB - 1) / EB;
     for (int q = 0; q < P.r; ++q) {
       if (a.split) {
-        add(3, BK_BLOCK_INV, 0, q, neb, neb << a.split,
+        add(3, BK_BLOCK_INV, 0, q, neb, neb * a.keep,
             (double)EB * (1u << a.blk_log) * (a.logL - a.split), block_lds_bytes(a), 0);
         const uint32_t items = col_items(a);
         const uint32_t n0 = (items + kColChunk - 1) / kColChunk;

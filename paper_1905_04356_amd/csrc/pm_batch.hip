@@ -79,8 +79,14 @@ __device__ __forceinline__ void block_v(const NttLaunch& a, int prime, int x, in
 template <typename TOut, int r>
 __device__ __forceinline__ void col_inv_cv(const NttLaunch& a, int prime, uint32_t i0,
                                            uint32_t i1) {
-  if (a.col_vec >= 2) col_inv_items<TOut, r, 2>(a, prime, i0, i1, kBatchNT);
-  else col_inv_items<TOut, r, 1>(a, prime, i0, i1, kBatchNT);
+  const bool tr = a.keep < (1 << r);  // three-quarter transform
+  if (a.col_vec >= 2) {
+    if (tr) col_inv_items<TOut, r, 2, true>(a, prime, i0, i1, kBatchNT);
+    else col_inv_items<TOut, r, 2>(a, prime, i0, i1, kBatchNT);
+  } else {
+    if (tr) col_inv_items<TOut, r, 1, true>(a, prime, i0, i1, kBatchNT);
+    else col_inv_items<TOut, r, 1>(a, prime, i0, i1, kBatchNT);
+  }
 }
 
 template <typename TOut>

@@ -36,6 +36,10 @@ struct NttLaunch {
                              // {4,4,3} (set for the thread count that runs the step)
   int lds_stride;            // 32-bit words between entries in LDS
   int blk_nt;                // single-product block step: threads (256 or 512)
+  int keep;                  // split transforms: position blocks transformed, 2^split,
+                             // or 3 2^split / 4 for a three-quarter transform (the
+                             // column pass then writes, and its inverse reads,
+                             // only the rows of those blocks)
   uint64_t in_prime_stride;  // elements between primes' input buffers
   uint64_t out_prime_stride; // elements between primes' output buffers
   const void* in;
@@ -44,7 +48,8 @@ struct NttLaunch {
 };
 
 // Pointwise products: for every point t and prime, Chat_t = L^{-1} Ahat_t Bhat_t
-// (m x n times n x k), all point-major u32.
+// (m x n times n x k), all point-major u32, at the first L points (all of
+// them, or 3/4 of them for a three-quarter transform).
 struct PointwiseLaunch {
   int m, n, k, L;
   int small_lds;             // limb planes up to this many bytes: 256 threads

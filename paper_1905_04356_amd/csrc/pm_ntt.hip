@@ -59,6 +59,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
     a->stride_log[i] = i < PP.npass ? PP.stride_log[i] : 0;
     a->tw_off[i] = i < PP.npass ? PP.tw_off[i] : 0;
   }
+  a->keep = PP.split ? 1 << PP.split : 1;
   a->nin = nin;
   a->out_lo = 0;
   a->E = E;
@@ -160,7 +161,7 @@ static int launch_reg(const NttLaunch& a, int nprimes, int zb, hipStream_t s, si
 
 template <bool DIF>
 static int launch_block(const NttLaunch& a, int nprimes, hipStream_t s) {
-  const int zb = 1 << a.split;
+  const int zb = a.keep;
   const size_t lds = block_lds_bytes(a);
   if (a.reg_kind)
     return a.blk_nt == 256 ? launch_reg<DIF, 256>(a, nprimes, zb, s, lds)

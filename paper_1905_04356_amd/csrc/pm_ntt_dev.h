@@ -592,7 +592,9 @@ __device__ __forceinline__ void block_tile_reg_kind(const NttLaunch& a, int prim
 // First forward pass of a split transform, r stages at stride S = L / 2^r,
 // items [it0, it1) with stride `step`: item (j, g) reads, for the CV entries
 // e = g CV .. g CV + CV - 1, the rows j + u S below nin of the
-// coefficient-major input and writes all 2^r rows of the point-major buffer.
+// coefficient-major input and writes rows j + u S, u < keep, of the
+// point-major buffer (keep = 2^r, or 3 2^r / 4 for a three-quarter
+// transform: the last quarter of the rows feeds only the points dropped).
 // ZHI (nin <= L/2): rows u >= 2^(r-1) are zero padding, not read, and the
 // first stage reduces to products by the twiddles.  The entries share the
 // twiddles.
@@ -607,6 +609,7 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
   const TIn* in = (const TIn*)a.in + a.in_prime_stride * prime;
   uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * prime;
   const Tw* tw = P.tw_fwd + a.tw_off[0];
+  const int keep = a.keep;
   for (uint32_t it = it0; it < it1; it += step) {
     const uint32_t j = it / G, e = (it - j * G) * CV;
     uint32_t x[CV][R];
@@ -629,6 +632,7 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
     for (int c = 0; c < CV; ++c) butterflies<r, true, ZHI>(x[c], t, q);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
+      if (u >= 3 * R / 4 && u >= keep) break;
       Vec<uint32_t, CV> y;
 #pragma unroll
       for (int c = 0; c < CV; ++c) y.v[c] = x[c][u];
@@ -649,14 +653,64 @@ __device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint
   else col_fwd_items<TIn, REDUCE, r, 1>(a, prime, it0, it1, step);
 }
 
+// Inverse of a three-quarter first pass (r >= 2 stages, R = 2^r, Q = R/4):
+// the forward pass kept its outputs u < 3Q, and the coefficients
+// X_u = c_{j+uS} are zero for u >= 3Q (the product has fewer than 3L/4).
+// The stages below distance R/4 are undone on each kept quarter and the one
+// at distance R/4 on the first half; then, with c = j + uS (u < Q) and
+// I = w^(L/4),
+//   x[u] = (X_u + X_{u+2Q}) / 2,  x[u+Q] = X_{u+Q} / 2,
+//   x[u+2Q] = w^c (X_u - X_{u+2Q} + I X_{u+Q}) / 4,
+// so X_{u+Q} = 2 x[u+Q] and X_u, X_{u+2Q} = x[u] +- (2 w^-c x[u+2Q] - I x[u+Q]),
+// w^-c being the twiddle of the top stage.  (The input rows carry the factor
+// 1/R that the full inverse pass cancels, so the results are the
+// coefficients themselves, as there.)
+template <int r>
+__device__ __forceinline__ void butterflies_inv34(uint32_t* x, const Tw* t, uint32_t q,
+                                                  uint32_t i4, uint32_t i4p) {
+  constexpr int R = 1 << r, H = R / 2, Q = R / 4;
+  const uint32_t nq = opaque_neg(q);
+#pragma unroll
+  for (int v = 0; v < r - 2; ++v) {
+#pragma unroll
+    for (int u = 0; u < 3 * Q; ++u) {
+      if (u & (1 << v)) continue;
+      const int u2 = u | (1 << v);
+      const Tw tt = t[(1 << v) - 1 + (u & ((1 << v) - 1))];
+      const uint32_t a0 = x[u], b0 = mul_shoup_nq(x[u2], tt.w, tt.wp, q, nq);
+      x[u] = add_mod(a0, b0, q);
+      x[u2] = sub_mod(a0, b0, q);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Q; ++u) {
+    const Tw tt = t[Q - 1 + u];
+    const uint32_t a0 = x[u], b0 = mul_shoup_nq(x[u + Q], tt.w, tt.wp, q, nq);
+    x[u] = add_mod(a0, b0, q);
+    x[u + Q] = sub_mod(a0, b0, q);
+  }
+#pragma unroll
+  for (int u = 0; u < Q; ++u) {
+    const Tw tt = t[H - 1 + u];
+    const uint32_t g = mul_shoup_nq(x[u + H], tt.w, tt.wp, q, nq);
+    const uint32_t ib = mul_shoup_nq(x[u + Q], i4, i4p, q, nq);
+    const uint32_t s = sub_mod(add_mod(g, g, q), ib, q);
+    const uint32_t a0 = x[u];
+    x[u] = add_mod(a0, s, q);
+    x[u + H] = sub_mod(a0, s, q);
+    x[u + Q] = add_mod(x[u + Q], x[u + Q], q);
+  }
+}
+
 // Last inverse pass of a split transform: item (j, g) reads rows j + u S of
 // the point-major buffer for CV consecutive entries and writes coefficients
 // out_lo .. out_lo + nin - 1 to rows 0 .. nin - 1 of the coefficient-major
-// output.
-template <typename TOut, int r, int CV>
+// output.  TR: a three-quarter transform (rows u < 3 2^r / 4 only).
+template <typename TOut, int r, int CV, bool TR = false>
 __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uint32_t it0,
                                               uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
+  constexpr int KEEP = TR ? 3 * R / 4 : R;
   const PrimeConst& P = a.pc[prime];
   const uint32_t S = 1u << (a.logL - r);
   const uint32_t E = (uint32_t)a.E, G = E / CV;
@@ -667,7 +721,7 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
     const uint32_t j = it / G, e = (it - j * G) * CV;
     uint32_t x[CV][R];
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
+    for (int u = 0; u < KEEP; ++u) {
       const Vec<uint32_t, CV> v = *(const Vec<uint32_t, CV>*)(in + (size_t)(j + u * S) * E + e);
 #pragma unroll
       for (int c = 0; c < CV; ++c) x[c][u] = v.v[c];
@@ -676,9 +730,12 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
 #pragma unroll
     for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
 #pragma unroll
-    for (int c = 0; c < CV; ++c) butterflies<r, false, false>(x[c], t, P.q);
+    for (int c = 0; c < CV; ++c) {
+      if (TR) butterflies_inv34<r>(x[c], t, P.q, P.i4, P.i4p);
+      else butterflies<r, false, false>(x[c], t, P.q);
+    }
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
+    for (int u = 0; u < KEEP; ++u) {
       const uint32_t row = j + u * S - (uint32_t)a.out_lo;  // wraps above nin below out_lo
       if (row < (uint32_t)a.nin) {
         Vec<TOut, CV> y;
@@ -690,12 +747,19 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
   }
 }
 
+template <typename TOut, int r, bool TR>
+__device__ __forceinline__ void col_inv_tile_t(const NttLaunch& a, int prime, uint32_t it0,
+                                               uint32_t it1, uint32_t step) {
+  if (a.col_vec == 4) col_inv_items<TOut, r, 4, TR>(a, prime, it0, it1, step);
+  else if (a.col_vec == 2) col_inv_items<TOut, r, 2, TR>(a, prime, it0, it1, step);
+  else col_inv_items<TOut, r, 1, TR>(a, prime, it0, it1, step);
+}
+
 template <typename TOut, int r>
 __device__ __forceinline__ void col_inv_tile(const NttLaunch& a, int prime, uint32_t it0,
                                              uint32_t it1, uint32_t step) {
-  if (a.col_vec == 4) col_inv_items<TOut, r, 4>(a, prime, it0, it1, step);
-  else if (a.col_vec == 2) col_inv_items<TOut, r, 2>(a, prime, it0, it1, step);
-  else col_inv_items<TOut, r, 1>(a, prime, it0, it1, step);
+  if (a.keep < (1 << r)) col_inv_tile_t<TOut, r, true>(a, prime, it0, it1, step);
+  else col_inv_tile_t<TOut, r, false>(a, prime, it0, it1, step);
 }
 
 }  // namespace pm

@@ -232,10 +232,22 @@ static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int l
   const GlobalKnobs& G = global_knobs();
   if (P.kn.split < 2 || logL < G.split_min_log || P.kn.split >= logL) P.kn.split = 0;
   P.pointwise = choose_pointwise(m, n, k, P.kn.pointwise);
+  // Three-quarter transforms (split transforms of whole products whose
+  // da + db - 1 coefficients fit in 3L/4 points; global knob trunc34).
+  P.trunc = 0;
+  P.npts = (int)L;
+  P.keep = P.kn.split ? 1 << P.kn.split : 1;
+  if (G.trunc34 && force_log < 0 && lo == 0 && (uint64_t)nout == (uint64_t)da + db - 1 &&
+      P.kn.split >= 2 && 4 * need <= 3 * L) {
+    P.trunc = 1;
+    P.npts = (int)(3 * L / 4);
+    P.keep = 3 << (P.kn.split - 2);
+  }
+  const uint64_t np = (uint64_t)P.npts;
   uint64_t off = 0;
-  P.off_ahat = off; off = align_up(off + 4 * L * mn, 256);
-  P.off_bhat = off; off = align_up(off + 4 * L * nk, 256);
-  P.off_chat = off; off = align_up(off + 4 * L * mk, 256);
+  P.off_ahat = off; off = align_up(off + 4 * np * mn, 256);
+  P.off_bhat = off; off = align_up(off + 4 * np * nk, 256);
+  P.off_chat = off; off = align_up(off + 4 * np * mk, 256);
   P.prime_stride = off;
   P.off_cq = P.prime_stride * (uint64_t)P.r;
   P.ws_bytes = P.off_cq;

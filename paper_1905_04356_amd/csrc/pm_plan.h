@@ -70,6 +70,8 @@ struct GlobalKnobs {
   int vdm_max_d;         // CRT-mode u32 products with d <= this go through Vandermonde
   int min_wg;            // single-product transforms: fewer entries per workgroup
                          // while a launch has fewer workgroups than this (0: off)
+  int trunc34;           // three-quarter transforms: 0 off, 1 where the wrapped form
+                         // does not apply, 2 also in place of the wrapped form
 };
 
 // Prime classes of the tuning table: direct mode with q < 2^30, direct mode
@@ -91,6 +93,7 @@ PassPlan make_pass_plan(int logL, int split, int maxr);
 struct PrimeConst {
   uint32_t q;
   uint32_t linv, linv_p;   // L^{-1} mod q and its Shoup companion
+  uint32_t i4, i4p;        // w^(L/4) (w the forward L-th root) and its companion
   uint32_t pad;
   uint64_t mu;             // floor((2^64-1)/q) for Barrett reduction
   const Tw* tw_fwd;        // device: forward tables (PassPlan order)
@@ -105,6 +108,13 @@ struct Plan {
   int pointwise;         // 0 VALU, 1 MFMA
   Knobs kn;              // launch shapes (tuning table or defaults)
   int tune_entry;        // tuning-table entry of kn, -1 for the defaults
+  // Three-quarter transforms: a whole product with 2d - 1 <= 3L/4 needs only
+  // the evaluations at the roots of (x^(L/2) - 1)(x^(L/4) - w^(L/4)), the
+  // first 3L/4 points of the bit-reversed order; the column pass drops the
+  // rest and the last inverse pass solves for the coefficients from them.
+  int trunc;             // 1: three-quarter transform
+  int npts;              // evaluation points: L, or 3L/4
+  int keep;              // column-pass rows (and position blocks) kept: 2^split or 3/4 of it
   int m, n, k, d;
   // coefficient counts of A and B, and the window [lo, lo + nout) of the
   // product's coefficients that is computed (full product: d, d, 0, 2d-1)

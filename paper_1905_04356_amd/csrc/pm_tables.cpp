@@ -220,6 +220,10 @@ void prime_const_host(uint32_t q, int logL, PrimeConst* out) {
   out->linv = (uint32_t)powmod_u64(L % q, q - 2, q);
   out->linv_p = shoup_of(out->linv, q);
   out->mu = ~0ull / q;
+  if (logL >= 2) {
+    out->i4 = (uint32_t)powmod_u64(root_of_unity(q, logL), L / 4, q);
+    out->i4p = shoup_of(out->i4, q);
+  }
 }
 
 int prepare_twiddles(const TwKey* keys, int n, hipStream_t s) {

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(B.EXPORTS)
-    assert L.pm_abi_version() == 7
+    assert L.pm_abi_version() == 8
     assert B.status_str(B.PM_EWORKSPACE).startswith("PM_EWORKSPACE")
 
 

@@ -1,0 +1,168 @@
+"""Three-quarter transforms: whole products with L/2 < 2d - 1 <= 3L/4 are
+evaluated only at the roots of (x^(L/2) - 1)(x^(L/4) - w^(L/4)), the first
+3L/4 points of the bit-reversed order, and the last inverse pass solves for
+the coefficients from those.  Every coefficient is compared with the oracle
+at the edges of the band (2d - 1 = L/2 + 1 and 3L/4 - 1) and just above it,
+for column passes of 2, 3 and 4 stages, direct and CRT moduli (32- and
+64-bit), odd entry counts, single and batched calls, evaluations made at
+full length consumed by three-quarter products, and in place of the wrapped
+form."""
+from __future__ import annotations
+
+import json
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1905_04356_amd import binding as Bd  # noqa: E402
+from paper_1905_04356_amd import inputs as I  # noqa: E402
+from paper_1905_04356_amd import polymat  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+P30 = 998244353
+P31 = 2013265921
+P32 = 4294967291                  # 2^32 - 5: no 2-power roots, CRT
+P60 = 1152921504606846883         # 60-bit, CRT
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _restore_table():
+    yield
+    torch.cuda.synchronize()
+    Bd.tune_load(None)
+
+
+def load(split, maxr=4, **glob):
+    g = {"split_min_log": 8}
+    g.update(glob)
+    Bd.tune_load(json.dumps({"format": "pm-tune-1", "global": g,
+                             "entries": [{"knobs": {"split": split, "maxr": maxr}}]}))
+
+
+def operands(p, m, n, k, d, dtype, seed):
+    A = I.polymat(seed, 0, I.TENSOR_A, p, d, m, n, dtype)
+    B = I.polymat(seed, 0, I.TENSOR_B, p, d, n, k, dtype)
+    return A, B
+
+
+def edge_degrees(logL):
+    L = 1 << logL
+    return [L // 4 + 1,        # 2d - 1 = L/2 + 1: the band's first length
+            3 * L // 8,        # 2d - 1 = 3L/4 - 1: its last
+            3 * L // 8 + 1]    # 2d - 1 = 3L/4 + 1: L points again
+
+
+CASES = [  # (p, m, n, k, logL, dtype, split, maxr)
+    (P31, 4, 4, 4, 9, np.uint32, 2, 4),
+    (P30, 3, 5, 7, 10, np.uint32, 3, 3),
+    (P31, 8, 8, 4, 11, np.uint32, 4, 4),
+    (P30, 5, 2, 3, 12, np.uint32, 2, 2),
+    (P31, 16, 8, 16, 13, np.uint32, 4, 3),
+    (P32, 4, 6, 2, 10, np.uint32, 3, 4),
+    (P60, 4, 4, 4, 11, np.uint64, 4, 4),
+    (P60, 3, 3, 5, 9, np.uint64, 2, 3),
+]
+
+
+def check(C, ref, tag):
+    got = C.cpu().numpy().astype(np.uint64)
+    bad = np.argwhere(got != ref)
+    assert bad.size == 0, f"{tag}: {len(bad)} mismatches, first at {bad[:3].tolist()}"
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_band_edges_single_and_batched_equal_the_oracle(ci):
+    p, m, n, k, logL, dt, split, maxr = CASES[ci]
+    L = 1 << logL
+    load(split, maxr)
+    eb = 4 if dt == np.uint32 else 8
+    As, Bs, refs = [], [], []
+    for i, d in enumerate(edge_degrees(logL)):
+        info = Bd.pm_plan(p, m, n, k, d, eb)
+        want = 3 * L // 4 if 4 * (2 * d - 1) <= 3 * L else L
+        assert (1 << info.log2_len, info.num_points) == (L, want), d
+        say(f"[trunc] case {ci} p={p} {m}x{n}x{k} d={d} L={L} split={split} pts={want}")
+        A, B = operands(p, m, n, k, d, dt, seed=700 + 10 * ci + i)
+        ref = O.polymatmul(p, A, B)
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = polymat.mul(p, tA, tB)
+        torch.cuda.synchronize()
+        check(C, ref, f"single d={d}")
+        As.append(tA)
+        Bs.append(tB)
+        refs.append(ref)
+    outs = polymat.mul_batched(p, As, Bs)
+    torch.cuda.synchronize()
+    for C, ref, d in zip(outs, refs, edge_degrees(logL)):
+        check(C, ref, f"batched d={d}")
+
+
+def test_full_length_evaluations_feed_three_quarter_products():
+    """Evaluations are always made at all L points; a three-quarter product
+    reads the first 3L/4 of them."""
+    p, m, n, k, d = P31, 8, 16, 4, 1400          # 2d - 1 = 2799 <= 3072
+    load(4)
+    assert Bd.pm_plan(p, m, n, k, d, 4).num_points == 3072
+    A, B = operands(p, m, n, k, d, np.uint32, seed=760)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = O.polymatmul(p, A, B)
+    Ae = polymat.evaluate(p, tA, 0)
+    Be = polymat.evaluate(p, tB, 1)
+    torch.cuda.synchronize()
+    say("[trunc] evaluations given: A, B, both")
+    for ae, be in ((Ae, None), (None, Be), (Ae, Be)):
+        (C,) = polymat.mul_batched(p, [tA], [tB], A_evals=[ae], B_evals=[be])
+        torch.cuda.synchronize()
+        check(C, ref, f"evals {ae is not None} {be is not None}")
+
+
+@pytest.mark.parametrize("p,m,n,k,d", [
+    (P30, 4, 4, 4, 520),        # 2d - 1 = 2^10 + 15
+    (P31, 3, 5, 2, 1100),       # 2^11 + 151
+    (P60, 2, 3, 2, 600),        # 2^10 + 175, CRT
+])
+def test_in_place_of_the_wrapped_form(p, m, n, k, d):
+    """With the knob at 2, sizes the wrapped form would take (size bound
+    lowered) run as three-quarter transforms, single and batched."""
+    dt = np.uint64 if p > 0xFFFFFFFF else np.uint32
+    eb = 8 if dt == np.uint64 else 4
+    load(4, wrap_min_work_log=0)
+    assert Bd.pm_plan(p, m, n, k, d, eb).wrap_log2_len > 0
+    load(4, wrap_min_work_log=0, trunc34=2)
+    info = Bd.pm_plan(p, m, n, k, d, eb)
+    assert info.wrap_log2_len == 0 and info.num_points == 3 << (info.log2_len - 2)
+    say(f"[trunc] wrap band p={p} {m}x{n}x{k} d={d}")
+    A, B = operands(p, m, n, k, d, dt, seed=780 + d)
+    ref = O.polymatmul(p, A, B)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = polymat.mul(p, tA, tB)
+    (Cb,) = polymat.mul_batched(p, [tA], [tB])
+    torch.cuda.synchronize()
+    check(C, ref, "single")
+    check(Cb, ref, "batched")
+
+
+def test_knob_off_gives_the_same_products():
+    """trunc34 = 0 (all L points) and the default give equal results."""
+    p, m, n, k, d = P30, 16, 16, 16, 1500
+    A, B = operands(p, m, n, k, d, np.uint32, seed=790)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    load(4, trunc34=0)
+    assert Bd.pm_plan(p, m, n, k, d, 4).num_points == 4096
+    C0 = polymat.mul(p, tA, tB)
+    load(4)
+    assert Bd.pm_plan(p, m, n, k, d, 4).num_points == 3072
+    C1 = polymat.mul(p, tA, tB)
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1)
+    check(C1, O.polymatmul(p, A, B), "default")

@@ -86,6 +86,36 @@ def test_global_knobs_move_the_wrapped_length_rule():
     assert B.pm_plan(P30, m, n, k, d, 4).wrap_log2_len == 0   # 151 > 2048 / 64
 
 
+def test_three_quarter_transforms_are_planned_for_whole_products_in_the_band():
+    """Whole products with L/2 < 2d - 1 <= 3L/4 on split transforms take 3L/4
+    points (the workspace shrinks with them); 2d - 1 above the band, unsplit
+    lengths, coefficient windows and the knob set to 0 keep L points; with
+    the knob at 2 the three-quarter transform replaces the wrapped form."""
+    B.tune_load("")
+    for d, L, pts in [(1025, 4096, 3072), (1536, 4096, 3072), (1537, 4096, 4096),
+                      (2049, 8192, 6144), (3072, 8192, 6144), (4096, 8192, 8192)]:
+        info = B.pm_plan(P31, 16, 16, 8, d, 4)
+        assert (1 << info.log2_len, info.num_points) == (L, pts), d
+    full = B.pm_plan(P31, 16, 16, 8, 1500, 4)
+    B.tune_load(table(glob={"trunc34": 0}))
+    off = B.pm_plan(P31, 16, 16, 8, 1500, 4)
+    assert off.num_points == 4096 and full.num_points == 3072
+    assert 3 * off.workspace_bytes == 4 * full.workspace_bytes
+    # unsplit transforms: no
+    B.tune_load(table([{"knobs": {"split": 0}}]))
+    assert B.pm_plan(P31, 16, 16, 8, 1500, 4).num_points == 4096
+    # CRT moduli too (every prime's transform)
+    B.tune_load("")
+    crt = B.pm_plan((1 << 61) - 1, 4, 4, 4, 1500, 8)
+    assert crt.mode == 1 and crt.num_points == 3072
+    # the wrapped form keeps precedence unless the knob says 2
+    B.tune_load(table(glob={"wrap_min_work_log": 0}))
+    assert B.pm_plan(P30, 8, 8, 8, 1100, 4).wrap_log2_len == 11
+    B.tune_load(table(glob={"wrap_min_work_log": 0, "trunc34": 2}))
+    w = B.pm_plan(P30, 8, 8, 8, 1100, 4)
+    assert w.wrap_log2_len == 0 and w.num_points == 3072
+
+
 @pytest.mark.parametrize("bad", [
     "{",                                                             # not JSON
     "[]",                                                            # not an object
@@ -99,6 +129,7 @@ def test_global_knobs_move_the_wrapped_length_rule():
     table([{"knobs": {"maxr": 3.5}}]),                               # not an integer
     table(glob={"wrap_top_div": 0}),                                 # bad global
     table(glob={"nope": 1}),
+    table(glob={"trunc34": 3}),
     table([{"knobs": {}}]) + "x",                                    # trailing text
 ])
 def test_invalid_tables_are_rejected_and_the_current_one_stays(bad):
