@@ -314,8 +314,17 @@ int vdm_max_d() { return global_knobs().vdm_max_d; }
 // 2^12 + 903 0.94; at 2^11 + 151, where (mn + nk + mk) 2^j = 2^24, 1.03; small
 // shapes and tops near 2^(j-1) 1.0-2.3).  The bounds are global knobs
 // (wrap_min_log, default 10, the least j; wrap_top_div, 4; wrap_min_work_log,
-// 25).  run_wrapped returns 1 when the product was launched this way, 0 when
-// it does not apply, or a pm_status.
+// 25).  Where the product also fits a three-quarter transform (3L/4 points,
+// one product, no correction), that is faster from a top of about 2^j / 8
+// for L <= 2^13 (L = 2^11..2^13, wrapped time over three-quarter time: at
+// t = 0.09 2^j 0.89-0.94 for 128x128x64, 1.01-1.05 for 64x64x{32,64}; at
+// 0.16 2^j 1.04-1.09 and 1.15-1.21); for L >= 2^14 the two halves of the wrapped form run on
+// transforms of half the length, whose cost per point is lower, and it stays
+// ahead over the whole band (0.92-0.99 of the three-quarter time at
+// t = 0.24 2^j for L = 2^14, 0.75 for 2^15).  Hence the top bound
+// 2^j / wrap_top_div_tr (8) for log2 L <= wrap_tr_max_log (13).
+// run_wrapped returns 1 when the product was launched this way, 0 when it
+// does not apply, or a pm_status.
 
 // j when a whole product of plan P takes the wrapped form on 2^j points
 // (with P's own workspace), else 0; the cyclic and top plans through pc, pt.
@@ -326,7 +335,9 @@ int wrap_log_plans(const Plan& P, Plan* pc, Plan* pt) {
   if (P.trunc && G.trunc34 == 2) return 0;  // the three-quarter transform instead
   const int d = P.d, Lp = 1 << j, t = 2 * d - 1 - Lp;
   const uint64_t entries = (uint64_t)P.m * P.n + (uint64_t)P.n * P.k + (uint64_t)P.m * P.k;
-  if (t < 1 || t > Lp / G.wrap_top_div || d > Lp ||
+  const int div =
+      P.trunc && P.logL <= G.wrap_tr_max_log ? G.wrap_top_div_tr : G.wrap_top_div;
+  if (t < 1 || t > Lp / div || d > Lp ||
       (entries << j) < (1ull << G.wrap_min_work_log))
     return 0;
   if (make_cyclic_plan(P.p, P.m, P.n, P.k, d, j, P.elem_bytes, pc) != PM_OK) return 0;

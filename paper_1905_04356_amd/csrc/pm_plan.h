@@ -70,8 +70,11 @@ struct GlobalKnobs {
   int vdm_max_d;         // CRT-mode u32 products with d <= this go through Vandermonde
   int min_wg;            // single-product transforms: fewer entries per workgroup
                          // while a launch has fewer workgroups than this (0: off)
-  int trunc34;           // three-quarter transforms: 0 off, 1 where the wrapped form
-                         // does not apply, 2 also in place of the wrapped form
+  int trunc34;           // three-quarter transforms: 0 off, 1 on (the wrapped form
+                         // keeps tops t <= 2^j / wrap_top_div_tr), 2 on, never wrapped
+  int wrap_top_div_tr;   // wrapped form where a three-quarter transform applies and
+                         // log2 L <= wrap_tr_max_log: top t <= 2^j / wrap_top_div_tr
+  int wrap_tr_max_log;
 };
 
 // Prime classes of the tuning table: direct mode with q < 2^30, direct mode

@@ -90,6 +90,8 @@ GlobalKnobs env_global() {
   g.vdm_max_d = env_int("PM_TUNE_VDM_MAXD", 64, 0, 1 << 20);
   g.min_wg = env_int("PM_TUNE_MIN_WG", 512, 0, 1 << 20);
   g.trunc34 = env_int("PM_TUNE_TRUNC34", 1, 0, 2);
+  g.wrap_top_div_tr = 8;
+  g.wrap_tr_max_log = 13;
   return g;
 }
 
@@ -255,7 +257,8 @@ const KnobDef kGlobals[] = {
     {"batch_pw_pipe_pts", 1, 1 << 20}, {"batch_direct_max", 0, 1 << 20},
     {"batch_graph", 0, 1},        {"wrap_min_log", 1, 99},     {"wrap_top_div", 1, 1 << 20},
     {"wrap_min_work_log", 0, 62}, {"vdm_max_d", 0, 1 << 20}, {"min_wg", 0, 1 << 20},
-    {"trunc34", 0, 2},
+    {"trunc34", 0, 2},            {"wrap_top_div_tr", 1, 1 << 20},
+    {"wrap_tr_max_log", 0, 99},
 };
 
 int* knob_slot(Knobs& k, int i) {
@@ -267,7 +270,8 @@ int* knob_slot(Knobs& k, int i) {
 int* global_slot(GlobalKnobs& g, int i) {
   int* f[] = {&g.lds_log, &g.split_min_log, &g.blk_pad, &g.batch_tile_log, &g.batch_pw_work,
               &g.batch_pw_pipe_pts, &g.batch_direct_max, &g.batch_graph, &g.wrap_min_log,
-              &g.wrap_top_div, &g.wrap_min_work_log, &g.vdm_max_d, &g.min_wg, &g.trunc34};
+              &g.wrap_top_div, &g.wrap_min_work_log, &g.vdm_max_d, &g.min_wg, &g.trunc34,
+              &g.wrap_top_div_tr, &g.wrap_tr_max_log};
   return f[i];
 }
 

@@ -205,16 +205,20 @@ def test_profile_session_rules():
 
 @pytest.mark.parametrize("m,n,k,d,j", [
     (128, 8, 128, 4740, 13),   # 2d - 1 = 9479: 8192 points plus a 1287-coefficient top
-    (64, 64, 64, 2560, 12),    # top 1023 <= 2^12 / 4
+                               # (L = 2^14: tops up to 2^13 / 4)
+    (64, 64, 64, 2304, 12),    # top 511 <= 2^12 / 8 (L = 2^13 also fits 3L/4 points)
+    (64, 64, 64, 2306, 0),     # top 515 > 2^12 / 8: the three-quarter transform
     (64, 64, 64, 2562, 0),     # top 1027 > 2^12 / 4
     (64, 64, 64, 1100, 0),     # (mn + nk + mk) 2^11 < 2^25
-    (128, 128, 64, 600, 10),
+    (128, 128, 64, 560, 10),   # top 95 <= 2^10 / 8
+    (128, 128, 64, 600, 0),    # top 175 > 2^10 / 8
     (3, 4, 2, 600, 0),
     (64, 64, 32, 4096, 0),     # 2d - 1 = 8191 < 2^13: no top
 ])
 def test_plan_reports_the_wrapped_form(m, n, k, d, j):
     """pm_plan's wrap_log2_len follows the rule pm_mul applies: wrap only
-    large products whose top t = 2d - 1 - 2^j is at most 2^j / 4."""
+    large products whose top t = 2d - 1 - 2^j is at most 2^j / 4, or 2^j / 8
+    where a three-quarter transform of at most 2^13 points also fits."""
     assert B.pm_plan(998244353, m, n, k, d, 4).wrap_log2_len == j
 
 

@@ -471,10 +471,12 @@ def _wrapped(p, A, B):
 @pytest.mark.parametrize("p,m,n,k,d,wraps", [
     (P30, 3, 4, 2, 600, False),      # small products: plain transforms
     (P30, 64, 64, 64, 1100, False),  # (mn + nk + mk) 2^11 below 2^25
-    (P30, 128, 128, 64, 600, True),  # 2^10 points + a 175-coefficient top
+    (P30, 128, 128, 64, 560, True),  # 2^10 points + a 95-coefficient top
+    (P30, 128, 128, 64, 600, False), # top 175 > 2^10 / 8: three-quarter transform
     (P31, 64, 64, 64, 2100, True),   # 2^12 + 103
-    (P30, 64, 64, 64, 2560, True),   # top 1023 <= 2^12 / 4: wrapped
-    (P30, 64, 64, 64, 2562, False),  # top 1027: the plain 8192-point transform
+    (P30, 64, 64, 64, 2304, True),   # top 511 <= 2^12 / 8: wrapped
+    (P30, 64, 64, 64, 2306, False),  # top 515: the 6144-point three-quarter transform
+    (P30, 64, 64, 32, 4600, True),   # L = 2^14: tops up to 2^13 / 4 (here 1007) wrap
 ])
 def test_wrapped_lengths(p, m, n, k, d, wraps):
     """Products with 2^j < 2d-1 <= 1.25 2^j and enough work: a cyclic product
@@ -499,7 +501,7 @@ def test_wrapped_crt_u64():
 
 def test_wrapped_equals_plain_transforms():
     p, m, n, k = P30, 64, 64, 64
-    for d in (2050, 2100, 2560):
+    for d in (2050, 2100, 2304):
         A, B = tensors(p, m, n, k, d, seed=15)
         wrapped, took = _wrapped(p, A, B)
         assert took, d

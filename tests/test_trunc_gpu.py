@@ -133,10 +133,11 @@ def test_full_length_evaluations_feed_three_quarter_products():
 ])
 def test_in_place_of_the_wrapped_form(p, m, n, k, d):
     """With the knob at 2, sizes the wrapped form would take (size bound
-    lowered) run as three-quarter transforms, single and batched."""
+    lowered, top bound at 2^j / 4) run as three-quarter transforms, single and
+    batched."""
     dt = np.uint64 if p > 0xFFFFFFFF else np.uint32
     eb = 8 if dt == np.uint64 else 4
-    load(4, wrap_min_work_log=0)
+    load(4, wrap_min_work_log=0, wrap_top_div_tr=4)
     assert Bd.pm_plan(p, m, n, k, d, eb).wrap_log2_len > 0
     load(4, wrap_min_work_log=0, trunc34=2)
     info = Bd.pm_plan(p, m, n, k, d, eb)

@@ -80,9 +80,10 @@ def test_global_knobs_move_the_wrapped_length_rule():
     B.tune_load("")
     m, n, k, d = 8, 8, 8, 1100                 # 2d - 1 = 2199 = 2^11 + 151
     assert B.pm_plan(P30, m, n, k, d, 4).wrap_log2_len == 0
-    B.tune_load(table(glob={"wrap_min_work_log": 0}))
+    # (three-quarter transforms off: they take over this top otherwise)
+    B.tune_load(table(glob={"wrap_min_work_log": 0, "trunc34": 0}))
     assert B.pm_plan(P30, m, n, k, d, 4).wrap_log2_len == 11
-    B.tune_load(table(glob={"wrap_min_work_log": 0, "wrap_top_div": 64}))
+    B.tune_load(table(glob={"wrap_min_work_log": 0, "wrap_top_div": 64, "trunc34": 0}))
     assert B.pm_plan(P30, m, n, k, d, 4).wrap_log2_len == 0   # 151 > 2048 / 64
 
 
@@ -108,11 +109,17 @@ def test_three_quarter_transforms_are_planned_for_whole_products_in_the_band():
     B.tune_load("")
     crt = B.pm_plan((1 << 61) - 1, 4, 4, 4, 1500, 8)
     assert crt.mode == 1 and crt.num_points == 3072
-    # the wrapped form keeps precedence unless the knob says 2
+    # where both apply, the wrapped form keeps the small tops: t <= 2^j / 8 for
+    # L <= 2^13, every top of its band above; the knob at 2: never wrapped
     B.tune_load(table(glob={"wrap_min_work_log": 0}))
-    assert B.pm_plan(P30, 8, 8, 8, 1100, 4).wrap_log2_len == 11
+    assert B.pm_plan(P30, 8, 8, 8, 1200, 4).wrap_log2_len == 0     # t = 351 > 2^11 / 8
+    assert B.pm_plan(P30, 8, 8, 8, 1050, 4).wrap_log2_len == 11    # t = 51
+    assert B.pm_plan(P30, 8, 8, 8, 4300, 4).wrap_log2_len == 13    # L = 2^14, t = 407
+    assert B.pm_plan(P30, 8, 8, 8, 4300, 4).num_points == 12288
+    B.tune_load(table(glob={"wrap_min_work_log": 0, "wrap_top_div_tr": 4}))
+    assert B.pm_plan(P30, 8, 8, 8, 1200, 4).wrap_log2_len == 11
     B.tune_load(table(glob={"wrap_min_work_log": 0, "trunc34": 2}))
-    w = B.pm_plan(P30, 8, 8, 8, 1100, 4)
+    w = B.pm_plan(P30, 8, 8, 8, 1050, 4)
     assert w.wrap_log2_len == 0 and w.num_points == 3072
 
 
