@@ -461,6 +461,7 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
 
 KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing
     ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_block_kernel<true", "ntt_fwd"),
+    ("ntt_col_fwd_pair_kernel", "ntt_fwd"), ("ntt_block_regc_pair_kernel", "ntt_fwd"),
     ("ntt_block_regc_kernel<true", "ntt_fwd"), ("ntt_block_regc_kernel<false", "ntt_inv"),
     ("ntt_fwd_kernel", "ntt_fwd"), ("pointwise", "pointwise"),
     ("ntt_block_kernel<false", "ntt_inv"), ("ntt_col_inv_kernel", "ntt_inv"),
@@ -643,7 +644,7 @@ def summarize_counters(root, workload, steps_pmc=3):
         if "ntt_col_inv" in name:
             return "col_inv"
         if "ntt_block" in name:
-            return "block_fwd" if "<true" in name else "block_inv"
+            return "block_fwd" if "<true" in name or "_pair_" in name else "block_inv"
         return None
 
     simds = CUS * 4

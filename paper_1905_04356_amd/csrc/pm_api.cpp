@@ -265,10 +265,17 @@ namespace {
 int launch_product(const Plan& P, const ProductLaunches& L, const bool skip_fwd[2],
                    hipStream_t s) {
   int st;
-  for (int op = 0; op < 2; ++op) {
-    if (skip_fwd[op]) continue;
+  if (!skip_fwd[0] && !skip_fwd[1] && ntt_fwd_pair_ok(L.f[0], L.f[1])) {
     KernelTimer kt(K_NTT_FWD, s);
-    if (launch_ntt_fwd(L.f[op], P.elem_bytes, L.reduce, P.r, s) != hipSuccess) return PM_EDEVICE;
+    if (launch_ntt_fwd_pair(L.f[0], L.f[1], P.elem_bytes, L.reduce, P.r, s) != hipSuccess)
+      return PM_EDEVICE;
+  } else {
+    for (int op = 0; op < 2; ++op) {
+      if (skip_fwd[op]) continue;
+      KernelTimer kt(K_NTT_FWD, s);
+      if (launch_ntt_fwd(L.f[op], P.elem_bytes, L.reduce, P.r, s) != hipSuccess)
+        return PM_EDEVICE;
+    }
   }
   {
     KernelTimer kt(K_POINTWISE, s);

@@ -88,6 +88,11 @@ struct CrtLaunch {
 int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
                    hipStream_t s);
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s);
+// Both operands' forward transforms in one launch per step, where their split
+// transforms share the pass structure and register tile (ntt_fwd_pair_ok).
+bool ntt_fwd_pair_ok(const NttLaunch& a, const NttLaunch& b);
+int launch_ntt_fwd_pair(const NttLaunch& a, const NttLaunch& b, int elem_bytes, int reduce,
+                        int nprimes, hipStream_t s);
 int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 // C[i] -= C[off + i] mod p for i < count (elements of elem_bytes bytes).
 int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,

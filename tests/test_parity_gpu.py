@@ -7,6 +7,7 @@ random-point and Freivalds checks over all outputs.
 """
 from __future__ import annotations
 
+import json
 import sys
 
 import numpy as np
@@ -556,6 +557,31 @@ def test_kernel_timing_counts_only_unpaused_launches():
         assert one[kind][1] >= 1 and one[kind][0] > 0.0, kind
         assert two[kind][1] == 2 * one[kind][1], kind
     assert one["crt"][1] == 0 and one["batched"][1] == 0
+
+
+def test_operand_transforms_share_launches():
+    """Where both operands' split transforms have the same register tile, the
+    forward transforms of A and B run as one first-pass and one block-step
+    launch (two launches instead of four); the result equals the one of
+    separate launches (a table without register tiles)."""
+    p, m, n, k, d = P31, 64, 64, 32, 3000
+    A, B = tensors(p, m, n, k, d, seed=21)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    Bd.pm_profile_begin()
+    C = polymat.mul(p, tA, tB)
+    st = Bd.pm_profile_end()
+    assert st["ntt_fwd"][1] == 2, st["ntt_fwd"]
+    Bd.tune_load(json.dumps({"format": "pm-tune-1", "entries": [{"knobs": {"reg_tile": 0}}]}))
+    try:
+        Bd.pm_profile_begin()
+        C2 = polymat.mul(p, tA, tB)
+        st2 = Bd.pm_profile_end()
+        torch.cuda.synchronize()
+    finally:
+        Bd.tune_load(None)
+    assert st2["ntt_fwd"][1] == 4, st2["ntt_fwd"]
+    assert torch.equal(C, C2)
+    sampled_check(p, A, B, C.cpu().numpy(), seed=21, entries=4)
 
 
 @pytest.mark.parametrize("p,m,n,k,d", [
