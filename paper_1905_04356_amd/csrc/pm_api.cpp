@@ -282,6 +282,12 @@ int launch_product(const Plan& P, const ProductLaunches& L, const bool skip_fwd[
     st = P.pointwise == 1 ? launch_pointwise_mfma(L.pw, P.r, s) : launch_pointwise(L.pw, P.r, s);
     if (st != hipSuccess) return PM_EDEVICE;
   }
+  if (P.mode == 1 && global_knobs().crt_fused && ntt_inv_crt_ok(L.inv, P.r, P.elem_bytes)) {
+    KernelTimer kt(K_NTT_INV, s);
+    if (launch_ntt_inv_crt(L.inv, L.crt, P.elem_bytes, P.r, s) != hipSuccess)
+      return PM_EDEVICE;
+    return PM_OK;
+  }
   {
     KernelTimer kt(K_NTT_INV, s);
     if (launch_ntt_inv(L.inv, P.mode == 0 ? P.elem_bytes : 4, P.r, s) != hipSuccess)

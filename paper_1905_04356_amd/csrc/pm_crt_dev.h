@@ -17,44 +17,54 @@
 
 namespace pm {
 
-// Outputs idx = i0, i0 + step, ... below min(i1, count), for R primes known
-// at compile time: the constants are read once, before the loop, and the
-// loops over primes unroll.
-template <typename TOut, int R>
-__device__ __forceinline__ void crt_range_r(const CrtLaunch& a, uint64_t i0, uint64_t i1,
-                                            uint64_t step) {
-  if (i1 > a.count) i1 = a.count;
+// The constants of R primes known at compile time, read once (the loops over
+// primes unroll).
+template <int R>
+struct CrtConsts {
   uint32_t q[R], mu32[R], inv[R][R], invp[R][R];
   uint64_t radix[R];
+  uint64_t p, mu_p;
+  double pinv;
+
+  __device__ __forceinline__ explicit CrtConsts(const CrtLaunch& a) {
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    q[i] = a.q[i];
-    mu32[i] = a.mu32[i];
-    radix[i] = a.radix_mod_p[i];
+    for (int i = 0; i < R; ++i) {
+      q[i] = a.q[i];
+      mu32[i] = a.mu32[i];
+      radix[i] = a.radix_mod_p[i];
 #pragma unroll
-    for (int j = 0; j < i; ++j) {
-      inv[i][j] = a.inv[i][j];
-      invp[i][j] = a.inv_p[i][j];
+      for (int j = 0; j < i; ++j) {
+        inv[i][j] = a.inv[i][j];
+        invp[i][j] = a.inv_p[i][j];
+      }
     }
+    p = a.p;
+    mu_p = a.mu_p;
+    pinv = a.pinv;
   }
-  const uint64_t p = a.p, mu_p = a.mu_p, pstride = a.prime_stride;
-  const double pinv = a.pinv;
-  for (uint64_t idx = i0; idx < i1; idx += step) {
-    uint32_t v[R], y[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = a.cq[pstride * i + idx];
+
+  // One Garner step for prime i: (t - y_j) q_j^{-1} mod q_i.
+  __device__ __forceinline__ uint32_t step(int i, int j, uint32_t t, uint32_t yj) const {
+    // y_j < q_j < 2^31: Barrett with floor(2^32 / q_i) leaves [0, 2 q_i)
+    const uint32_t r = reduce_once(yj - __umulhi(yj, mu32[i]) * q[i], q[i]);
+    return mul_shoup(sub_mod(t, r, q[i]), inv[i][j], invp[i][j], q[i]);
+  }
+
+  // X mod p from v[i] = X mod q_i (0 <= X < prod q_i).
+  __device__ __forceinline__ uint64_t value(const uint32_t (&v)[R]) const {
+    uint32_t y[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       uint32_t t = v[i];
 #pragma unroll
-      for (int j = 0; j < i; ++j) {
-        // y_j < q_j < 2^31: Barrett with floor(2^32 / q_i) leaves [0, 2 q_i)
-        const uint32_t yj = reduce_once(y[j] - __umulhi(y[j], mu32[i]) * q[i], q[i]);
-        t = sub_mod(t, yj, q[i]);
-        t = mul_shoup(t, inv[i][j], invp[i][j], q[i]);
-      }
+      for (int j = 0; j < i; ++j) t = step(i, j, t, y[j]);
       y[i] = t;
     }
+    return combine(y);
+  }
+
+  // X mod p from its Garner digits y_i.
+  __device__ __forceinline__ uint64_t combine(const uint32_t (&y)[R]) const {
     uint64_t acc = 0;
     if (p <= 0xFFFFFFFFull) {
       // y_i (prod_{j<i} q_j mod p) < 2^63: Barrett with floor((2^64-1)/p)
@@ -95,7 +105,23 @@ __device__ __forceinline__ void crt_range_r(const CrtLaunch& a, uint64_t i0, uin
       if (r >= (int64_t)p) r -= (int64_t)p;
       acc = (uint64_t)r;
     }
-    ((TOut*)a.out)[idx] = (TOut)acc;
+    return acc;
+  }
+};
+
+// Outputs idx = i0, i0 + step, ... below min(i1, count), for R primes known
+// at compile time.
+template <typename TOut, int R>
+__device__ __forceinline__ void crt_range_r(const CrtLaunch& a, uint64_t i0, uint64_t i1,
+                                            uint64_t step) {
+  if (i1 > a.count) i1 = a.count;
+  const CrtConsts<R> cc(a);
+  const uint64_t pstride = a.prime_stride;
+  for (uint64_t idx = i0; idx < i1; idx += step) {
+    uint32_t v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = a.cq[pstride * i + idx];
+    ((TOut*)a.out)[idx] = (TOut)cc.value(v);
   }
 }
 

@@ -88,6 +88,14 @@ struct CrtLaunch {
 int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
                    hipStream_t s);
 int launch_ntt_inv(const NttLaunch& a, int out_elem_bytes, int nprimes, hipStream_t s);
+// CRT mode: the inverse transforms of all primes and the Chinese remaindering,
+// the last inverse pass and the reconstruction in one kernel (no residue
+// arrays in HBM), where supported (ntt_inv_crt_ok: split transforms whose
+// first pass has 3 or 4 stages, 2-3 primes for 32-bit outputs, 2-5 for 64-bit,
+// not 5 primes with a full 4-stage pass).
+bool ntt_inv_crt_ok(const NttLaunch& a, int nprimes, int out_elem_bytes);
+int launch_ntt_inv_crt(const NttLaunch& a, const CrtLaunch& c, int out_elem_bytes, int nprimes,
+                       hipStream_t s);
 // Both operands' forward transforms in one launch per step, where their split
 // transforms share the pass structure and register tile (ntt_fwd_pair_ok).
 bool ntt_fwd_pair_ok(const NttLaunch& a, const NttLaunch& b);

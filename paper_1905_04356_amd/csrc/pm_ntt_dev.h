@@ -29,7 +29,10 @@
 //     consecutive positions; the LDS kernel then holds many entries of one
 //     block and transforms it in place.
 #pragma once
+#include <utility>
+
 #include "pm_arith.h"
+#include "pm_crt_dev.h"
 #include "pm_kernels.h"
 
 namespace pm {
@@ -744,6 +747,71 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
         *(Vec<TOut, CV>*)(out + (size_t)row * E + e) = y;
       }
     }
+  }
+}
+
+// f(integral_constant<int, U>) for U in the sequence, unrolled whatever the
+// size of f's body (a loop's unroll pragma gives up on large bodies, and an
+// unrolled loop is what keeps register arrays out of scratch memory).
+template <int... U, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, U...>, F&& f) {
+  (f(std::integral_constant<int, U>{}), ...);
+}
+
+// Last inverse pass of all NP primes' transforms with the Chinese
+// remaindering folded in (CRT mode): item (j, e) runs the pass on rows j + uS
+// of each prime's evaluations (one entry per item) and writes the
+// coefficients mod p, rebuilt from the NP residues in registers, straight to
+// the output C[row][e] (c.out), so the residues never go through HBM.
+// TR: a three-quarter transform.
+template <typename TOut, int r, int NP, bool TR>
+__device__ __forceinline__ void col_inv_crt_items(const NttLaunch& a, const CrtLaunch& c,
+                                                  uint32_t it0, uint32_t it1, uint32_t step) {
+  constexpr int R = 1 << r;
+  constexpr int KEEP = TR ? 3 * R / 4 : R;
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E;
+  const CrtConsts<NP> cc(c);
+  TOut* out = (TOut*)c.out;
+  for (uint32_t it = it0; it < it1; it += step) {
+    const uint32_t j = it / E, e = it - j * E;
+    // Garner digits, row by row, formed as each prime's pass completes, so
+    // only one prime's residues are live beside the digits.  The scheduling
+    // barrier keeps the next prime's loads from being hoisted over this
+    // prime's work (which would hold every prime's residues at once).
+    uint32_t y[NP][R];
+    static_for(std::make_integer_sequence<int, NP>{}, [&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const PrimeConst& P = a.pc[i];
+      const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * i;
+      uint32_t x[R];
+#pragma unroll
+      for (int u = 0; u < KEEP; ++u) x[u] = in[(size_t)(j + u * S) * E + e];
+      const Tw* tw = P.tw_inv + a.tw_off[0];
+      Tw t[R - 1];
+#pragma unroll
+      for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+      if (TR) butterflies_inv34<r>(x, t, P.q, P.i4, P.i4p);
+      else butterflies<r, false, false>(x, t, P.q);
+      static_for(std::make_integer_sequence<int, KEEP>{}, [&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        uint32_t v = x[u];
+#pragma unroll
+        for (int jj = 0; jj < i; ++jj) v = cc.step(i, jj, v, y[jj][u]);
+        y[i][u] = v;
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    static_for(std::make_integer_sequence<int, KEEP>{}, [&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const uint32_t row = j + u * S - (uint32_t)a.out_lo;  // wraps above nin below out_lo
+      if (row < (uint32_t)a.nin) {
+        uint32_t yu[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) yu[i] = y[i][u];
+        out[(size_t)row * E + e] = (TOut)cc.combine(yu);
+      }
+    });
   }
 }
 

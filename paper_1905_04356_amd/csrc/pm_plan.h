@@ -75,6 +75,7 @@ struct GlobalKnobs {
   int wrap_top_div_tr;   // wrapped form where a three-quarter transform applies and
                          // log2 L <= wrap_tr_max_log: top t <= 2^j / wrap_top_div_tr
   int wrap_tr_max_log;
+  int crt_fused;         // CRT mode: last inverse pass and reconstruction in one kernel (1)
 };
 
 // Prime classes of the tuning table: direct mode with q < 2^30, direct mode
