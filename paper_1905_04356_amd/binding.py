@@ -382,10 +382,21 @@ def pm_mul_geo_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream) -> int:
     return lib().pm_mul_geo_u32(p, m, n, k, d, A, B, C, ws, ws_bytes, stream)
 
 
+_tune_epoch = 0
+
+
+def tune_epoch() -> int:
+    """Counts the tables installed through tune_load (sizes that the
+    launch shapes decide are cached per epoch)."""
+    return _tune_epoch
+
+
 def tune_load(text: str | None) -> None:
     """Install a tuning table (JSON text); None re-reads the default file,
     "" removes the table (defaults).  Raises on an invalid table."""
+    global _tune_epoch
     st = lib().pm_tune_load(None if text is None else text.encode())
+    _tune_epoch += 1
     if st != PM_OK:
         raise PmError(st, "pm_tune_load")
 

@@ -2,6 +2,8 @@
 //
 // The device work of each workgroup lives in pm_ntt_dev.h; this file wraps
 // it in one kernel per tile kind and launches one product's transforms.
+#include <algorithm>
+
 #include "pm_batch.h"
 #include "pm_ntt_dev.h"
 #include "pm_profile.h"
@@ -54,6 +56,25 @@ __global__ __launch_bounds__(kColNT) void ntt_col_fwd_pair_kernel(NttLaunch a, N
   else
     col_fwd_tile<TIn, REDUCE, r>(b, blockIdx.y, (blockIdx.x - nb_a) * kColNT + threadIdx.x,
                                  col_items(b), (gridDim.x - nb_a) * kColNT);
+}
+
+// Unsplit transforms (short lengths): both operands' LDS tiles in one launch.
+template <typename TIn, bool REDUCE, int V>
+__global__ __launch_bounds__(kNT) void ntt_fwd_pair_kernel(NttLaunch a, NttLaunch b,
+                                                           uint32_t nb_a) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t x = xcd_block(blockIdx.x, gridDim.x);
+  if (x < nb_a) fwd_lds_tile<TIn, REDUCE, V>(a, blockIdx.y, x, lds);
+  else fwd_lds_tile<TIn, REDUCE, V>(b, blockIdx.y, x - nb_a, lds);
+}
+
+template <int V, int NT>
+__global__ __launch_bounds__(NT, 4) void ntt_block_pair_kernel(NttLaunch a, NttLaunch b,
+                                                              uint32_t nb_a) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t x = xcd_block(blockIdx.x, gridDim.x);
+  if (x < nb_a) block_tile<true, V, NT>(a, blockIdx.y, x, blockIdx.z, lds);
+  else block_tile<true, V, NT>(b, blockIdx.y, x - nb_a, blockIdx.z, lds);
 }
 
 template <int NT, int PT, int R1, int R2, int R3>
@@ -233,10 +254,13 @@ int launch_ntt_fwd(const NttLaunch& a, int elem_bytes, int reduce, int nprimes,
 // ---- both operands in one launch per step ------------------------------------
 
 bool ntt_fwd_pair_ok(const NttLaunch& a, const NttLaunch& b) {
+  if (!a.split && !b.split)  // unsplit: one LDS kernel per operand, same passes
+    return a.logL == b.logL && a.npass == b.npass;
   if (!a.split || a.split != b.split || a.logL != b.logL || a.keep != b.keep ||
-      a.npass != b.npass || !a.reg_kind || a.reg_kind != b.reg_kind || a.blk_nt != b.blk_nt ||
-      a.eb_log != b.eb_log || a.blk_pitch != b.blk_pitch)
+      a.npass != b.npass || a.reg_kind != b.reg_kind || a.blk_nt != b.blk_nt)
     return false;
+  // the register tile fixes the entries per tile; LDS tiles may differ
+  if (a.reg_kind && (a.eb_log != b.eb_log || a.blk_pitch != b.blk_pitch)) return false;
   for (int i = 0; i < a.npass; ++i)
     if (a.stages[i] != b.stages[i] || a.stride_log[i] != b.stride_log[i]) return false;
   return true;
@@ -286,11 +310,62 @@ static int launch_reg_pair(const NttLaunch& a, const NttLaunch& b, int nprimes, 
   }
 }
 
+template <int V, int NT>
+static int launch_block_pair_v(const NttLaunch& a, const NttLaunch& b, int nprimes,
+                               hipStream_t s) {
+  const size_t lds = std::max(block_lds_bytes(a), block_lds_bytes(b));
+  auto kernel = ntt_block_pair_kernel<V, NT>;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const uint32_t na = (a.E + (1 << a.eb_log) - 1) >> a.eb_log;
+  const uint32_t nb = (b.E + (1 << b.eb_log) - 1) >> b.eb_log;
+  return launch(kernel, dim3(na + nb, nprimes, a.keep), dim3(NT), lds, s, a, b, na);
+}
+
+// LDS-tile block steps of both operands: vectors of the width both allow.
+template <int NT>
+static int launch_block_pair(const NttLaunch& a, const NttLaunch& b, int nprimes,
+                             hipStream_t s) {
+  const int v = std::min(a.vec, b.vec);
+  if (v == 4) return launch_block_pair_v<4, NT>(a, b, nprimes, s);
+  if (v == 2) return launch_block_pair_v<2, NT>(a, b, nprimes, s);
+  return launch_block_pair_v<1, NT>(a, b, nprimes, s);
+}
+
+template <typename TIn, bool REDUCE, int V>
+static int launch_lds_pair_v(const NttLaunch& a, const NttLaunch& b, int nprimes,
+                             hipStream_t s) {
+  const size_t lds = std::max(lds_bytes(a), lds_bytes(b));
+  auto kernel = ntt_fwd_pair_kernel<TIn, REDUCE, V>;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const uint32_t na = (a.E + (1 << a.eb_log) - 1) >> a.eb_log;
+  const uint32_t nb = (b.E + (1 << b.eb_log) - 1) >> b.eb_log;
+  return launch(kernel, dim3(na + nb, nprimes), dim3(kNT), lds, s, a, b, na);
+}
+
 template <typename TIn, bool REDUCE>
 static int launch_fwd_pair_t(const NttLaunch& a, const NttLaunch& b, int nprimes,
                              hipStream_t s) {
+  if (!a.split) {
+    // 32-bit inputs move in 16-byte vectors where both operands allow, 64-bit in 16 bytes
+    constexpr int VW = sizeof(TIn) == 4 ? 4 : 2;
+    if (a.vec >= VW && b.vec >= VW) return launch_lds_pair_v<TIn, REDUCE, VW>(a, b, nprimes, s);
+    return launch_lds_pair_v<TIn, REDUCE, 1>(a, b, nprimes, s);
+  }
   int st = launch_col_pair<TIn, REDUCE>(a, b, nprimes, s);
   if (st != hipSuccess) return st;
+  if (!a.reg_kind)
+    return a.blk_nt == 256 ? launch_block_pair<256>(a, b, nprimes, s)
+                           : launch_block_pair<kNT>(a, b, nprimes, s);
   return a.blk_nt == 256 ? launch_reg_pair<256>(a, b, nprimes, s)
                          : launch_reg_pair<kNT>(a, b, nprimes, s);
 }

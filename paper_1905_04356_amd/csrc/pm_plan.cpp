@@ -49,7 +49,7 @@ int v2_u64(uint64_t x) {
 }
 
 // Deterministic Miller-Rabin for 64-bit n (bases: the primes up to 37).
-bool is_prime_u64(uint64_t n) {
+static bool miller_rabin_u64(uint64_t n) {
   static const uint64_t B[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
   if (n < 2) return false;
   for (uint64_t b : B)
@@ -68,6 +68,21 @@ bool is_prime_u64(uint64_t n) {
     if (comp) return false;
   }
   return true;
+}
+
+// The planner asks about the same few moduli on every call, and the test
+// costs a few microseconds: the last answers are kept per thread.
+bool is_prime_u64(uint64_t n) {
+  thread_local uint64_t seen[4] = {0, 0, 0, 0};
+  thread_local bool answer[4] = {false, false, false, false};
+  thread_local int next = 0;
+  for (int i = 0; i < 4; ++i)
+    if (seen[i] == n && n != 0) return answer[i];
+  const bool r = miller_rabin_u64(n);
+  seen[next] = n;
+  answer[next] = r;
+  next = (next + 1) & 3;
+  return r;
 }
 
 // Primes q < 2^31 with 2^24 | q-1, largest first.  Each supports transforms

@@ -16,8 +16,14 @@ namespace pm {
 namespace {
 struct Rec {
   int kind;
+  int dev;
   hipEvent_t a, b;
 };
+
+int current_device() {
+  int dev = 0;
+  return hipGetDevice(&dev) == hipSuccess ? dev : 0;
+}
 std::atomic<int> g_on{0};  // 0 off, 1 timing, 2 paused
 std::mutex g_mu;
 std::vector<Rec> g_recs;
@@ -29,9 +35,26 @@ bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
+// Events of finished timing sessions, per device, for the next timed
+// launches (creating two events per launch costs more host time than the
+// launch itself for small products).
+std::vector<std::vector<hipEvent_t>> g_pool;
+
 // timing-only events: without the system-scope fence, completing one does
 // not write back and invalidate the caches
 bool make_pair(hipEvent_t* a, hipEvent_t* b) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  {
+    std::lock_guard<std::mutex> l(g_mu);
+    if ((int)g_pool.size() > dev && g_pool[dev].size() >= 2) {
+      *a = g_pool[dev].back();
+      g_pool[dev].pop_back();
+      *b = g_pool[dev].back();
+      g_pool[dev].pop_back();
+      return true;
+    }
+  }
   if (hipEventCreateWithFlags(a, hipEventDisableSystemFence) != hipSuccess) return false;
   if (hipEventCreateWithFlags(b, hipEventDisableSystemFence) != hipSuccess) {
     (void)hipEventDestroy(*a);
@@ -73,7 +96,7 @@ KernelTimer::~KernelTimer() {
     g_failed = true;
     return;
   }
-  g_recs.push_back(Rec{kind_, a_, b_});
+  g_recs.push_back(Rec{kind_, current_device(), a_, b_});
 }
 
 hipError_t launch_kernel(const void* fn, dim3 grid, dim3 block, void** args, size_t lds,
@@ -89,7 +112,7 @@ hipError_t launch_kernel(const void* fn, dim3 grid, dim3 block, void** args, siz
     e = hipExtLaunchKernel(fn, grid, block, args, lds, s, a, b, 0);
     if (e == hipSuccess) {
       std::lock_guard<std::mutex> l(g_mu);
-      g_recs.push_back(Rec{t_kind, a, b});
+      g_recs.push_back(Rec{t_kind, current_device(), a, b});
     } else {
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
@@ -134,8 +157,9 @@ pm_status pm_profile_end(pm_kernel_stats* out) {
       out->total_ms[r.kind] += ms;
       out->launches[r.kind] += 1;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    if (r.dev >= (int)pm::g_pool.size()) pm::g_pool.resize(r.dev + 1);
+    pm::g_pool[r.dev].push_back(r.b);
+    pm::g_pool[r.dev].push_back(r.a);
   }
   pm::g_recs.clear();
   return bad ? PM_EDEVICE : PM_OK;

@@ -20,13 +20,17 @@ def _stream_ptr(stream) -> int:
 
 
 @contextlib.contextmanager
-def _on_stream(stream, *inputs):
-    """Launch on `stream` (None: the current stream).  For another stream,
-    that stream first waits for the current stream's work (which produced
-    the inputs), the inputs are marked as in use on it, and tensors
-    allocated inside the block (outputs, workspaces) belong to it."""
-    cur = torch.cuda.current_stream()
-    if stream is None or stream == cur:
+def _on_stream(stream, *inputs, cur=None):
+    """Launch on `stream` (None: the current stream, `cur` if given).  For
+    another stream, that stream first waits for the current stream's work
+    (which produced the inputs), the inputs are marked as in use on it, and
+    tensors allocated inside the block (outputs, workspaces) belong to it."""
+    if stream is None:
+        yield
+        return
+    if cur is None:
+        cur = torch.cuda.current_stream()
+    if stream == cur:
         yield
         return
     stream.wait_stream(cur)
@@ -122,6 +126,22 @@ def plan(p: int, m: int, n: int, k: int, d: int, elem_bytes: int = 4):
     return _b.pm_plan(p, m, n, k, d, elem_bytes)
 
 
+_sizes: dict = {}
+
+
+def _product_sizes(p: int, m: int, n: int, k: int, d: int, eb: int) -> tuple[int, int]:
+    """(workspace bytes, table bytes) of a product, cached per shape and
+    tuning table (each query plans the product in the library)."""
+    key = (p, m, n, k, d, eb, _b.tune_epoch())
+    got = _sizes.get(key)
+    if got is None:
+        if len(_sizes) > 4096:
+            _sizes.clear()
+        got = (_b.pm_workspace_bytes(p, m, n, k, d, eb), _b.pm_tables_bytes(p, m, n, k, d, eb))
+        _sizes[key] = got
+    return got
+
+
 def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
         workspace: Workspace | None = None, stream=None) -> torch.Tensor:
     """C = A B mod p on the GPU (asynchronous on `stream`)."""
@@ -138,15 +158,17 @@ def mul(p: int, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = Non
         raise ValueError("A and B must be GPU tensors")
     A = A.contiguous()
     B = B.contiguous()
-    with _on_stream(stream, A, B):
+    cur = torch.cuda.current_stream()
+    sptr = int((stream if stream is not None else cur).cuda_stream)
+    with _on_stream(stream, A, B, cur=cur):
         if out is None:
             out = torch.empty((2 * d - 1, m, k), dtype=A.dtype, device=A.device)
-        ws_bytes = _b.pm_workspace_bytes(p, m, n, k, d, eb)
+        ws_bytes, tab_bytes = _product_sizes(p, m, n, k, d, eb)
         ws = (workspace or _workspace(A.device)).get(ws_bytes)
         fn = _b.pm_mul_u32 if eb == 4 else _b.pm_mul_u64
         st = _with_tables(A.device, lambda: fn(
             p, m, n, k, d, A.data_ptr(), B.data_ptr(), out.data_ptr(), ws.data_ptr(),
-            ws.numel(), _stream_ptr(stream)), _b.pm_tables_bytes(p, m, n, k, d, eb))
+            ws.numel(), sptr), tab_bytes)
     if st != _b.PM_OK:
         raise _b.PmError(st, "pm_mul")
     return out

@@ -560,10 +560,12 @@ def test_kernel_timing_counts_only_unpaused_launches():
 
 
 def test_operand_transforms_share_launches():
-    """Where both operands' split transforms have the same register tile, the
+    """Where both operands' split transforms have the same pass structure, the
     forward transforms of A and B run as one first-pass and one block-step
-    launch (two launches instead of four); the result equals the one of
-    separate launches (a table without register tiles)."""
+    launch (two launches instead of four), with register tiles or with
+    LDS-resident ones; the result equals the one from each operand's
+    evaluations made alone. Short unsplit transforms run as one launch for
+    both operands."""
     p, m, n, k, d = P31, 64, 64, 32, 3000
     A, B = tensors(p, m, n, k, d, seed=21)
     tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
@@ -579,9 +581,28 @@ def test_operand_transforms_share_launches():
         torch.cuda.synchronize()
     finally:
         Bd.tune_load(None)
-    assert st2["ntt_fwd"][1] == 4, st2["ntt_fwd"]
+    assert st2["ntt_fwd"][1] == 2, st2["ntt_fwd"]        # LDS-resident tiles, paired too
     assert torch.equal(C, C2)
+    # each operand transformed alone (evaluations), then the product from them
+    Ae, Be = polymat.evaluate(p, tA, 0), polymat.evaluate(p, tB, 1)
+    (C3,) = polymat.mul_batched(p, [tA], [tB], A_evals=[Ae], B_evals=[Be])
+    torch.cuda.synchronize()
+    assert torch.equal(C, C3)
     sampled_check(p, A, B, C.cpu().numpy(), seed=21, entries=4)
+    # short lengths (one LDS kernel per operand): one launch for both, with
+    # 16-byte vectors, and with 1-word vectors where an entry count is odd;
+    # split transforms with LDS-resident block tiles (few entries): two
+    for (p, m, n, k, d, launches) in ((P30, 8, 8, 8, 256, 1), (P31, 3, 5, 7, 300, 1),
+                                      (P30, 4, 6, 4, 500, 1), (P30, 4, 6, 4, 1000, 2),
+                                      (P31, 3, 5, 7, 2500, 2)):
+        A, B = tensors(p, m, n, k, d, seed=22)
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        Bd.pm_profile_begin()
+        C = polymat.mul(p, tA, tB)
+        st = Bd.pm_profile_end()
+        torch.cuda.synchronize()
+        assert st["ntt_fwd"][1] == launches, (m, n, k, d, st["ntt_fwd"])
+        assert np.array_equal(C.cpu().numpy().astype(np.uint64), O.polymatmul(p, A, B))
 
 
 @pytest.mark.parametrize("p,m,n,k,d", [
