@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -1303,18 +1304,26 @@ std::vector<uint8_t> batch_signature(uint64_t p, int eb, const pm_product* prods
   return sig;
 }
 
+int run_batch_phases(uint64_t p, int eb, const std::vector<Plan>& plans,
+                     const std::vector<uint64_t>& offs, const BatchLayout& lay,
+                     const pm_product* prods, uint8_t* ws, uint64_t ws_bytes, hipStream_t s);
+
+// log2 of a product's transform work, (mn + nk + mk) points primes.
+double work_log2(const Plan& P) {
+  const double e = (double)P.m * P.n + (double)P.n * P.k + (double)P.m * P.k;
+  return std::log2(e * (double)P.npts * (double)P.r);
+}
+
 int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
               const std::vector<uint64_t>& offs, const BatchLayout& lay, const pm_product* prods,
               uint8_t* ws, uint64_t ws_bytes, hipStream_t s) {
   const int count = (int)plans.size();
   // Global knobs: batch_direct_max (default 2) is the largest batch launched
-  // per product; batch_graph 0 turns graph replay off.
+  // per product; batch_single_min_log (see below).
   const GlobalKnobs G = global_knobs();
-  const int direct_max = G.batch_direct_max;
-  const bool use_graphs = G.batch_graph != 0;
   int st = prepare_plans(plans.data(), plans.size(), s);
   if (st != PM_OK) return st;
-  if (count <= direct_max) return run_direct(plans, offs, prods, ws, s);
+  if (count <= G.batch_direct_max) return run_direct(plans, offs, prods, ws, s);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
     // The caller is capturing a graph of its own: the phase launches would
@@ -1323,6 +1332,42 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
     // by one with their parameters in kernel arguments (same results).
     return run_direct(plans, offs, prods, ws, s);
   }
+  // Products whose transforms fill the device on their own, (mn + nk + mk)
+  // points primes >= 2^batch_single_min_log, gain nothing from sharing
+  // launches and run faster on the single-product kernels (launch shapes
+  // tuned per shape, both operands per launch): they are launched that way,
+  // ahead of the phase launches of the others (0: never; default 25, the
+  // best of 18..30 on 512 products of the batched shape rule: 77 products
+  // as single launches, 56.8 -> 55.5 ms per call; more singles lose to the
+  // shared launches, 62.6 ms at 18).
+  if (G.batch_single_min_log > 0) {
+    std::vector<Plan> bp, rp;
+    std::vector<uint64_t> bo, ro;
+    std::vector<pm_product> bpr, rpr;
+    for (int i = 0; i < count; ++i) {
+      const bool big = work_log2(plans[i]) >= (double)G.batch_single_min_log;
+      (big ? bp : rp).push_back(plans[i]);
+      (big ? bo : ro).push_back(offs[i]);
+      (big ? bpr : rpr).push_back(prods[i]);
+    }
+    if (!bp.empty()) {
+      st = run_direct(bp, bo, bpr.data(), ws, s);
+      if (st != PM_OK || rp.empty()) return st;
+      if ((int)rp.size() <= G.batch_direct_max) return run_direct(rp, ro, rpr.data(), ws, s);
+      return run_batch_phases(p, eb, rp, ro, lay, rpr.data(), ws, ws_bytes, s);
+    }
+  }
+  return run_batch_phases(p, eb, plans, offs, lay, prods, ws, ws_bytes, s);
+}
+
+// The phase launches of a batch (graph replay from the second occurrence of
+// the same batch; global knob batch_graph 0 turns replay off).
+int run_batch_phases(uint64_t p, int eb, const std::vector<Plan>& plans,
+                     const std::vector<uint64_t>& offs, const BatchLayout& lay,
+                     const pm_product* prods, uint8_t* ws, uint64_t ws_bytes, hipStream_t s) {
+  const GlobalKnobs G = global_knobs();
+  const bool use_graphs = G.batch_graph != 0;
+  int st = PM_OK;
   if (!use_graphs) {
     BatchBuild B;
     st = build_batch(plans, offs, lay, prods, ws, &B);

@@ -93,6 +93,7 @@ GlobalKnobs env_global() {
   g.wrap_top_div_tr = 8;
   g.wrap_tr_max_log = 13;
   g.crt_fused = env_int("PM_TUNE_CRT_FUSED", 1, 0, 1);
+  g.batch_single_min_log = env_int("PM_TUNE_BATCH_SINGLE_MIN_LOG", 25, 0, 62);
   return g;
 }
 
@@ -260,6 +261,7 @@ const KnobDef kGlobals[] = {
     {"wrap_min_work_log", 0, 62}, {"vdm_max_d", 0, 1 << 20}, {"min_wg", 0, 1 << 20},
     {"trunc34", 0, 2},            {"wrap_top_div_tr", 1, 1 << 20},
     {"wrap_tr_max_log", 0, 99},   {"crt_fused", 0, 1},
+    {"batch_single_min_log", 0, 62},
 };
 
 int* knob_slot(Knobs& k, int i) {
@@ -272,7 +274,8 @@ int* global_slot(GlobalKnobs& g, int i) {
   int* f[] = {&g.lds_log, &g.split_min_log, &g.blk_pad, &g.batch_tile_log, &g.batch_pw_work,
               &g.batch_pw_pipe_pts, &g.batch_direct_max, &g.batch_graph, &g.wrap_min_log,
               &g.wrap_top_div, &g.wrap_min_work_log, &g.vdm_max_d, &g.min_wg, &g.trunc34,
-              &g.wrap_top_div_tr, &g.wrap_tr_max_log, &g.crt_fused};
+              &g.wrap_top_div_tr, &g.wrap_tr_max_log, &g.crt_fused,
+              &g.batch_single_min_log};
   return f[i];
 }
 

@@ -146,3 +146,37 @@ def test_small_wrapped_products_equal_the_oracle(p, m, n, k, d, j):
     ref = O.polymatmul(p, A, B)
     bad = np.argwhere(C.cpu().numpy().astype(np.uint64) != ref)
     assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+
+
+def test_large_products_of_a_batch_run_as_single_products():
+    """With batch_single_min_log, the products of a batched call with at
+    least that much transform work run on the single-product kernels and the
+    rest in the phase launches; results equal the all-phase batch and the
+    oracle (sampled), for thresholds that take none, some and all of them."""
+    p = P30
+    shapes = [(64, 32, 64, 2000), (8, 8, 8, 300), (32, 64, 16, 1500), (4, 4, 4, 50),
+              (16, 16, 16, 3000), (64, 64, 64, 700)]
+    As, Bs, refs = [], [], []
+    for i, (m, n, k, d) in enumerate(shapes):
+        A, B = operands(p, m, n, k, d, np.uint32, seed=70 + i)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        refs.append(O.polymatmul_entries(p, A, B, [(0, 0), (m - 1, k - 1)]))
+    results = {}
+    for v in (0, 24, 23, 1):
+        Bd.tune_load(table({}, {"batch_single_min_log": v}))
+        say(f"[tune] batch_single_min_log={v}")
+        Bd.pm_profile_begin()
+        for _ in range(3):      # eager, graph capture, replay
+            outs = polymat.mul_batched(p, As, Bs)
+        st = Bd.pm_profile_end()
+        torch.cuda.synchronize()
+        # the phase launches run while some products remain for them
+        assert (st["batched"][1] > 0) == (v != 1), (v, st["batched"])
+        results[v] = [C.cpu().numpy() for C in outs]
+    for v in (24, 23, 1):
+        for a, b in zip(results[0], results[v]):
+            assert np.array_equal(a, b), v
+    for (m, n, k, d), C, ref in zip(shapes, results[0], refs):
+        got = np.stack([C[:, 0, 0], C[:, m - 1, k - 1]]).astype(np.uint64)
+        assert np.array_equal(got, np.asarray(ref).reshape(got.shape)), (m, n, k, d)
