@@ -402,7 +402,7 @@ def bench_wrap(p=998244353, seed=10, reps=10):
     return {"workload": f"products mod {p} with 2d - 1 just above a power of two", "runs": rows}
 
 
-def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
+def bench_batched(steps, warmup, seed=3, count=512, p=998244353, settle_s=1.0):
     """Config 3: `count` products with the batched shape rule, all in one
     batched call per step, against one pm_mul call per product on the same
     stream (same inputs, outputs, device)."""
@@ -426,6 +426,7 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     for _ in range(warmup):
         polymat.mul_batched(p, As, Bs, outs, workspace=wsb, stream=stream)
     torch.cuda.synchronize()
+    settle(lambda: polymat.mul_batched(p, As, Bs, outs, workspace=wsb, stream=stream), settle_s)
     Bd.pm_profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -435,11 +436,22 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353):
     kb = Bd.pm_profile_end()
     batched_ws = wsb.buf.numel()
     del wsb
+    # a marker kernel between the batched calls and the single calls, so that
+    # a kernel trace of this run can be split (the batched calls also launch
+    # single-product kernels for their largest products)
+    mark = torch.zeros(64, dtype=torch.uint32, device=dev)
+    Bd.pm_neg_mod(p, mark.data_ptr(), mark.data_ptr(), 64, 4, int(stream.cuda_stream))
+    torch.cuda.synchronize()
     wss = polymat.Workspace(dev)
     for _ in range(warmup):
         for A, B, C in zip(As, Bs, outs):
             polymat.mul(p, A, B, out=C, workspace=wss, stream=stream)
     torch.cuda.synchronize()
+
+    def singles():
+        for A, B, C in zip(As, Bs, outs):
+            polymat.mul(p, A, B, out=C, workspace=wss, stream=stream)
+    settle(singles, settle_s)
     Bd.pm_profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -553,7 +565,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
             traffic[kind_of(name)] += v * wscale / pmc_total_steps
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
-              "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0")
+              "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 --settle-seconds 0")
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           f"`avg us` is rocprofv3's --stats average over all calls ({warmup_stats} warm-up "
@@ -574,7 +586,8 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
-                  "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0")
+                  "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 "
+                  "--settle-seconds 0")
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
@@ -651,7 +664,7 @@ def summarize_counters(root, workload, steps_pmc=3):
     cmd = ("timeout -s KILL 90 rocprofv3 --pmc " + " ".join(COUNTERS) +
            " --output-format csv -d gpurun_out/vc -o vc -- python3 bench.py --steps "
            f"{steps_pmc - 1} --warmup 1 --workload {workload} --no-cpu-baseline --no-batched "
-           "--no-middle --no-pmbasis --no-extra --serving-seconds 0")
+           "--no-middle --no-pmbasis --no-extra --serving-seconds 0 --settle-seconds 0")
     md = [f"# Instruction counters: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
           f"Sums over the {steps} steps of the run, divided by {steps} (per step). "
@@ -684,19 +697,24 @@ def summarize_counters(root, workload, steps_pmc=3):
 def summarize_batched(root, batched_calls, single_rounds):
     """profiles/c3_batched_kernels.md from a rocprofv3 --kernel-trace run of
     `bench.py --only-batched` under root/sb/: the batched calls' kernels (the
-    phase kernels and the corrections of wrapped products, up to the end of
-    the last phase kernel) and the one-call-per-product kernels after them,
-    as device time per call or round."""
+    phase kernels, the single-product kernels of their largest products and
+    the corrections of wrapped products, up to the marker kernel that
+    bench_batched launches between its two parts) and the one-call-per-product
+    kernels after it, as device time per call or round."""
     import collections
     import csv
     import glob
     files = glob.glob(os.path.join(root, "sb", "*kernel_trace.csv"))
     rows = sorted(csv.DictReader(open(files[0])), key=lambda r: int(r["Start_Timestamp"]))
-    rows = [r for r in rows if "pm::" in r["Kernel_Name"]]
+    # (one-time table fills left out)
+    rows = [r for r in rows if "pm::" in r["Kernel_Name"] and "fill_" not in r["Kernel_Name"]]
+    # the batched calls' kernels (phase kernels, the single-product kernels of
+    # their largest products, corrections) run from the first phase kernel's
+    # call to the marker kernel that bench.py launches before the single calls
     batch = [i for i, r in enumerate(rows) if "batch_kernel" in r["Kernel_Name"]]
-    first, last = batch[0], batch[-1]
-    while last + 1 < len(rows) and "unwrap_kernel" in rows[last + 1]["Kernel_Name"]:
-        last += 1
+    marks = [i for i, r in enumerate(rows) if "neg_mod_kernel" in r["Kernel_Name"]]
+    first, last = 0, marks[0] - 1
+    assert batch and batch[-1] < marks[0]
 
     def table(sel, per):
         agg = collections.defaultdict(lambda: [0, 0.0])
@@ -711,9 +729,9 @@ def summarize_batched(root, batched_calls, single_rounds):
         return out + [f"| total | | {tot:.3f} |"], tot
 
     cmd = ("rocprofv3 --kernel-trace --output-format csv -d gpurun_out/sb -o sb -- "
-           "python3 bench.py --only-batched")
+           "python3 bench.py --only-batched --settle-seconds 0")
     tb, b_ms = table(rows[first:last + 1], batched_calls)
-    ts, s_ms = table(rows[last + 1:], single_rounds)
+    ts, s_ms = table(rows[last + 2:], single_rounds)
     md = ["# Kernel profile: c3 (512 products, one batched call vs one pm_mul per product)", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
           f"Device time of the kernels per batched call ({batched_calls} calls: warm-up, "
@@ -796,7 +814,23 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bench_single(workload, steps, warmup):
+def settle(step, seconds):
+    """Untimed steps until the device has run for `seconds` (after the
+    warm-up steps): the clocks ramp up over the first few hundred
+    milliseconds of load, and a timed region that starts earlier measures
+    the ramp rather than the kernels. Returns the steps run."""
+    import torch
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            step()
+        n += 8
+        torch.cuda.synchronize()
+    return n
+
+
+def bench_single(workload, steps, warmup, settle_s=1.0):
     """One product per step (pm_mul on resident operands): throughput, the
     per-step device time distribution, per-kernel device times and their
     rooflines, and the whole path's roofline fraction."""
@@ -823,6 +857,8 @@ def bench_single(workload, steps, warmup):
     for _ in range(warmup):
         polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream)
     torch.cuda.synchronize()
+    settled = settle(lambda: polymat.mul(p, tA, tB, out=tC, workspace=ws, stream=stream),
+                     settle_s)
 
     # Kernel durations come from the dispatch events of every
     # PROFILE_EVERY-th step of the timed loop (each timed launch costs a few
@@ -891,6 +927,8 @@ def bench_single(workload, steps, warmup):
         "n_gpus": 1,
         "steps": steps,
         "warmup": warmup,
+        "settle_s": settle_s,
+        "untimed_steps_run": warmup + settled,
         "ms_per_step": wall / steps * 1e3,
         "device_ms_per_step": mean_ms,
         "device_ms_per_step_dist": dist,
@@ -1036,6 +1074,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the tuned-vs-default comparisons and the c1/c4 products")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--settle-seconds", type=float, default=1.0,
+                    help="untimed steps after the warm-up steps until the device has run "
+                         "this long (clock ramp-up), before each timed region")
     ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the serving trace (0: skip)")
     ap.add_argument("--serving-warmup", type=float, default=5.0,
@@ -1071,13 +1112,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
-        print(json.dumps(bench_batched(args.batched_steps, 2)), flush=True)
+        print(json.dumps(bench_batched(args.batched_steps, 2, settle_s=args.settle_seconds)),
+              flush=True)
         return
 
     import torch
 
     progress(f"single product {args.workload}: {args.warmup} warm-up, {args.steps} timed steps")
-    res = bench_single(args.workload, args.steps, args.warmup)
+    res = bench_single(args.workload, args.steps, args.warmup, args.settle_seconds)
     out = res.pop("_out")
     p, m, n, k, d = res["p"], res["m"], res["n"], res["k"], res["d"]
     A, B = res["A"], res["B"]
@@ -1088,7 +1130,7 @@ def main():
     for w in () if args.no_extra else ("c1", "c4"):
         if w != args.workload:
             progress(f"single product {w}")
-            r = bench_single(w, 20, 20)
+            r = bench_single(w, 20, 20, args.settle_seconds)
             o = r.pop("_out")
             keep = {kk: o[kk] for kk in ("value", "unit", "ms_per_step", "device_ms_per_step",
                                          "device_ms_per_step_dist", "dtype", "config",
@@ -1101,7 +1143,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         progress("batched: 512 products")
-        out["batched"] = bench_batched(args.batched_steps, 2)
+        out["batched"] = bench_batched(args.batched_steps, 2, settle_s=args.settle_seconds)
         if not args.no_extra:
             out["tuning"]["batched"] = bench_batched_tuned_vs_default()
         torch.cuda.empty_cache()
