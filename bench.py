@@ -61,9 +61,17 @@ def workload_params(name):
     return p, m, n, k, d, dt
 
 
-def kernel_work(kind, plan, p, m, n, k, d, eb):
+def garner_ops(r):
+    """VALU instructions of one reconstruction from r residues: r (r-1) / 2
+    Garner steps (Barrett correction 3, modular difference 3, Shoup product
+    5) and the sum of r digit products mod p (about 12 each)."""
+    return 11 * r * (r - 1) // 2 + 12 * r
+
+
+def kernel_work(kind, plan, p, m, n, k, d, eb, crt_folded=False):
     """Algorithmic work of all launches of one kernel kind in one product:
-    (bytes, ops, ops_unit, peak, bound)."""
+    (bytes, ops). crt_folded: CRT mode with the reconstruction done by the
+    last inverse pass (no residue arrays; its operations count there)."""
     L = 1 << plan.log2_len
     r = plan.num_primes
     logL = plan.log2_len
@@ -74,6 +82,10 @@ def kernel_work(kind, plan, p, m, n, k, d, eb):
         return byts, ops
     if kind == "ntt_inv":
         E = m * k
+        if crt_folded:
+            byts = 4 * L * E * r + eb * (2 * d - 1) * E
+            ops = OPS_INV_BUTTERFLY * (L // 2) * logL * E * r + garner_ops(r) * (2 * d - 1) * E
+            return byts, ops
         out_b = eb if plan.mode == 0 else 4
         byts = 4 * L * E * r + out_b * (2 * d - 1) * E * r
         ops = OPS_INV_BUTTERFLY * (L // 2) * logL * E * r
@@ -898,10 +910,11 @@ def bench_single(workload, steps, warmup, settle_s=1.0):
     work = float(m) * n * k * d
     value = work * steps / wall
     kernels = {}
+    folded = plan.mode == 1 and kstats.get("crt", (0.0, 0))[1] == 0
     for kind, (ms, launches) in kstats.items():
         if launches == 0:
             continue
-        byts, ops = kernel_work(kind, plan, p, m, n, k, d, eb)
+        byts, ops = kernel_work(kind, plan, p, m, n, k, d, eb, crt_folded=folded)
         sec = ms / 1e3 / timed_steps          # device seconds per product
         kernels[kind] = {"ms_per_step": ms / timed_steps, "launches_per_step":
                          launches / timed_steps, "algorithmic_bytes": byts,
@@ -943,6 +956,8 @@ def bench_single(workload, steps, warmup, settle_s=1.0):
                    "primes": plan.num_primes,
                    "pointwise": "mfma_int8" if plan.pointwise == 1 else "valu",
                    "tune_entry": plan.tune_entry},
+        "crt_reconstruction": None if plan.mode == 0 else
+        ("in the last inverse pass (ntt_inv)" if folded else "separate kernel (crt)"),
         "roofline": roof,
         "kernels": kernels,
         "kernel_timing": f"dispatch start/stop events on {timed_steps} of the {steps} "
@@ -1134,7 +1149,8 @@ def main():
             o = r.pop("_out")
             keep = {kk: o[kk] for kk in ("value", "unit", "ms_per_step", "device_ms_per_step",
                                          "device_ms_per_step_dist", "dtype", "config",
-                                         "roofline", "kernels", "steps", "warmup")}
+                                         "roofline", "kernels", "steps", "warmup",
+                                         "crt_reconstruction")}
             if not args.no_cpu_baseline:
                 keep["cpu_baseline"] = cpu_baseline(r["p"], r["A"], r["B"], r["m"], r["n"],
                                                     r["k"], r["d"], 5.0)
