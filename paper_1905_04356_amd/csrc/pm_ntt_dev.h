@@ -437,10 +437,29 @@ __device__ __forceinline__ void block_tile(const NttLaunch& a, int prime, int eb
 // next's).  The first pass takes its values straight from the loads and the
 // last one stores straight from registers, so LDS sees two accesses per
 // residue per pass boundary and none at the ends.  Positions are swizzled in
-// LDS (p ^ ((p >> 3) & 7)) so that the strided position sets of a wave spread
-// over the banks.
+// LDS so that the strided position sets of a wave spread over the banks.
+// With 8 positions per thread: p ^ ((p >> 3) & 7) (no conflicts measured).
+// With 16: bit b (b < 3) of p is xored with the parity of p & M_b,
+// M_0 = 1658, M_1 = 1388, M_2 = 2800 (M_b holds no bit at or below b, so
+// the map is a bijection on every aligned block of 8 or more positions);
+// the masks came from a search over such maps against a model of the tile's
+// LDS accesses that reproduced the measured conflict counts (32 banks, a
+// wave's 8-byte accesses served 128 bytes at a time), and removed the 3
+// conflict cycles per LDS instruction that the first map left in the
+// {4,3,3} structures (measured at L = 2^14; no time change there, the LDS
+// exchange being hidden).  Both maps are linear over GF(2), and a thread's
+// position is the bitwise or of a part from its thread index and a part
+// from its register index (disjoint bit fields), so the swizzle of the
+// register part is a compile-time constant and the thread part's is
+// computed once per pass.
 
-__device__ __forceinline__ int reg_swz(int p) { return p ^ ((p >> 3) & 7); }
+template <int PT>
+__host__ __device__ constexpr int reg_swz(int p) {
+  if (PT == 8) return p ^ ((p >> 3) & 7);
+  const unsigned x = (unsigned)p;
+  return p ^ ((__builtin_popcount(x & 1658u) & 1) | ((__builtin_popcount(x & 1388u) & 1) << 1) |
+              ((__builtin_popcount(x & 2800u) & 1) << 2));
+}
 
 // r stages at stride 2^s on each of the thread's PT / 2^r groups, twiddles
 // of group c at tw[k S + j].  At stride 1 (s = 0) every group has j = 0, so
@@ -484,7 +503,7 @@ struct RegPasses {
 };
 
 template <int PT, int r, int s>
-__device__ __forceinline__ int reg_pos_c(int w, int v) {
+__host__ __device__ constexpr int reg_pos_c(int w, int v) {
   const int c = v >> r, u = v & ((1 << r) - 1);
   const int wg = w * (PT >> r) + c;
   return ((wg >> s) << (s + r)) + (wg & ((1 << s) - 1)) + (u << s);
@@ -499,18 +518,23 @@ __device__ __forceinline__ void reg_steps(uint32_t (&x)[ET][PT], int w, int el, 
   if constexpr (K > 0) {
     constexpr int ip = DIF ? K - 1 : RP::np - K;        // previous pass
     constexpr int rp = RP::r(ip), sp = RP::s(ip);
+    // swizzled position = thread part ^ register part (see reg_swz)
+    const int wp = reg_swz<PT>(reg_pos_c<PT, rp, sp>(w, 0));
+    const int wc = reg_swz<PT>(reg_pos_c<PT, r, s>(w, 0));
 #pragma unroll
     for (int v = 0; v < PT; ++v) {
       Vec<uint32_t, ET> y;
 #pragma unroll
       for (int e = 0; e < ET; ++e) y.v[e] = x[e][v];
-      *(Vec<uint32_t, ET>*)(lds + (reg_swz(reg_pos_c<PT, rp, sp>(w, v)) << EBL) + el) = y;
+      const int sv = reg_swz<PT>(reg_pos_c<PT, rp, sp>(0, v));
+      *(Vec<uint32_t, ET>*)(lds + ((wp ^ sv) << EBL) + el) = y;
     }
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < PT; ++v) {
+      const int sv = reg_swz<PT>(reg_pos_c<PT, r, s>(0, v));
       const Vec<uint32_t, ET> y =
-          *(const Vec<uint32_t, ET>*)(lds + (reg_swz(reg_pos_c<PT, r, s>(w, v)) << EBL) + el);
+          *(const Vec<uint32_t, ET>*)(lds + ((wc ^ sv) << EBL) + el);
 #pragma unroll
       for (int e = 0; e < ET; ++e) x[e][v] = y.v[e];
     }
