@@ -87,6 +87,19 @@ __global__ __launch_bounds__(NT, 4) void ntt_block_regc_pair_kernel(NttLaunch a,
 }
 
 // (two waves per SIMD: up to 256 VGPRs for the NP x 2^r residues an item holds)
+// CRT mode, the first forward pass of all primes from one read of the input
+// (col_fwd_items_mp), for one operand or both (nb_a = gridDim.x: one).
+template <typename TIn, int r>
+__global__ __launch_bounds__(kColNT) void ntt_col_fwd_mp_kernel(NttLaunch a, NttLaunch b,
+                                                                uint32_t nb_a, int nprimes) {
+  if (blockIdx.x < nb_a)
+    col_fwd_tile_mp<TIn, r>(a, nprimes, blockIdx.x * kColNT + threadIdx.x, col_items(a),
+                            nb_a * kColNT);
+  else
+    col_fwd_tile_mp<TIn, r>(b, nprimes, (blockIdx.x - nb_a) * kColNT + threadIdx.x,
+                            col_items(b), (gridDim.x - nb_a) * kColNT);
+}
+
 template <typename TOut, int r, int NP, bool TR>
 __global__ __launch_bounds__(kColNT, 2) void ntt_col_inv_crt_kernel(NttLaunch a, CrtLaunch c) {
   const uint32_t items = (1u << (a.logL - r)) * (uint32_t)a.E;
@@ -183,8 +196,35 @@ static int launch_col(K kernel, const NttLaunch& a, int nprimes, hipStream_t s) 
   return launch(kernel, dim3((unsigned)blocks, nprimes), dim3(kColNT), 0, s, a);
 }
 
+static uint32_t col_blocks(const NttLaunch& a) {
+  const uint64_t blocks = (col_items(a) + (uint64_t)kColNT - 1) / kColNT;
+  return (uint32_t)(blocks > 8192 ? 8192 : blocks);
+}
+
+// CRT mode with several primes and inputs within L/2 rows: the first pass of
+// every prime from one read of the input (global knob col_fwd_mp).
+template <bool REDUCE>
+static bool col_mp_ok(const NttLaunch& a, int nprimes) {
+  return REDUCE && nprimes > 1 && a.in_prime_stride == 0 && 2 * a.nin <= (1 << a.logL) &&
+         global_knobs().col_fwd_mp;
+}
+
+// The multi-prime first pass of a (nb = 0) or of a and b.
+template <typename TIn>
+static int launch_col_mp(const NttLaunch& a, const NttLaunch* b, int nprimes, hipStream_t s) {
+  const uint32_t na = col_blocks(a), nb = b ? col_blocks(*b) : 0;
+  const NttLaunch& bb = b ? *b : a;
+  const dim3 grid(na + nb);
+  switch (a.split) {
+    case 2: return launch(ntt_col_fwd_mp_kernel<TIn, 2>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
+    case 3: return launch(ntt_col_fwd_mp_kernel<TIn, 3>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
+    default: return launch(ntt_col_fwd_mp_kernel<TIn, 4>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
+  }
+}
+
 template <typename TIn, bool REDUCE>
 static int launch_col_fwd_r(const NttLaunch& a, int nprimes, hipStream_t s) {
+  if (col_mp_ok<REDUCE>(a, nprimes)) return launch_col_mp<TIn>(a, nullptr, nprimes, s);
   switch (a.split) {
     case 2: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 2>, a, nprimes, s);
     case 3: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 3>, a, nprimes, s);
@@ -266,13 +306,11 @@ bool ntt_fwd_pair_ok(const NttLaunch& a, const NttLaunch& b) {
   return true;
 }
 
-static uint32_t col_blocks(const NttLaunch& a) {
-  const uint64_t blocks = (col_items(a) + (uint64_t)kColNT - 1) / kColNT;
-  return (uint32_t)(blocks > 8192 ? 8192 : blocks);
-}
 
 template <typename TIn, bool REDUCE>
 static int launch_col_pair(const NttLaunch& a, const NttLaunch& b, int nprimes, hipStream_t s) {
+  if (col_mp_ok<REDUCE>(a, nprimes) && col_mp_ok<REDUCE>(b, nprimes))
+    return launch_col_mp<TIn>(a, &b, nprimes, s);
   const uint32_t na = col_blocks(a), nb = col_blocks(b);
   const dim3 grid(na + nb, nprimes);
   switch (a.split) {

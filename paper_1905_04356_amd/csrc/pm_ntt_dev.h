@@ -668,6 +668,66 @@ __device__ __forceinline__ void col_fwd_items(const NttLaunch& a, int prime, uin
   }
 }
 
+// CRT mode: the first pass of every prime's transform from one read of the
+// input rows.  Item (j, g) loads rows j + u S (u < 2^(r-1): the inputs fill
+// at most L/2 rows) once, then for each prime reduces them, runs the pass
+// and writes that prime's rows u < keep; the per-prime launch reads the
+// same input once per prime.
+template <typename TIn, int r, int CV>
+__device__ __forceinline__ void col_fwd_items_mp(const NttLaunch& a, int nprimes, uint32_t it0,
+                                                 uint32_t it1, uint32_t step) {
+  constexpr int R = 1 << r, H = R / 2;
+  const uint32_t S = 1u << (a.logL - r);
+  const uint32_t E = (uint32_t)a.E, G = E / CV;
+  const TIn* in = (const TIn*)a.in;
+  const int keep = a.keep;
+  for (uint32_t it = it0; it < it1; it += step) {
+    const uint32_t j = it / G, e = (it - j * G) * CV;
+    Vec<TIn, CV> v[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const uint32_t row = j + u * S;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v[u].v[c] = 0;
+      if (row < (uint32_t)a.nin) v[u] = load_nt((const Vec<TIn, CV>*)(in + (size_t)row * E + e));
+    }
+#pragma unroll 1
+    for (int i = 0; i < nprimes; ++i) {
+      const PrimeConst& P = a.pc[i];
+      const uint32_t q = P.q;
+      uint32_t x[CV][R];
+#pragma unroll
+      for (int u = 0; u < H; ++u)
+#pragma unroll
+        for (int c = 0; c < CV; ++c) x[c][u] = reduce_u64((uint64_t)v[u].v[c], q, P.mu);
+      const Tw* tw = P.tw_fwd + a.tw_off[0];
+      Tw t[R - 1];
+#pragma unroll
+      for (int k = 0; k < R - 1; ++k) t[k] = tw[k * S + j];
+#pragma unroll
+      for (int c = 0; c < CV; ++c) butterflies<r, true, true>(x[c], t, q);
+      uint32_t* out = (uint32_t*)a.out + a.out_prime_stride * i;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (u >= 3 * R / 4 && u >= keep) break;
+        Vec<uint32_t, CV> y;
+#pragma unroll
+        for (int c = 0; c < CV; ++c) y.v[c] = x[c][u];
+        *(Vec<uint32_t, CV>*)(out + (size_t)(j + u * S) * E + e) = y;
+      }
+    }
+  }
+}
+
+template <typename TIn, int r>
+__device__ __forceinline__ void col_fwd_tile_mp(const NttLaunch& a, int nprimes, uint32_t it0,
+                                                uint32_t it1, uint32_t step) {
+  constexpr int CVMAX = sizeof(TIn) == 8 ? 2 : 4;
+  if (a.col_vec >= CVMAX) col_fwd_items_mp<TIn, r, CVMAX>(a, nprimes, it0, it1, step);
+  else if (a.col_vec >= 2) col_fwd_items_mp<TIn, r, 2>(a, nprimes, it0, it1, step);
+  else col_fwd_items_mp<TIn, r, 1>(a, nprimes, it0, it1, step);
+}
+
 template <typename TIn, bool REDUCE, int r>
 __device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint32_t it0,
                                              uint32_t it1, uint32_t step) {

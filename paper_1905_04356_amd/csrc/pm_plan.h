@@ -76,6 +76,7 @@ struct GlobalKnobs {
                          // log2 L <= wrap_tr_max_log: top t <= 2^j / wrap_top_div_tr
   int wrap_tr_max_log;
   int crt_fused;         // CRT mode: last inverse pass and reconstruction in one kernel (1)
+  int col_fwd_mp;        // CRT mode: each forward first pass for all primes from one read (1)
   int batch_single_min_log;  // batched calls: products of at least 2^this transform work
                              // ((mn + nk + mk) points primes) run as single products (0: none)
 };

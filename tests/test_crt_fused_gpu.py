@@ -1,8 +1,10 @@
 """CRT mode with the last inverse pass and the Chinese remaindering in one
-kernel: products and coefficient windows for 2 to 5 primes, 32- and 64-bit
-moduli, 3- and 4-stage first passes, full and three-quarter lengths, equal
-to the oracle coefficient by coefficient and to the separate kernels
-(global knob crt_fused = 0)."""
+kernel, and with each forward first pass computed for all primes from one
+read of the input: products and coefficient windows for 2 to 5 primes, 32-
+and 64-bit moduli, 3- and 4-stage first passes, full and three-quarter
+lengths, equal to the oracle coefficient by coefficient and to per-prime
+first passes and separate reconstruction (global knobs crt_fused = 0,
+col_fwd_mp = 0)."""
 from __future__ import annotations
 
 import json
@@ -36,7 +38,7 @@ def _restore_table():
 def load(split, fused, maxr=4):
     Bd.tune_load(json.dumps({"format": "pm-tune-1",
                              "global": {"split_min_log": 8, "crt_fused": fused,
-                                        "vdm_max_d": 0},
+                                        "col_fwd_mp": fused, "vdm_max_d": 0},
                              "entries": [{"knobs": {"split": split, "maxr": maxr}}]}))
 
 
