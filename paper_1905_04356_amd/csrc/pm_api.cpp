@@ -157,6 +157,13 @@ void fill_crt(const Plan& P, CrtLaunch* c) {
 
 namespace pm {
 
+// Lazy butterflies in the register-tile block steps (global knob lazy): direct
+// mode with 2q - 1 <= 0x7F7F7F7F, so that 4q < 2^32 and the pointwise
+// kernels' digit split (exact up to 0x7F7F7F7F) takes values below 2q.
+bool lazy_ok(const Plan& P) {
+  return P.mode == 0 && 2ull * P.q[0] - 1 <= 0x7F7F7F7Full && global_knobs().lazy;
+}
+
 // All launch descriptors of one product; A, B, C device pointers, ws the
 // product's workspace (laid out by make_plan).
 int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, uint8_t* ws,
@@ -193,6 +200,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   fb.in = B;
   fb.out = bhat;
   fa.keep = fb.keep = P.keep;
+  fa.lazy = fb.lazy = lazy_ok(P);
 
   PointwiseLaunch& pw = L->pw;
   pw.m = m; pw.n = n; pw.k = k; pw.L = P.npts;
@@ -223,6 +231,7 @@ int fill_product_launches(const Plan& P, const void* A, const void* B, void* C, 
   fill_ntt_launch(&ic, P.logL, m * k, P.nout, P.mode == 1 ? 4 : P.elem_bytes, true,
                   batched, P.kn);
   ic.keep = P.keep;
+  ic.lazy = lazy_ok(P);
   ic.out_lo = P.lo;
   ic.in = chat;
   ic.in_prime_stride = pstride;
@@ -878,6 +887,7 @@ pm_status eval_common(uint64_t p, int32_t role, int32_t rows, int32_t cols, int3
   NttLaunch a;
   memset(&a, 0, sizeof a);
   fill_ntt_launch(&a, P.logL, rows * cols, d, eb, false, false, P.kn);
+  a.lazy = lazy_ok(P);
   for (int i = 0; i < P.r; ++i) a.pc[i] = pc[i];
   a.in = X;
   a.out = Xe;

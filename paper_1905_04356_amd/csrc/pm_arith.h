@@ -69,6 +69,14 @@ __device__ __forceinline__ uint32_t mul_shoup_nq(uint32_t a, uint32_t w, uint32_
   return reduce_once((uint32_t)((uint64_t)qt * nq + (uint64_t)(a * w)), q);
 }
 
+// mul_shoup_nq without the final correction: a*w mod q in [0, 2q) for any
+// a < 2^32 (Harvey's lazy range).
+__device__ __forceinline__ uint32_t mul_shoup_lazy_nq(uint32_t a, uint32_t w, uint32_t wp,
+                                                      uint32_t nq) {
+  const uint32_t qt = __umulhi(a, wp);
+  return (uint32_t)((uint64_t)qt * nq + (uint64_t)(a * w));
+}
+
 // x mod q for any 64-bit x; mu = floor((2^64-1)/q).
 __device__ __forceinline__ uint32_t reduce_u64(uint64_t x, uint32_t q, uint64_t mu) {
   uint64_t qt = __umul64hi(x, mu);

@@ -36,6 +36,9 @@ struct NttLaunch {
                              // {4,4,3} (set for the thread count that runs the step)
   int lds_stride;            // 32-bit words between entries in LDS
   int blk_nt;                // single-product block step: threads (256 or 512)
+  int lazy;                  // register-tile block steps keep residues in [0, 2q) (moduli
+                             // with 2q - 1 <= 0x7F7F7F7F): their outputs feed the pointwise
+                             // kernels, or the inverse's last pass, which reduces them
   int keep;                  // split transforms: position blocks transformed, 2^split,
                              // or 3 2^split / 4 for a three-quarter transform (the
                              // column pass then writes, and its inverse reads,

@@ -128,6 +128,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
     a->tw_off[i] = i < PP.npass ? PP.tw_off[i] : 0;
   }
   a->keep = PP.split ? 1 << PP.split : 1;
+  a->lazy = 0;
   a->nin = nin;
   a->out_lo = 0;
   a->E = E;

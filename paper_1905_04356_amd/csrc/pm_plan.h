@@ -77,6 +77,7 @@ struct GlobalKnobs {
   int wrap_tr_max_log;
   int crt_fused;         // CRT mode: last inverse pass and reconstruction in one kernel (1)
   int col_fwd_mp;        // CRT mode: each forward first pass for all primes from one read (1)
+  int lazy;              // lazy butterflies in register-tile block steps where q allows (1)
   int batch_single_min_log;  // batched calls: products of at least 2^this transform work
                              // ((mn + nk + mk) points primes) run as single products (0: none)
 };

@@ -95,6 +95,7 @@ GlobalKnobs env_global() {
   g.crt_fused = env_int("PM_TUNE_CRT_FUSED", 1, 0, 1);
   g.batch_single_min_log = env_int("PM_TUNE_BATCH_SINGLE_MIN_LOG", 25, 0, 62);
   g.col_fwd_mp = env_int("PM_TUNE_COL_FWD_MP", 1, 0, 1);
+  g.lazy = env_int("PM_TUNE_LAZY", 1, 0, 1);
   return g;
 }
 
@@ -262,7 +263,7 @@ const KnobDef kGlobals[] = {
     {"wrap_min_work_log", 0, 62}, {"vdm_max_d", 0, 1 << 20}, {"min_wg", 0, 1 << 20},
     {"trunc34", 0, 2},            {"wrap_top_div_tr", 1, 1 << 20},
     {"wrap_tr_max_log", 0, 99},   {"crt_fused", 0, 1},
-    {"batch_single_min_log", 0, 62}, {"col_fwd_mp", 0, 1},
+    {"batch_single_min_log", 0, 62}, {"col_fwd_mp", 0, 1},     {"lazy", 0, 1},
 };
 
 int* knob_slot(Knobs& k, int i) {
@@ -276,7 +277,7 @@ int* global_slot(GlobalKnobs& g, int i) {
               &g.batch_pw_pipe_pts, &g.batch_direct_max, &g.batch_graph, &g.wrap_min_log,
               &g.wrap_top_div, &g.wrap_min_work_log, &g.vdm_max_d, &g.min_wg, &g.trunc34,
               &g.wrap_top_div_tr, &g.wrap_tr_max_log, &g.crt_fused,
-              &g.batch_single_min_log, &g.col_fwd_mp};
+              &g.batch_single_min_log, &g.col_fwd_mp, &g.lazy};
   return f[i];
 }
 

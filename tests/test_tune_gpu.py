@@ -180,3 +180,33 @@ def test_large_products_of_a_batch_run_as_single_products():
     for (m, n, k, d), C, ref in zip(shapes, results[0], refs):
         got = np.stack([C[:, 0, 0], C[:, m - 1, k - 1]]).astype(np.uint64)
         assert np.array_equal(got, np.asarray(ref).reshape(got.shape)), (m, n, k, d)
+
+
+def test_lazy_butterflies_change_no_result():
+    """Register-tile block steps with Harvey's lazy range ([0, 2q), moduli
+    with 2q - 1 <= 0x7F7F7F7F) and with canonical residues give the same
+    products, single and batched, with evaluations, at full and
+    three-quarter lengths, with LDS-resident tiles on one side (global knob
+    lazy)."""
+    p = P30
+    shapes = [(16, 16, 16, 1500), (8, 12, 4, 3000), (5, 7, 3, 2100), (16, 16, 8, 4096)]
+    As, Bs, refs = [], [], []
+    for i, (m, n, k, d) in enumerate(shapes):
+        A, B = operands(p, m, n, k, d, np.uint32, seed=90 + i)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        refs.append(O.polymatmul(p, A, B))
+    got = {}
+    for lazy in (1, 0):
+        Bd.tune_load(table({}, {"lazy": lazy}))
+        say(f"[tune] lazy={lazy}")
+        singles = [polymat.mul(p, a, b) for a, b in zip(As, Bs)]
+        batched = polymat.mul_batched(p, As, Bs)
+        ev = [polymat.mul_batched(p, [a], [b], A_evals=[polymat.evaluate(p, a, 0)])[0]
+              for a, b in zip(As, Bs)]
+        torch.cuda.synchronize()
+        got[lazy] = [c.cpu().numpy().astype(np.uint64) for c in singles + batched + ev]
+    for a, b in zip(got[0], got[1]):
+        assert np.array_equal(a, b)
+    for i, ref in enumerate(refs):
+        assert np.array_equal(got[1][i], ref), shapes[i]
