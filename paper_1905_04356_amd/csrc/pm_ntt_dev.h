@@ -851,15 +851,14 @@ __device__ __forceinline__ void butterflies_inv34(uint32_t* x, const Tw* t, uint
 // Last inverse pass of a split transform: item (j, g) reads rows j + u S of
 // the point-major buffer for CV consecutive entries and writes coefficients
 // out_lo .. out_lo + nin - 1 to rows 0 .. nin - 1 of the coefficient-major
-// output.  TR: a three-quarter transform (rows u < 3 2^r / 4 only).
-template <typename TOut, int r, int CV, bool TR = false>
-__device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uint32_t it0,
-                                              uint32_t it1, uint32_t step) {
+// output.  TR: a three-quarter transform (rows u < 3 2^r / 4 only).  LAZYIN:
+// the inputs lie in [0, 2q) and are reduced once on loading.
+template <typename TOut, int r, int CV, bool TR, bool LAZYIN>
+__device__ __forceinline__ void col_inv_items_t(const NttLaunch& a, int prime, uint32_t it0,
+                                                uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
   constexpr int KEEP = TR ? 3 * R / 4 : R;
   const PrimeConst& P = a.pc[prime];
-  // the register-tile block step before this pass left residues in [0, 2q)
-  const bool lazy_in = a.lazy && a.reg_kind;
   const uint32_t S = 1u << (a.logL - r);
   const uint32_t E = (uint32_t)a.E, G = E / CV;
   const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * prime;
@@ -872,7 +871,7 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
     for (int u = 0; u < KEEP; ++u) {
       const Vec<uint32_t, CV> v = *(const Vec<uint32_t, CV>*)(in + (size_t)(j + u * S) * E + e);
 #pragma unroll
-      for (int c = 0; c < CV; ++c) x[c][u] = lazy_in ? reduce_once(v.v[c], P.q) : v.v[c];
+      for (int c = 0; c < CV; ++c) x[c][u] = LAZYIN ? reduce_once(v.v[c], P.q) : v.v[c];
     }
     Tw t[R - 1];
 #pragma unroll
@@ -893,6 +892,15 @@ __device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uin
       }
     }
   }
+}
+
+template <typename TOut, int r, int CV, bool TR = false>
+__device__ __forceinline__ void col_inv_items(const NttLaunch& a, int prime, uint32_t it0,
+                                              uint32_t it1, uint32_t step) {
+  // the register-tile block step before this pass left residues in [0, 2q);
+  // the flag is uniform, so the canonical case carries no reduction
+  if (a.lazy && a.reg_kind) col_inv_items_t<TOut, r, CV, TR, true>(a, prime, it0, it1, step);
+  else col_inv_items_t<TOut, r, CV, TR, false>(a, prime, it0, it1, step);
 }
 
 // f(integral_constant<int, U>) for U in the sequence, unrolled whatever the
