@@ -143,11 +143,14 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   // A single product with few entries takes fewer entries per workgroup,
   // down to one, while its launch would have fewer than min_wg workgroups:
   // such transforms are latency-bound (a full-size register tile is kept).
-  if (!batched && G.min_wg > 0) {
+  // Unsplit lengths have their own bound: fewer entries per workgroup there
+  // also narrows the vectors of the LDS tile's loads.
+  const int min_wg = PP.split ? G.min_wg : G.min_wg_unsplit;
+  if (!batched && min_wg > 0) {
     const int nt_log = blk_nt == 512 ? 9 : 8;
     const bool full_reg = PP.split && kn.reg_tile && a->blk_log + eb == nt_log + 5;
     const long zb = PP.split ? 1L << PP.split : 1;
-    while (eb > 0 && !full_reg && ((E + (1L << eb) - 1) >> eb) * zb < G.min_wg) --eb;
+    while (eb > 0 && !full_reg && ((E + (1L << eb) - 1) >> eb) * zb < min_wg) --eb;
   }
   a->eb_log = eb;
   // entries move between HBM and LDS in vectors of V consecutive residues

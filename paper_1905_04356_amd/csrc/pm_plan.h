@@ -68,8 +68,9 @@ struct GlobalKnobs {
   int wrap_top_div;      // ... top t <= 2^j / wrap_top_div
   int wrap_min_work_log; // ... (mn + nk + mk) 2^j >= 2^wrap_min_work_log
   int vdm_max_d;         // CRT-mode u32 products with d <= this go through Vandermonde
-  int min_wg;            // single-product transforms: fewer entries per workgroup
-                         // while a launch has fewer workgroups than this (0: off)
+  int min_wg;            // single-product split transforms: fewer entries per
+                         // workgroup while a launch has fewer workgroups than this (0: off)
+  int min_wg_unsplit;    // the same for transforms of lengths below the split
   int trunc34;           // three-quarter transforms: 0 off, 1 on (the wrapped form
                          // keeps tops t <= 2^j / wrap_top_div_tr), 2 on, never wrapped
   int wrap_top_div_tr;   // wrapped form where a three-quarter transform applies and

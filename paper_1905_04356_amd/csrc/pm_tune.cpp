@@ -89,6 +89,7 @@ GlobalKnobs env_global() {
   g.wrap_min_work_log = 25;
   g.vdm_max_d = env_int("PM_TUNE_VDM_MAXD", 64, 0, 1 << 20);
   g.min_wg = env_int("PM_TUNE_MIN_WG", 512, 0, 1 << 20);
+  g.min_wg_unsplit = env_int("PM_TUNE_MIN_WG_UNSPLIT", 256, 0, 1 << 20);
   g.trunc34 = env_int("PM_TUNE_TRUNC34", 1, 0, 2);
   g.wrap_top_div_tr = 8;
   g.wrap_tr_max_log = 13;
@@ -264,6 +265,7 @@ const KnobDef kGlobals[] = {
     {"trunc34", 0, 2},            {"wrap_top_div_tr", 1, 1 << 20},
     {"wrap_tr_max_log", 0, 99},   {"crt_fused", 0, 1},
     {"batch_single_min_log", 0, 62}, {"col_fwd_mp", 0, 1},     {"lazy", 0, 1},
+    {"min_wg_unsplit", 0, 1 << 20},
 };
 
 int* knob_slot(Knobs& k, int i) {
@@ -277,7 +279,7 @@ int* global_slot(GlobalKnobs& g, int i) {
               &g.batch_pw_pipe_pts, &g.batch_direct_max, &g.batch_graph, &g.wrap_min_log,
               &g.wrap_top_div, &g.wrap_min_work_log, &g.vdm_max_d, &g.min_wg, &g.trunc34,
               &g.wrap_top_div_tr, &g.wrap_tr_max_log, &g.crt_fused,
-              &g.batch_single_min_log, &g.col_fwd_mp, &g.lazy};
+              &g.batch_single_min_log, &g.col_fwd_mp, &g.lazy, &g.min_wg_unsplit};
   return f[i];
 }
 

@@ -123,6 +123,26 @@ def test_three_quarter_transforms_are_planned_for_whole_products_in_the_band():
     assert w.wrap_log2_len == 0 and w.num_points == 3072
 
 
+def test_every_global_knob_is_accepted():
+    glob = {"lds_log": 14, "split_min_log": 11, "blk_pad": 0, "batch_tile_log": 14,
+            "batch_pw_work": 8192, "batch_pw_pipe_pts": 16, "batch_direct_max": 2,
+            "batch_graph": 1, "wrap_min_log": 10, "wrap_top_div": 4, "wrap_min_work_log": 25,
+            "vdm_max_d": 64, "min_wg": 512, "min_wg_unsplit": 256, "trunc34": 1,
+            "wrap_top_div_tr": 8, "wrap_tr_max_log": 13, "crt_fused": 1,
+            "batch_single_min_log": 25, "col_fwd_mp": 1, "lazy": 1}
+    B.tune_load(table(glob=glob))
+    assert B.tune_info()[0] == 0
+    # the defaults, so plans are those of no table
+    def plan():
+        x = B.pm_plan(P31, 64, 64, 32, 4096, 4)
+        return [list(v) if f == "primes" else v
+                for f, v in ((f[0], getattr(x, f[0])) for f in x._fields_)]
+
+    c2 = plan()
+    B.tune_load("")
+    assert plan() == c2
+
+
 @pytest.mark.parametrize("bad", [
     "{",                                                             # not JSON
     "[]",                                                            # not an object
@@ -137,6 +157,7 @@ def test_three_quarter_transforms_are_planned_for_whole_products_in_the_band():
     table(glob={"wrap_top_div": 0}),                                 # bad global
     table(glob={"nope": 1}),
     table(glob={"trunc34": 3}),
+    table(glob={"min_wg_unsplit": -1}),
     table([{"knobs": {}}]) + "x",                                    # trailing text
 ])
 def test_invalid_tables_are_rejected_and_the_current_one_stays(bad):
