@@ -114,7 +114,9 @@ typedef struct pm_plan_info {
  * products of a batched call run on the single-product kernels), the
  * wrapped-length and three-quarter-length rules, whether CRT-mode products
  * fold the reconstruction into the last inverse pass and read their input
- * once for all primes.  No choice changes a result.  The table is JSON (format "pm-tune-1", written by
+ * once for all primes, lazy butterfly ranges for small moduli, and how far
+ * small single products spread over workgroups.  No choice changes a
+ * result.  The table is JSON (format "pm-tune-1", written by
  * the tuning driver paper_1905_04356_amd/tune.py); it is read on first use
  * from $PM_TUNE_TABLE if set (empty: none), else from tune_table.json beside
  * libpm.so; a missing or invalid file leaves the defaults (PM_TUNE_*
