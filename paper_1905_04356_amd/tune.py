@@ -12,7 +12,9 @@ log2 L, shape bucket). For each bucket a representative product is timed
 operands) under its current knobs, then one knob at a time is changed
 (coordinate descent over the admissible values), keeping a change when it
 is faster by more than `--margin`. A bucket gets an entry only when its best
-knobs beat the defaults by that margin. Global knobs of the batched path
+knobs beat the defaults by that margin. Knob values that most buckets of
+one length chose become a whole-length entry for that length's other
+shapes, if they speed up shapes outside the grid. Global knobs of the batched path
 (pointwise work per tile, block-tile size) are tuned on the batched workload
 (512 products of the batched shape rule), timed as whole batched calls.
 
@@ -259,6 +261,47 @@ def tune_batch_globals(entries, margin, quick, glob0=None):
     return glob, best, base
 
 
+def length_fallbacks(entries, report, margin, rounds=3):
+    """Entries for whole lengths (direct primes below 2^30): where at least
+    3/4 of the buckets tuned at one log2 L chose the same values of some
+    knobs, those values become an entry for that length's other buckets
+    (placed after the bucket entries, since the first match wins), kept only
+    if they speed up two shapes outside the grid at that length (timed in
+    interleaved rounds, median)."""
+    groups = {}
+    for rec in report:
+        if rec["_key"][0] == 0:
+            groups.setdefault(rec["_key"][1], []).append(rec)
+    out = []
+    for logL, recs in sorted(groups.items()):
+        if len(recs) < 4:
+            continue
+        counts = {}
+        for rec in recs:
+            for kv in rec["_knobs"].items():
+                counts[kv] = counts.get(kv, 0) + 1
+        common = {k: v for (k, v), c in counts.items() if 4 * c >= 3 * len(recs)}
+        if not common:
+            continue
+        d = recs[0]["shape"][3]
+        prods = [Product(P_LT30, m, n, k, d) for (m, n, k) in ((32, 32, 32), (8, 64, 8))]
+        fb = {"prime_class": CLASS_NAME[0], "log2_len": logL, "knobs": common}
+        times = {0: [], 1: []}
+        for _ in range(rounds):
+            for with_fb in (0, 1):
+                B.tune_load(table_json(entries + out + ([fb] if with_fb else [])))
+                times[with_fb].append(sum(pr.time_us() for pr in prods))
+        t0, t1 = sorted(times[0])[rounds // 2], sorted(times[1])[rounds // 2]
+        kept = t1 < t0 * (1 - margin)
+        say(f"[tune] L=2^{logL} fallback {json.dumps(common)}: other shapes {t0:.1f} -> "
+            f"{t1:.1f} us{'' if kept else ' (not kept)'}")
+        if kept:
+            out.append(dict(fb, us=round(t1, 2), default_us=round(t0, 2)))
+        del prods
+        torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default=DEFAULT_OUT)
@@ -278,7 +321,8 @@ def main(argv=None):
         if any(e["_key"] == key for e in report):
             continue
         knobs, t_best, t_default, tried = tune_bucket(prod, args.margin, args.passes, args.reps)
-        rec = {"_key": key, "shape": [m, n, k, d], "p": p, "candidates": tried,
+        rec = {"_key": key, "_knobs": knobs or {}, "shape": [m, n, k, d], "p": p,
+               "candidates": tried,
                "us": round(t_best, 2), "default_us": round(t_default, 2)}
         say(f"[tune] {CLASS_NAME[key[0]]} L=2^{key[1]} {m}x{n}x{k} d={d}: "
             f"default {t_default:.1f} us, best {t_best:.1f} us "
@@ -290,6 +334,7 @@ def main(argv=None):
             entries.append(e)
         del prod
         torch.cuda.empty_cache()
+    entries += length_fallbacks(entries, report, args.margin)
     gmin, rep = tune_min_wg(entries, args.margin)
     for knob, (t0, t1) in rep.items():
         say(f"[tune] {knob} {gmin.get(knob, 'default')}: small products {t0:.1f} -> {t1:.1f} us")
