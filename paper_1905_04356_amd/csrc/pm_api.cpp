@@ -157,11 +157,14 @@ void fill_crt(const Plan& P, CrtLaunch* c) {
 
 namespace pm {
 
-// Lazy butterflies in the register-tile block steps (global knob lazy): direct
-// mode with 2q - 1 <= 0x7F7F7F7F, so that 4q < 2^32 and the pointwise
+// Lazy butterflies in the register-tile block steps (global knob lazy): every
+// prime with 2q - 1 <= 0x7F7F7F7F, so that 4q < 2^32 and the pointwise
 // kernels' digit split (exact up to 0x7F7F7F7F) takes values below 2q.
 bool lazy_ok(const Plan& P) {
-  return P.mode == 0 && 2ull * P.q[0] - 1 <= 0x7F7F7F7Full && global_knobs().lazy;
+  if (!global_knobs().lazy) return false;
+  for (int i = 0; i < P.r; ++i)
+    if (2ull * P.q[i] - 1 > 0x7F7F7F7Full) return false;
+  return true;
 }
 
 // All launch descriptors of one product; A, B, C device pointers, ws the

@@ -100,11 +100,11 @@ __global__ __launch_bounds__(kColNT) void ntt_col_fwd_mp_kernel(NttLaunch a, Ntt
                             col_items(b), (gridDim.x - nb_a) * kColNT);
 }
 
-template <typename TOut, int r, int NP, bool TR>
+template <typename TOut, int r, int NP, bool TR, bool LAZYIN>
 __global__ __launch_bounds__(kColNT, 2) void ntt_col_inv_crt_kernel(NttLaunch a, CrtLaunch c) {
   const uint32_t items = (1u << (a.logL - r)) * (uint32_t)a.E;
-  col_inv_crt_items<TOut, r, NP, TR>(a, c, blockIdx.x * kColNT + threadIdx.x, items,
-                                     gridDim.x * kColNT);
+  col_inv_crt_items<TOut, r, NP, TR, LAZYIN>(a, c, blockIdx.x * kColNT + threadIdx.x, items,
+                                             gridDim.x * kColNT);
 }
 
 template <typename TOut, int r>
@@ -454,17 +454,24 @@ bool ntt_inv_crt_ok(const NttLaunch& a, int nprimes, int out_elem_bytes) {
   return nprimes >= 2 && nprimes <= 5;
 }
 
-template <typename TOut, int r, int NP>
-static int launch_inv_crt_r(const NttLaunch& a, const CrtLaunch& c, hipStream_t s) {
+template <typename TOut, int r, int NP, bool LAZYIN>
+static int launch_inv_crt_rl(const NttLaunch& a, const CrtLaunch& c, hipStream_t s) {
   const uint64_t items = ((uint64_t)1 << (a.logL - r)) * (uint64_t)a.E;
   uint64_t blocks = (items + kColNT - 1) / kColNT;
   if (blocks > 8192) blocks = 8192;
   const bool tr = a.keep < (1 << r);
   if (tr)
-    return launch(ntt_col_inv_crt_kernel<TOut, r, NP, true>, dim3((unsigned)blocks),
+    return launch(ntt_col_inv_crt_kernel<TOut, r, NP, true, LAZYIN>, dim3((unsigned)blocks),
                   dim3(kColNT), 0, s, a, c);
-  return launch(ntt_col_inv_crt_kernel<TOut, r, NP, false>, dim3((unsigned)blocks),
+  return launch(ntt_col_inv_crt_kernel<TOut, r, NP, false, LAZYIN>, dim3((unsigned)blocks),
                 dim3(kColNT), 0, s, a, c);
+}
+
+// the register-tile block step before the pass leaves lazy residues in [0, 2q)
+template <typename TOut, int r, int NP>
+static int launch_inv_crt_r(const NttLaunch& a, const CrtLaunch& c, hipStream_t s) {
+  if (a.lazy && a.reg_kind) return launch_inv_crt_rl<TOut, r, NP, true>(a, c, s);
+  return launch_inv_crt_rl<TOut, r, NP, false>(a, c, s);
 }
 
 template <typename TOut, int NP>

@@ -916,8 +916,9 @@ __device__ __forceinline__ void static_for(std::integer_sequence<int, U...>, F&&
 // of each prime's evaluations (one entry per item) and writes the
 // coefficients mod p, rebuilt from the NP residues in registers, straight to
 // the output C[row][e] (c.out), so the residues never go through HBM.
-// TR: a three-quarter transform.
-template <typename TOut, int r, int NP, bool TR>
+// TR: a three-quarter transform.  LAZYIN: the inputs lie in [0, 2q) and are
+// reduced once on loading.
+template <typename TOut, int r, int NP, bool TR, bool LAZYIN>
 __device__ __forceinline__ void col_inv_crt_items(const NttLaunch& a, const CrtLaunch& c,
                                                   uint32_t it0, uint32_t it1, uint32_t step) {
   constexpr int R = 1 << r;
@@ -939,7 +940,10 @@ __device__ __forceinline__ void col_inv_crt_items(const NttLaunch& a, const CrtL
       const uint32_t* in = (const uint32_t*)a.in + a.in_prime_stride * i;
       uint32_t x[R];
 #pragma unroll
-      for (int u = 0; u < KEEP; ++u) x[u] = in[(size_t)(j + u * S) * E + e];
+      for (int u = 0; u < KEEP; ++u) {
+        x[u] = in[(size_t)(j + u * S) * E + e];
+        if (LAZYIN) x[u] = reduce_once(x[u], P.q);
+      }
       const Tw* tw = P.tw_inv + a.tw_off[0];
       Tw t[R - 1];
 #pragma unroll

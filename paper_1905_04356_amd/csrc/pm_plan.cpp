@@ -100,6 +100,19 @@ static const uint32_t kCrtPrimes[] = {
     167772161u,   //   5 * 2^25 + 1
 };
 
+// Primes q with 2q - 1 <= 0x7F7F7F7F (below 2^30) and 2^20 | q-1, largest
+// first: their transforms run lazy butterflies (residues kept in [0, 2q)).
+static const uint32_t kCrtPrimesLazy[] = {
+    1053818881u,  // 1005 * 2^20 + 1
+    1051721729u,  // 1003 * 2^20 + 1
+    1045430273u,  //  997 * 2^20 + 1
+    1012924417u,  //  483 * 2^21 + 1
+    1007681537u,  //  961 * 2^20 + 1
+    1004535809u,  //  479 * 2^21 + 1
+    998244353u,   //  119 * 2^23 + 1
+    985661441u,   //  235 * 2^22 + 1
+};
+
 // split: stages of the column pass (0: none; kept below logL by the
 // planner); maxr: most stages per later pass.
 PassPlan make_pass_plan(int logL, int split, int maxr) {
@@ -240,6 +253,19 @@ static int make_plan_core(uint64_t p, int m, int n, int k, int da, int db, int l
       if (big_cmp(prod, bound) > 0) break;
     }
     if (big_cmp(prod, bound) <= 0) return PM_EUNSUPPORTED;
+    // As many primes below 2^30 suffice for most products: take those, whose
+    // transforms keep lazy residues.
+    Big lprod = big_from(1);
+    uint32_t lq[kMaxPrimes];
+    int lr = 0;
+    for (uint32_t q : kCrtPrimesLazy) {
+      if (lr == P.r) break;
+      if (v2_u64(q - 1) < logL) continue;
+      lq[lr++] = q;
+      lprod = big_mul(lprod, q);
+    }
+    if (lr == P.r && big_cmp(lprod, bound) > 0)
+      for (int i = 0; i < lr; ++i) P.q[i] = lq[i];
   }
   const int pclass = P.mode == 1 ? kClassCrt : P.q[0] < (1u << 30) ? kClassDirectLt30
                                                                      : kClassDirectGe30;

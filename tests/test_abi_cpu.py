@@ -74,6 +74,25 @@ def test_plan_crt_uses_the_fewest_primes(p, n, d, eb):
     assert math.prod(qs[:-1]) <= bound  # no prime is superfluous
 
 
+def test_plan_crt_prefers_primes_below_2_30_at_the_same_count():
+    """Primes with 2q - 1 <= 0x7F7F7F7F let the transforms keep lazy residues;
+    the planner takes them when as many suffice, else the larger primes."""
+    lazy = lambda qs: all(2 * q - 1 <= 0x7F7F7F7F for q in qs)  # noqa: E731
+    p60 = (1 << 61) - 1
+    c4 = B.pm_plan(p60, 32, 32, 32, 2048, 8)
+    qs = [c4.primes[i] for i in range(c4.num_primes)]
+    assert c4.num_primes == 5 and lazy(qs) and math.prod(qs) > crt_bound(p60, 32, 2048)
+    u32 = B.pm_plan(4294967291, 64, 64, 32, 4096, 4)
+    qs = [u32.primes[i] for i in range(u32.num_primes)]
+    assert u32.num_primes == 3 and lazy(qs)
+    # bound 32 (p-1)^2 ~ 2^61: two primes below 2^30 give 2^59.9, two of
+    # 31 bits 2^62.0, so the larger primes stay
+    p28 = 268435399
+    w = B.pm_plan(p28, 4, 4, 4, 8, 4)
+    qs = [w.primes[i] for i in range(w.num_primes)]
+    assert w.num_primes == 2 and not lazy(qs) and math.prod(qs) > crt_bound(p28, 4, 8)
+
+
 def test_plan_length_is_next_power_of_two():
     for d in (1, 2, 3, 4, 5, 16, 17, 33, 4096, 4097, 8192):
         info = B.pm_plan(2013265921, 2, 2, 2, d, 4)

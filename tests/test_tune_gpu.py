@@ -210,3 +210,39 @@ def test_lazy_butterflies_change_no_result():
         assert np.array_equal(a, b)
     for i, ref in enumerate(refs):
         assert np.array_equal(got[1][i], ref), shapes[i]
+
+
+@pytest.mark.parametrize("crt_fused", [1, 0])
+def test_lazy_butterflies_in_crt_mode(crt_fused):
+    """CRT products take primes below 2^30 where as many suffice, so their
+    register-tile block steps keep lazy residues too: lazy and canonical
+    butterflies give the same products (single and batched, 60-bit u64 and
+    32-bit u32 moduli, with the reconstruction folded into the last inverse
+    pass or separate, full and three-quarter lengths), equal to the oracle."""
+    p60, p32 = I.seeded_prime_60(4), 4294967291
+    cases = [(p60, 8, 8, 8, 1500, np.uint64), (p60, 5, 7, 3, 2100, np.uint64),
+             (p32, 8, 16, 4, 3000, np.uint32), (p32, 3, 5, 7, 1100, np.uint32)]
+    As, Bs, refs = {}, {}, {}
+    for i, (p, m, n, k, d, dt) in enumerate(cases):
+        info = Bd.pm_plan(p, m, n, k, d, 8 if dt == np.uint64 else 4)
+        qs = [info.primes[j] for j in range(info.num_primes)]
+        assert info.mode == 1 and all(2 * q - 1 <= 0x7F7F7F7F for q in qs), qs
+        A, B = operands(p, m, n, k, d, dt, seed=120 + i)
+        As[i], Bs[i] = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        refs[i] = O.polymatmul(p, A, B)
+    got = {}
+    for lazy in (1, 0):
+        Bd.tune_load(table({}, {"lazy": lazy, "crt_fused": crt_fused}))
+        say(f"[tune] crt lazy={lazy} crt_fused={crt_fused}")
+        outs = []
+        for p in (p60, p32):
+            idx = [i for i, c in enumerate(cases) if c[0] == p]
+            outs += [polymat.mul(p, As[i], Bs[i]) for i in idx]
+            outs += polymat.mul_batched(p, [As[i] for i in idx], [Bs[i] for i in idx])
+        torch.cuda.synchronize()
+        got[lazy] = [c.cpu().numpy().astype(np.uint64) for c in outs]
+    for a, b in zip(got[0], got[1]):
+        assert np.array_equal(a, b)
+    order = [0, 1, 0, 1, 2, 3, 2, 3]
+    for c, i in zip(got[1], order):
+        assert np.array_equal(c, refs[i]), cases[i]
