@@ -261,6 +261,16 @@ def tune_batch_globals(entries, margin, quick, glob0=None):
     return glob, best, base
 
 
+def common_knobs(chosen: list[dict]) -> dict:
+    """Knob values that at least 3/4 of the buckets chose ({} for a bucket
+    that kept the defaults)."""
+    counts = {}
+    for c in chosen:
+        for kv in c.items():
+            counts[kv] = counts.get(kv, 0) + 1
+    return {k: v for (k, v), n in counts.items() if 4 * n >= 3 * len(chosen)}
+
+
 def length_fallbacks(entries, report, margin, rounds=3):
     """Entries for whole lengths (direct primes below 2^30): where at least
     3/4 of the buckets tuned at one log2 L chose the same values of some
@@ -276,11 +286,7 @@ def length_fallbacks(entries, report, margin, rounds=3):
     for logL, recs in sorted(groups.items()):
         if len(recs) < 4:
             continue
-        counts = {}
-        for rec in recs:
-            for kv in rec["_knobs"].items():
-                counts[kv] = counts.get(kv, 0) + 1
-        common = {k: v for (k, v), c in counts.items() if 4 * c >= 3 * len(recs)}
+        common = common_knobs([rec["_knobs"] for rec in recs])
         if not common:
             continue
         d = recs[0]["shape"][3]

@@ -212,3 +212,14 @@ def test_committed_table_parses():
     B.tune_load(open(path).read())
     entries, source = B.tune_info()
     assert entries >= 1 and source == 2
+
+
+def test_whole_length_entries_take_the_knobs_most_buckets_chose():
+    from paper_1905_04356_amd.tune import common_knobs
+    big = {"blk_nt": 512, "blk_tile_log": 14}
+    assert common_knobs([big, big, dict(big, maxr=3), dict(big, pw_small_lds=0)]) == big
+    # one bucket of four kept the defaults: 3/4 still agree
+    assert common_knobs([big, big, big, {}]) == big
+    # two of four: no whole-length entry
+    assert common_knobs([big, big, {}, {"split": 3}]) == {}
+    assert common_knobs([{"split": 3}, {"split": 3}, {"split": 3}, {"split": 2}]) == {"split": 3}
