@@ -14,7 +14,10 @@ instead. The host loop:
   slot and its footprint and stamps its requests' completion times;
 * while a stream is free, takes ready requests in arrival order as long as
   their footprint (workspace + output bytes) fits the free HBM budget, and
-  launches them as one pm_mul_batched call on that stream.
+  launches them as one pm_mul_batched call on that stream. A request of at
+  least `solo_work` transform work runs in a launch of its own, so that the
+  small requests around it do not wait for it (all of a batch's outputs
+  complete together); it overlaps them on another stream instead.
 
 Requests that arrive while others run therefore join the next launch and
 overlap them on the device. Latency = completion (observed by the host) -
@@ -48,6 +51,12 @@ class PoolItem:
     B_eval: torch.Tensor | None
     footprint: int          # workspace + output bytes of one product
     wraps: bool = False     # pm_mul takes the wrapped form (no evaluations kept)
+
+    @property
+    def work(self) -> int:
+        """Transform work (m n + n k + m k) L, L = 2^ceil(log2(2d - 1))."""
+        L = 1 << max(0, (2 * self.d - 2).bit_length())
+        return (self.m * self.n + self.n * self.k + self.m * self.k) * L
 
 
 def make_pool(p: int, seed: int, count: int, device, with_evals: bool = True,
@@ -94,10 +103,12 @@ class Server:
     logic pass a host-side double instead."""
 
     def __init__(self, p: int, pool: list[PoolItem], budget_bytes: int, streams: int = 4,
-                 max_batch: int = 256, keep=(), launcher=None, warmup_s: float = 0.0):
+                 max_batch: int = 256, keep=(), launcher=None, warmup_s: float = 0.0,
+                 solo_work: int = 1 << 25):
         self.p, self.pool, self.budget = p, pool, budget_bytes
         self.warmup_s = warmup_s
         self.max_batch = max_batch
+        self.solo_work = solo_work
         self.nslots = streams
         self.launch = launcher or self._gpu_launch
         self.streams = None
@@ -163,9 +174,13 @@ class Server:
             inflight = still
             launched = False
             while free and ready:
-                ids, fp = [], 0
+                ids, fp, solo = [], 0, False
                 while ready and len(ids) < self.max_batch:
                     it = self.pool[items[ready[0]]]
+                    big = it.work >= self.solo_work
+                    if ids and (big or solo):
+                        break          # large requests run alone
+                    solo = big
                     if used + fp + it.footprint > self.budget and ids:
                         break
                     if used + fp + it.footprint > self.budget and inflight:

@@ -65,3 +65,23 @@ def test_max_batch_respected():
     srv, stats, launches = run([1], arrivals, items, budget=10 ** 6, slots=1, service_s=0.001,
                                max_batch=8)
     assert max(len(fps) for _, fps in launches) <= 8
+
+
+def test_large_requests_run_alone_in_fifo_order():
+    big = S.PoolItem(128, 128, 128, 6000, None, None, None, None, 10)    # 3 128^2 2^14
+    pool = fake_pool([10, 10]) + [big]
+    assert big.work >= 1 << 25 > pool[0].work
+    launches = []
+
+    def launcher(si, its):
+        launches.append([it.m for it in its])
+        return FakeEvent(time.perf_counter() + 0.002), [None] * len(its)
+
+    arrivals = [0.0005 * i for i in range(120)]
+    items = [2 if i % 7 == 3 else i % 2 for i in range(120)]
+    srv = S.Server(0, pool, 10 ** 9, streams=2, launcher=launcher)
+    stats = srv.run(arrivals, items)
+    assert stats["requests"] == 120
+    assert srv.admitted == list(range(120))
+    assert all(len(b) == 1 for b in launches if 128 in b)
+    assert any(len(b) > 1 for b in launches)            # the small ones still batch
