@@ -68,6 +68,15 @@ def garner_ops(r):
     return 11 * r * (r - 1) // 2 + 12 * r
 
 
+def butterfly_ops(plan):
+    """VALU operations per forward and inverse butterfly: Shoup's butterflies
+    on canonical residues (10, 11), or Harvey's lazy ones (8, 10) where every
+    prime of the plan is below 2^30."""
+    if all(2 * plan.primes[i] - 1 <= 0x7F7F7F7F for i in range(plan.num_primes)):
+        return 8, 10
+    return OPS_FWD_BUTTERFLY, OPS_INV_BUTTERFLY
+
+
 def kernel_work(kind, plan, p, m, n, k, d, eb, crt_folded=False):
     """Algorithmic work of all launches of one kernel kind in one product:
     (bytes, ops). crt_folded: CRT mode with the reconstruction done by the
@@ -75,20 +84,21 @@ def kernel_work(kind, plan, p, m, n, k, d, eb, crt_folded=False):
     L = 1 << plan.log2_len
     r = plan.num_primes
     logL = plan.log2_len
+    of, oi = butterfly_ops(plan)
     if kind == "ntt_fwd":
         E = m * n + n * k
         byts = eb * d * E + 4 * L * E * r
-        ops = OPS_FWD_BUTTERFLY * (L // 2) * logL * E * r
+        ops = of * (L // 2) * logL * E * r
         return byts, ops
     if kind == "ntt_inv":
         E = m * k
         if crt_folded:
             byts = 4 * L * E * r + eb * (2 * d - 1) * E
-            ops = OPS_INV_BUTTERFLY * (L // 2) * logL * E * r + garner_ops(r) * (2 * d - 1) * E
+            ops = oi * (L // 2) * logL * E * r + garner_ops(r) * (2 * d - 1) * E
             return byts, ops
         out_b = eb if plan.mode == 0 else 4
         byts = 4 * L * E * r + out_b * (2 * d - 1) * E * r
-        ops = OPS_INV_BUTTERFLY * (L // 2) * logL * E * r
+        ops = oi * (L // 2) * logL * E * r
         return byts, ops
     if kind == "pointwise":
         byts = 4 * L * (m * n + n * k + m * k) * r
@@ -142,6 +152,30 @@ def path_roofline(kernels, plan, device_ms):
         floor_s += max(t_hbm, t_ops)
     return {"floor_us": floor_s * 1e6, "measured_us": device_ms * 1e3,
             "frac": floor_s * 1e6 / (device_ms * 1e3)}
+
+
+def product_floor_us(plan, m, n, k, d, eb=4):
+    """The path floor of one product (as path_roofline) at the points its
+    plan evaluates: 3L/4 for three-quarter transforms, 2^j for the wrapped
+    form (its short top product left out); butterflies at Harvey's lazy
+    counts (8 forward, 10 inverse) where every prime is below 2^30; in CRT
+    mode the reconstruction is taken as folded into the last inverse pass
+    (its operations there, no residue arrays)."""
+    logL = plan.wrap_log2_len or plan.log2_len
+    L = 1 << logL
+    pts = L if plan.wrap_log2_len else plan.num_points
+    r = plan.num_primes
+    of, oi = butterfly_ops(plan)
+    bfly = (L // 2) * logL * pts / L          # butterflies per transform
+    ef, ei, ep = m * n + n * k, m * k, m * n + n * k + m * k
+    hbm, valu = HBM_PEAK_GBS * 1e3, VALU_PEAK_TOPS * 1e6   # bytes, ops per us
+    cnt = (2 * d - 1) * ei
+    garner = garner_ops(r) * cnt if plan.mode == 1 else 0
+    t = max((eb * d * ef + 4 * pts * ef * r) / hbm, of * bfly * ef * r / valu)
+    t += max((4 * pts * ei * r + eb * cnt) / hbm, (oi * bfly * ei * r + garner) / valu)
+    pw_ops = 32.0 * pts * m * n * k * r / (INT8_MFMA_PEAK_TOPS * 1e6) if plan.pointwise == 1 else 0
+    t += max(4 * pts * ep * r / hbm, pw_ops)
+    return t
 
 
 def cpu_baseline(p, A, B, m, n, k, d, target_s):
@@ -480,7 +514,21 @@ def bench_batched(steps, warmup, seed=3, count=512, p=998244353, settle_s=1.0):
             "speedup_vs_one_per_call": t_s / t_b, "sum_mnkd": work,
             "batched_workspace_GB": batched_ws / 1e9, "steps": steps, "warmup": warmup,
             "batched_kernel_ms": {kk: v[0] / steps for kk, v in kb.items() if v[1]},
-            "one_per_call_kernel_ms": {kk: v[0] / steps for kk, v in ks.items() if v[1]}}
+            "one_per_call_kernel_ms": {kk: v[0] / steps for kk, v in ks.items() if v[1]},
+            "path": batch_path(p, shapes, sum(v[0] for v in kb.values()) / steps,
+                               sum(v[0] for v in ks.values()) / steps)}
+
+
+def batch_path(p, shapes, device_ms_batched, device_ms_single):
+    """The sum of the products' path floors against the device time of one
+    batched call and of the single calls."""
+    from paper_1905_04356_amd import binding as Bd
+    floor_us = sum(product_floor_us(Bd.pm_plan(p, m, n, k, d, 4), m, n, k, d)
+                   for (m, n, k, d) in shapes)
+    return {"floor_ms": floor_us / 1e3, "frac": floor_us / 1e3 / device_ms_batched,
+            "frac_one_per_call": floor_us / 1e3 / device_ms_single,
+            "floor": "per product: sum over kernel kinds of max(algorithmic bytes at "
+                     "8 TB/s, operations at the unit's peak), at the plan's points"}
 
 
 KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing

@@ -83,3 +83,24 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_product_floor_matches_the_path_roofline_and_counts_lazy_butterflies():
+    from paper_1905_04356_amd import binding as Bd
+    p, m, n, k, d = 2013265921, 64, 64, 32, 4096
+    plan = Bd.pm_plan(p, m, n, k, d, 4)
+    kernels = {}
+    for kind in ("ntt_fwd", "pointwise", "ntt_inv"):
+        b, o = bench.kernel_work(kind, plan, p, m, n, k, d, 4)
+        kernels[kind] = {"algorithmic_bytes": b, "ops": o}
+    path = bench.path_roofline(kernels, plan, 1.0)
+    assert abs(bench.product_floor_us(plan, m, n, k, d) - path["floor_us"]) < 1e-6
+    assert bench.butterfly_ops(plan) == (10, 11)          # q >= 2^30: canonical
+    lazy = Bd.pm_plan(998244353, m, n, k, d, 4)
+    assert bench.butterfly_ops(lazy) == (8, 10)
+    # three-quarter points lower the floor's bytes
+    tr = Bd.pm_plan(998244353, 16, 16, 16, 1500, 4)
+    assert tr.num_points == 3 << (tr.log2_len - 2)
+    full = bench.product_floor_us(tr, 16, 16, 16, 1500)
+    assert 0 < full < bench.product_floor_us(Bd.pm_plan(998244353, 16, 16, 16, 2040, 4),
+                                             16, 16, 16, 2040)
