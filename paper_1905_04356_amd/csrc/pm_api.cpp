@@ -1169,6 +1169,9 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
   size_t lds[kBatchPhases] = {};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
     const Plan& P = plans[i];
+    // the phase kernels run column passes of 2 to 4 stages (run_batch sends
+    // products with 5 to the single-product kernels)
+    if (P.kn.split > 4) return PM_EUNSUPPORTED;
     int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i],
                                    true);
     if (st != PM_OK) return st;
@@ -1353,24 +1356,37 @@ int run_batch(uint64_t p, int eb, const std::vector<Plan>& plans,
   // best of 18..30 on 512 products of the batched shape rule: 77 products
   // as single launches, 56.8 -> 55.5 ms per call; more singles lose to the
   // shared launches, 62.6 ms at 18).
-  if (G.batch_single_min_log > 0) {
-    std::vector<Plan> bp, rp;
-    std::vector<uint64_t> bo, ro;
-    std::vector<pm_product> bpr, rpr;
-    for (int i = 0; i < count; ++i) {
-      const bool big = work_log2(plans[i]) >= (double)G.batch_single_min_log;
-      (big ? bp : rp).push_back(plans[i]);
-      (big ? bo : ro).push_back(offs[i]);
-      (big ? bpr : rpr).push_back(prods[i]);
+  //
+  // The phase kernels run column passes of at most 4 stages: a product whose
+  // plan has 5 and that stays in the phases runs a 4-stage first pass there
+  // (same points and workspace, another pass structure).
+  std::vector<Plan> bp, rp;
+  std::vector<uint64_t> bo, ro;
+  std::vector<pm_product> bpr, rpr;
+  bool clamped = false;
+  for (int i = 0; i < count; ++i) {
+    const bool big = G.batch_single_min_log > 0 &&
+                     work_log2(plans[i]) >= (double)G.batch_single_min_log;
+    Plan q = plans[i];
+    if (!big && q.kn.split > 4) {
+      q.kn.split = 4;
+      q.keep = q.trunc ? 3 << 2 : 1 << 4;
+      clamped = true;
     }
-    if (!bp.empty()) {
-      st = run_direct(bp, bo, bpr.data(), ws, s);
-      if (st != PM_OK || rp.empty()) return st;
-      if ((int)rp.size() <= G.batch_direct_max) return run_direct(rp, ro, rpr.data(), ws, s);
-      return run_batch_phases(p, eb, rp, ro, lay, rpr.data(), ws, ws_bytes, s);
-    }
+    (big ? bp : rp).push_back(q);
+    (big ? bo : ro).push_back(offs[i]);
+    (big ? bpr : rpr).push_back(prods[i]);
   }
-  return run_batch_phases(p, eb, plans, offs, lay, prods, ws, ws_bytes, s);
+  if (clamped) {
+    st = prepare_plans(rp.data(), rp.size(), s);
+    if (st != PM_OK) return st;
+  }
+  if (!bp.empty()) {
+    st = run_direct(bp, bo, bpr.data(), ws, s);
+    if (st != PM_OK || rp.empty()) return st;
+    if ((int)rp.size() <= G.batch_direct_max) return run_direct(rp, ro, rpr.data(), ws, s);
+  }
+  return run_batch_phases(p, eb, rp, ro, lay, rpr.data(), ws, ws_bytes, s);
 }
 
 // The phase launches of a batch (graph replay from the second occurrence of

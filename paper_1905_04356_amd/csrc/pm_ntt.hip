@@ -160,6 +160,7 @@ void fill_ntt_launch(NttLaunch* a, int logL, int E, int nin, int io_bytes, bool 
   // column items move at most 16 bytes per row access
   int cv = inverse ? kn.colvec_inv : kn.colvec_fwd;
   if (cv == 3) cv = 2;
+  if (PP.split >= 5 && cv > 2) cv = 2;  // 32 residues per entry
   // inputs longer than L/2 take the one-entry full-load column pass
   if (!inverse && 2 * nin > (1 << logL)) cv = 1;
   while (cv > 1 && ((E % cv) != 0 || cv * io_bytes > 16)) cv >>= 1;
@@ -222,6 +223,7 @@ static int launch_col_mp(const NttLaunch& a, const NttLaunch* b, int nprimes, hi
   switch (a.split) {
     case 2: return launch(ntt_col_fwd_mp_kernel<TIn, 2>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
     case 3: return launch(ntt_col_fwd_mp_kernel<TIn, 3>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
+    case 5: return launch(ntt_col_fwd_mp_kernel<TIn, 5>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
     default: return launch(ntt_col_fwd_mp_kernel<TIn, 4>, grid, dim3(kColNT), 0, s, a, bb, na, nprimes);
   }
 }
@@ -232,6 +234,7 @@ static int launch_col_fwd_r(const NttLaunch& a, int nprimes, hipStream_t s) {
   switch (a.split) {
     case 2: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 2>, a, nprimes, s);
     case 3: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 3>, a, nprimes, s);
+    case 5: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 5>, a, nprimes, s);
     default: return launch_col(ntt_col_fwd_kernel<TIn, REDUCE, 4>, a, nprimes, s);
   }
 }
@@ -241,6 +244,7 @@ static int launch_col_inv_r(const NttLaunch& a, int nprimes, hipStream_t s) {
   switch (a.split) {
     case 2: return launch_col(ntt_col_inv_kernel<TOut, 2>, a, nprimes, s);
     case 3: return launch_col(ntt_col_inv_kernel<TOut, 3>, a, nprimes, s);
+    case 5: return launch_col(ntt_col_inv_kernel<TOut, 5>, a, nprimes, s);
     default: return launch_col(ntt_col_inv_kernel<TOut, 4>, a, nprimes, s);
   }
 }
@@ -320,6 +324,7 @@ static int launch_col_pair(const NttLaunch& a, const NttLaunch& b, int nprimes, 
   switch (a.split) {
     case 2: return launch(ntt_col_fwd_pair_kernel<TIn, REDUCE, 2>, grid, dim3(kColNT), 0, s, a, b, na);
     case 3: return launch(ntt_col_fwd_pair_kernel<TIn, REDUCE, 3>, grid, dim3(kColNT), 0, s, a, b, na);
+    case 5: return launch(ntt_col_fwd_pair_kernel<TIn, REDUCE, 5>, grid, dim3(kColNT), 0, s, a, b, na);
     default: return launch(ntt_col_fwd_pair_kernel<TIn, REDUCE, 4>, grid, dim3(kColNT), 0, s, a, b, na);
   }
 }

@@ -778,10 +778,11 @@ __device__ __forceinline__ void col_fwd_items_mp(const NttLaunch& a, int nprimes
   }
 }
 
+// Passes of 5 stages take at most 2 entries per item (32 residues each).
 template <typename TIn, int r>
 __device__ __forceinline__ void col_fwd_tile_mp(const NttLaunch& a, int nprimes, uint32_t it0,
                                                 uint32_t it1, uint32_t step) {
-  constexpr int CVMAX = sizeof(TIn) == 8 ? 2 : 4;
+  constexpr int CVMAX = sizeof(TIn) == 8 || r >= 5 ? 2 : 4;
   if (a.col_vec >= CVMAX) col_fwd_items_mp<TIn, r, CVMAX>(a, nprimes, it0, it1, step);
   else if (a.col_vec >= 2) col_fwd_items_mp<TIn, r, 2>(a, nprimes, it0, it1, step);
   else col_fwd_items_mp<TIn, r, 1>(a, nprimes, it0, it1, step);
@@ -794,8 +795,13 @@ __device__ __forceinline__ void col_fwd_tile(const NttLaunch& a, int prime, uint
     col_fwd_items<TIn, REDUCE, r, 1, false>(a, prime, it0, it1, step);
     return;
   }
-  if (a.col_vec == 4) col_fwd_items<TIn, REDUCE, r, 4>(a, prime, it0, it1, step);
-  else if (a.col_vec == 2) col_fwd_items<TIn, REDUCE, r, 2>(a, prime, it0, it1, step);
+  if constexpr (r < 5) {
+    if (a.col_vec == 4) {
+      col_fwd_items<TIn, REDUCE, r, 4>(a, prime, it0, it1, step);
+      return;
+    }
+  }
+  if (a.col_vec >= 2) col_fwd_items<TIn, REDUCE, r, 2>(a, prime, it0, it1, step);
   else col_fwd_items<TIn, REDUCE, r, 1>(a, prime, it0, it1, step);
 }
 
@@ -975,8 +981,13 @@ __device__ __forceinline__ void col_inv_crt_items(const NttLaunch& a, const CrtL
 template <typename TOut, int r, bool TR>
 __device__ __forceinline__ void col_inv_tile_t(const NttLaunch& a, int prime, uint32_t it0,
                                                uint32_t it1, uint32_t step) {
-  if (a.col_vec == 4) col_inv_items<TOut, r, 4, TR>(a, prime, it0, it1, step);
-  else if (a.col_vec == 2) col_inv_items<TOut, r, 2, TR>(a, prime, it0, it1, step);
+  if constexpr (r < 5) {
+    if (a.col_vec == 4) {
+      col_inv_items<TOut, r, 4, TR>(a, prime, it0, it1, step);
+      return;
+    }
+  }
+  if (a.col_vec >= 2) col_inv_items<TOut, r, 2, TR>(a, prime, it0, it1, step);
   else col_inv_items<TOut, r, 1, TR>(a, prime, it0, it1, step);
 }
 

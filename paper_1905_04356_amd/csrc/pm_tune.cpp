@@ -54,7 +54,7 @@ int env_int(const char* name, int dflt, int lo, int hi) {
 
 Knobs env_knobs() {
   Knobs k;
-  k.split = env_int("PM_TUNE_NTT_SPLIT", 4, 0, 4);
+  k.split = env_int("PM_TUNE_NTT_SPLIT", 4, 0, 5);
   k.maxr = env_int("PM_TUNE_NTT_MAXR", 4, 2, 4);
   k.blk_nt = env_int("PM_TUNE_NTT_BLK_NT", 256, 256, 512) > 256 ? 512 : 256;
   k.blk_tile_log = env_int("PM_TUNE_NTT_BLK_TILE_LOG", 13, 11, 15);
@@ -251,7 +251,7 @@ struct KnobDef {
   int lo, hi;
 };
 const KnobDef kKnobs[] = {
-    {"split", 0, 4},        {"maxr", 2, 4},        {"blk_nt", 256, 512},
+    {"split", 0, 5},        {"maxr", 2, 4},        {"blk_nt", 256, 512},
     {"blk_tile_log", 11, 15}, {"colvec_fwd", 1, 4}, {"colvec_inv", 1, 4},
     {"reg_tile", 0, 1},     {"pointwise", 0, 1},   {"pw_small_lds", 0, 1 << 30},
     {"pw_pipe", -1, 2},     {"blk_nt_inv", 0, 512}, {"blk_tile_log_inv", 0, 15},

@@ -46,7 +46,7 @@ P_GE30 = 2013265921       # 15 2^27 + 1
 # together (threads and tile size of a block step); the defaults are among
 # the values.
 MOVES = [
-    [{"split": 4}, {"split": 3}],
+    [{"split": 4}, {"split": 3}, {"split": 5}],
     [{"maxr": 4}, {"maxr": 3}],
     [{"blk_nt": 256, "blk_tile_log": 13}, {"blk_nt": 512, "blk_tile_log": 14},
      {"blk_nt": 512, "blk_tile_log": 13}, {"blk_nt": 256, "blk_tile_log": 12},
@@ -276,7 +276,7 @@ def length_fallbacks(entries, report, margin, rounds=3):
     3/4 of the buckets tuned at one log2 L chose the same values of some
     knobs, those values become an entry for that length's other buckets
     (placed after the bucket entries, since the first match wins), kept only
-    if they speed up two shapes outside the grid at that length (timed in
+    if they speed up three shapes outside the grid at that length (timed in
     interleaved rounds, median)."""
     groups = {}
     for rec in report:
@@ -290,7 +290,8 @@ def length_fallbacks(entries, report, margin, rounds=3):
         if not common:
             continue
         d = recs[0]["shape"][3]
-        prods = [Product(P_LT30, m, n, k, d) for (m, n, k) in ((32, 32, 32), (8, 64, 8))]
+        prods = [Product(P_LT30, m, n, k, d)
+                 for (m, n, k) in ((32, 32, 32), (8, 64, 8), (128, 32, 32))]
         fb = {"prime_class": CLASS_NAME[0], "log2_len": logL, "knobs": common}
         times = {0: [], 1: []}
         for _ in range(rounds):

@@ -61,7 +61,7 @@ def test_entries_match_by_class_length_and_bucket_first_match_wins():
 
 
 @pytest.mark.parametrize("knobs", [{"maxr": 2, "split": 3}, {"maxr": 3}, {"split": 0},
-                                   {"split": 2, "maxr": 4}])
+                                   {"split": 2, "maxr": 4}, {"split": 5}])
 def test_pass_structure_knobs_keep_the_twiddle_count(knobs):
     """Any pass structure needs sum_i S_i (2^r_i - 1) = L - 1 twiddles per
     direction (the sum telescopes), so the table size of a length does not
@@ -158,6 +158,7 @@ def test_every_global_knob_is_accepted():
     table(glob={"nope": 1}),
     table(glob={"trunc34": 3}),
     table(glob={"min_wg_unsplit": -1}),
+    table([{"knobs": {"split": 6}}]),
     table([{"knobs": {}}]) + "x",                                    # trailing text
 ])
 def test_invalid_tables_are_rejected_and_the_current_one_stays(bad):

@@ -52,6 +52,8 @@ TABLES = [
     {"blk_tile_log": 12, "colvec_fwd": 1, "pw_pipe": 2, "pw_small_lds": 0},
     {"blk_tile_log": 14, "blk_nt": 512, "maxr": 3, "pw_pipe": 0, "pw_small_lds": 0},
     {"split": 0, "maxr": 4, "pw_pipe": 1, "pw_small_lds": 0},
+    {"split": 5, "colvec_fwd": 4, "colvec_inv": 4},
+    {"split": 5, "maxr": 3, "blk_nt": 512, "blk_tile_log": 14, "colvec_fwd": 1},
 ]
 GLOBAL = {"batch_tile_log": 13, "batch_pw_work": 2048, "batch_direct_max": 0,
           "batch_graph": 0}
@@ -246,3 +248,31 @@ def test_lazy_butterflies_in_crt_mode(crt_fused):
     order = [0, 1, 0, 1, 2, 3, 2, 3]
     for c, i in zip(got[1], order):
         assert np.array_equal(c, refs[i]), cases[i]
+
+
+@pytest.mark.parametrize("knobs", [{"split": 5}, {"split": 5, "blk_nt": 512, "blk_tile_log": 14}])
+def test_five_stage_column_passes_at_long_lengths(knobs):
+    """Column passes of 5 stages at L = 2^14 and 2^15 (full and three-quarter
+    lengths), the block steps after them on 9 and 10 stages; single calls and
+    a batched call (which runs such products on the single-product kernels),
+    equal to the oracle."""
+    shapes = [(P30, 2, 3, 2, 5000), (P31, 3, 2, 2, 7000), (P30, 2, 2, 3, 9000)]
+    Bd.tune_load(table(knobs, {"batch_direct_max": 0}))
+    As, Bs, refs = [], [], []
+    for idx, (p, m, n, k, d) in enumerate(shapes):
+        info = Bd.pm_plan(p, m, n, k, d, 4)
+        assert info.tune_entry == 0 and info.log2_len in (14, 15)
+        say(f"[tune] split 5: {m}x{n}x{k} d={d} L=2^{info.log2_len} pts={info.num_points}")
+        A, B = operands(p, m, n, k, d, np.uint32, seed=130 + idx)
+        refs.append(O.polymatmul(p, A, B))
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        C = polymat.mul(p, As[-1], Bs[-1])
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy().astype(np.uint64), refs[-1]), idx
+    for p in (P30, P31):
+        ids = [i for i, s in enumerate(shapes) if s[0] == p]
+        outs = polymat.mul_batched(p, [As[i] for i in ids], [Bs[i] for i in ids])
+        torch.cuda.synchronize()
+        for i, C in zip(ids, outs):
+            assert np.array_equal(C.cpu().numpy().astype(np.uint64), refs[i]), i
