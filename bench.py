@@ -869,6 +869,32 @@ def bench_serving(seconds, seed=5, rate=2000.0, pool_size=64, p=998244353,
     return out
 
 
+def valu_probe(blocks=8192, iters=4096, reps=5):
+    """The measured issue rate of 32-bit high multiplies (pm_probe_valu:
+    independent chains, blocks x 256 threads x iters x 8 lane-ops per
+    launch), against the VALU peak the ALU rooflines use; best of `reps`
+    event-timed launches."""
+    import torch
+
+    from paper_1905_04356_amd import binding as Bd
+    out = torch.empty(blocks * 256, dtype=torch.uint32, device="cuda")
+    st = torch.cuda.current_stream()
+    sp = int(st.cuda_stream)
+    Bd._check(Bd.pm_probe_valu(blocks, iters, out.data_ptr(), sp), "pm_probe_valu")
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        Bd._check(Bd.pm_probe_valu(blocks, iters, out.data_ptr(), sp), "pm_probe_valu")
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    rate = blocks * 256.0 * iters * 8 / best
+    return {"instruction": "v_mul_hi_u32, 8 independent chains per thread",
+            "lane_ops_per_s": rate, "frac_of_peak": rate / (VALU_PEAK_TOPS * 1e12),
+            "peak_lane_ops_per_s": VALU_PEAK_TOPS * 1e12, "blocks": blocks, "iters": iters}
+
+
 def progress(msg):
     """A progress line on stderr (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -1228,6 +1254,7 @@ def main():
         out["serving"] = bench_serving(args.serving_seconds, warmup_s=args.serving_warmup,
                                        sweep=args.serving_sweep, sweep_seconds=10.0)
         torch.cuda.empty_cache()
+    out["valu_probe"] = valu_probe()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, A, B, m, n, k, d, args.cpu_seconds)

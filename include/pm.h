@@ -394,6 +394,18 @@ pm_status pm_mul_batched_u64(uint64_t p, int32_t count, const pm_product* prods,
 pm_status pm_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int32_t elem_bytes,
                      void* stream);
 
+/* Measurement of the VALU issue rate that bounds the transforms (Section 2,
+ * "Polynomial multiplication": the butterflies' modular products; here
+ * 32-bit high multiplies, the instruction Shoup's products are built from).
+ * Launches `blocks` workgroups of 256 threads; each thread runs 8
+ * independent chains of `iters` high multiplies, blocks * 256 * iters * 8
+ * lane-ops in all, and writes one word to out[blockIdx * 256 + thread]
+ * (device memory of at least blocks * 1024 bytes, 4-byte aligned, owned by
+ * the caller).  The caller times the launch on `stream` (events around
+ * it).  PM_EINVAL for a NULL or misaligned out, blocks outside 1..2^20 or
+ * iters 0; PM_EDEVICE if the launch fails.  Asynchronous on `stream`. */
+pm_status pm_probe_valu(uint32_t blocks, uint32_t iters, void* out, void* stream);
+
 /* Count the elements of X (count residues of elem_bytes bytes, device
  * memory) that are >= p and write the count to *n_bad (host pointer).  This
  * call synchronises `stream`.  workspace: at least 8 bytes of device memory,

@@ -34,7 +34,7 @@ EXPORTS = ("pm_status_str", "pm_abi_version", "pm_plan", "pm_workspace_bytes",
            "pm_profile_pause", "pm_mbasis_workspace_bytes", "pm_mbasis_u32",
            "pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
            "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
-           "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32")
+           "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32", "pm_probe_valu")
 
 KERNEL_KINDS = ("ntt_fwd", "pointwise", "ntt_inv", "crt", "batched", "vdm_eval", "vdm_interp",
                 "geo")
@@ -147,9 +147,10 @@ def lib():
     L.pm_tune_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.pm_geo_workspace_bytes.argtypes = [u64, i32, i32, i32, i32, ctypes.POINTER(u64)]
     L.pm_mul_geo_u32.argtypes = [u32, i32, i32, i32, i32, vp, vp, vp, vp, u64, vp]
+    L.pm_probe_valu.argtypes = [u32, u32, vp, vp]
     for name in ("pm_tables_attach", "pm_tables_bytes", "pm_tables_reset", "pm_tables_info",
                  "pm_neg_mod", "pm_debug_fail_alloc", "pm_mul_noalloc", "pm_tune_load",
-                 "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32"):
+                 "pm_tune_info", "pm_geo_workspace_bytes", "pm_mul_geo_u32", "pm_probe_valu"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("pm_plan", "pm_workspace_bytes", "pm_mul_u32", "pm_mul_u64",
                  "pm_batched_workspace_bytes", "pm_mul_batched_u32", "pm_mul_batched_u64",
@@ -209,6 +210,10 @@ def pm_tables_info() -> tuple[int, int, int]:
     _check(lib().pm_tables_info(ctypes.byref(a), ctypes.byref(u), ctypes.byref(t)),
            "pm_tables_info")
     return a.value, u.value, t.value
+
+
+def pm_probe_valu(blocks, iters, out, stream) -> int:
+    return lib().pm_probe_valu(blocks, iters, out, stream)
 
 
 def pm_neg_mod(p, X, Y, count, elem_bytes, stream) -> int:

@@ -825,6 +825,15 @@ pm_status pm_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int32_t
              : PM_EDEVICE;
 }
 
+pm_status pm_probe_valu(uint32_t blocks, uint32_t iters, void* out, void* stream) {
+  if (!out || blocks == 0 || blocks > (1u << 20) || iters == 0 || ((uintptr_t)out & 3))
+    return PM_EINVAL;
+  return launch_probe_mulhi((uint32_t*)out, blocks, iters, 0x9E3779B1u, (hipStream_t)stream) ==
+                 hipSuccess
+             ? PM_OK
+             : PM_EDEVICE;
+}
+
 pm_status pm_check_residues(uint64_t p, const void* X, uint64_t count, int32_t elem_bytes,
                             uint64_t* n_bad, void* workspace, void* stream) {
   if (!X || !n_bad || !workspace || (elem_bytes != 4 && elem_bytes != 8)) return PM_EINVAL;

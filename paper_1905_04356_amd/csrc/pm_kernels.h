@@ -109,6 +109,8 @@ int launch_pointwise(const PointwiseLaunch& a, int nprimes, hipStream_t s);
 int launch_unwrap(void* C, uint64_t count, uint64_t off, uint64_t p, int elem_bytes,
                   hipStream_t s);
 // Y[i] = (p - X[i]) mod p for i < count (elements of elem_bytes bytes).
+int launch_probe_mulhi(uint32_t* out, uint32_t blocks, uint32_t iters, uint32_t m,
+                       hipStream_t s);
 int launch_neg_mod(uint64_t p, const void* X, void* Y, uint64_t count, int elem_bytes,
                    hipStream_t s);
 int launch_pointwise_mfma(const PointwiseLaunch& a, int nprimes, hipStream_t s);

@@ -175,3 +175,25 @@ def test_neg_mod(p, dtype):
     polymat.neg(p, t, out=t)               # in place
     torch.cuda.synchronize()
     assert np.array_equal(t.cpu().numpy().astype(np.uint64), want)
+
+
+def test_valu_probe_computes_its_chains():
+    """pm_probe_valu's output is the xor of its 8 chains x <- floor(x m / 2^32)
+    (m = 0x9E3779B1), so the launch is checked exactly against the host."""
+    from paper_1905_04356_amd import binding as Bd
+    blocks, iters, m = 3, 7, 0x9E3779B1
+    out = torch.zeros(blocks * 256, dtype=torch.int64, device="cuda").view(torch.uint32)
+    st = torch.cuda.current_stream()
+    assert Bd.pm_probe_valu(blocks, iters, out.data_ptr(), int(st.cuda_stream)) == Bd.PM_OK
+    torch.cuda.synchronize()
+    got = out[:blocks * 256].cpu().numpy().astype(np.uint64)
+    for t in range(256):
+        acc = 0
+        for c in range(8):
+            x = (t + 0x9E3779B9 * (c + 1)) & 0xFFFFFFFF
+            for _ in range(iters):
+                x = (x * m) >> 32
+            acc ^= x
+        assert all(int(got[b * 256 + t]) == acc for b in range(blocks)), t
+    assert Bd.pm_probe_valu(0, 1, out.data_ptr(), 0) == Bd.PM_EINVAL
+    assert Bd.pm_probe_valu(1, 0, out.data_ptr(), 0) == Bd.PM_EINVAL
