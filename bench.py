@@ -744,7 +744,7 @@ def summarize_counters(root, workload, steps_pmc=3):
         clock = g / dur[name] / 1e9 if dur[name] else float("nan")
         rl = role(name)
         opb = (c["SQ_INSTS_VALU"] * 64 / steps / bfly[rl]) if rl and bfly.get(rl) else None
-        short = name.split("(")[0].replace("void ", "")
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         md.append(f"| `{short}` | {len(disp[name]) / steps:.0f} | {c['SQ_WAVES'] / steps:.0f} | "
                   f"{c['SQ_INSTS_VALU'] / steps:.3g} | {c['SQ_INSTS_LDS'] / steps:.3g} | "
                   f"{c['SQ_LDS_BANK_CONFLICT'] / steps:.3g} | {g / steps:.3g} | {clock:.2f} | "
@@ -779,7 +779,8 @@ def summarize_batched(root, batched_calls, single_rounds):
     def table(sel, per):
         agg = collections.defaultdict(lambda: [0, 0.0])
         for r in sel:
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            name = (r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+                    .replace("void ", ""))
             agg[name][0] += 1
             agg[name][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
         out = ["| kernel | calls | ms per call or round |", "|---|---|---|"]
