@@ -532,7 +532,8 @@ def batch_path(p, shapes, device_ms_batched, device_ms_single):
 
 
 KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing
-    ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_block_kernel<true", "ntt_fwd"),
+    ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_col_fwd_mp_kernel", "ntt_fwd"),
+    ("ntt_col_inv_crt_kernel", "ntt_inv"), ("ntt_block_kernel<true", "ntt_fwd"),
     ("ntt_col_fwd_pair_kernel", "ntt_fwd"), ("ntt_block_regc_pair_kernel", "ntt_fwd"),
     ("ntt_block_regc_kernel<true", "ntt_fwd"), ("ntt_block_regc_kernel<false", "ntt_inv"),
     ("ntt_fwd_kernel", "ntt_fwd"), ("pointwise", "pointwise"),
@@ -623,9 +624,11 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     for name, v in write.items():
         if kind_of(name) and wscale:
             traffic[kind_of(name)] += v * wscale / pmc_total_steps
+    wflag = "" if workload == "c2" else f" --workload {workload}"
     cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
-              "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 --settle-seconds 0")
+              "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 --settle-seconds 0"
+              + wflag)
     md = [f"# Kernel profile: {workload}", "",
           "Command (from the repository root, on one MI355X):", "", "```", cmd_st, "```", "",
           f"`avg us` is rocprofv3's --stats average over all calls ({warmup_stats} warm-up "
@@ -647,7 +650,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
                   "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 "
-                  "--settle-seconds 0")
+                  "--settle-seconds 0" + wflag)
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
         md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
