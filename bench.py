@@ -534,6 +534,7 @@ def batch_path(p, shapes, device_ms_batched, device_ms_single):
 KERNEL_KIND_OF = (  # rocprofv3 kernel-name fragment -> kind of the C ABI's timing
     ("ntt_col_fwd_kernel", "ntt_fwd"), ("ntt_col_fwd_mp_kernel", "ntt_fwd"),
     ("ntt_col_inv_crt_kernel", "ntt_inv"), ("ntt_block_kernel<true", "ntt_fwd"),
+    ("ntt_fwd_pair_kernel", "ntt_fwd"), ("ntt_block_pair_kernel", "ntt_fwd"),
     ("ntt_col_fwd_pair_kernel", "ntt_fwd"), ("ntt_block_regc_pair_kernel", "ntt_fwd"),
     ("ntt_block_regc_kernel<true", "ntt_fwd"), ("ntt_block_regc_kernel<false", "ntt_inv"),
     ("ntt_fwd_kernel", "ntt_fwd"), ("pointwise", "pointwise"),
