@@ -6,7 +6,8 @@ the residual shape of Algorithm PM-Basis (a basis of degree <= c times the
 series truncated at order c + d), prefixes (truncated products), single
 coefficients, the top coefficient, inputs longer than half the transform
 length in both the unsplit (L < 2^11) and split (L >= 2^11) transforms, CRT
-moduli in 32 and 64 bits, and full-size sampled entries.
+moduli in 32 and 64 bits, full-size sampled entries, and windows under
+5-stage first passes.
 """
 from __future__ import annotations
 
@@ -134,3 +135,22 @@ def test_middle_pm_basis_size_sampled():
     rows = O.middle_entries(p, A, B, c, d, pairs)
     for s, (i, j) in enumerate(pairs):
         assert np.array_equal(C[:, i, j].astype(np.uint64), rows[s]), (i, j)
+
+
+@pytest.mark.parametrize("case", [
+    (2, 3, 2, 1024, 2048, 1024, 1024),   # L = 2^11, input longer than L/2
+    (2, 2, 2, 4097, 8192, 4096, 4096),   # L = 2^13
+    (1, 2, 2, 6000, 9000, 5000, 4000),   # L = 2^14, ragged window
+])
+@pytest.mark.parametrize("p,dtype", [(P30, np.uint32), ((1 << 61) - 1, np.uint64)])
+def test_middle_under_five_stage_first_passes(p, dtype, case):
+    """Coefficient windows with a 5-stage first pass (tuning knob split 5):
+    inputs longer than half the transform take the one-entry full-load
+    column pass; direct and CRT moduli."""
+    import json
+    Bd.tune_load(json.dumps({"format": "pm-tune-1", "entries": [{"knobs": {"split": 5}}]}))
+    try:
+        check(p, *case, seed=4, dtype=dtype)
+    finally:
+        torch.cuda.synchronize()
+        Bd.tune_load(None)
