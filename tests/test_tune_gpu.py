@@ -105,19 +105,23 @@ def test_products_under_forced_knobs_equal_the_oracle(ti):
             assert np.array_equal(C.cpu().numpy().astype(np.uint64), refs[i]), (ti, i)
 
 
-def test_evaluations_under_one_table_feed_products_under_another():
+@pytest.mark.parametrize("ta,tb,tc", [
+    ({"split": 3, "maxr": 2}, {"split": 4, "maxr": 4, "reg_tile": 0}, {"split": 2, "maxr": 3}),
+    ({"split": 5}, {"split": 4}, {"split": 5, "maxr": 3}),
+])
+def test_evaluations_under_one_table_feed_products_under_another(ta, tb, tc):
     """The point order of evaluations does not depend on the pass structure."""
     p, m, n, k, d = P31, 8, 16, 4, 1800
     A, B = operands(p, m, n, k, d, np.uint32, seed=50)
     tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     ref = O.polymatmul(p, A, B)
-    Bd.tune_load(table({"split": 3, "maxr": 2}))
+    Bd.tune_load(table(ta))
     Ae = polymat.evaluate(p, tA, 0)
     torch.cuda.synchronize()
-    Bd.tune_load(table({"split": 4, "maxr": 4, "reg_tile": 0}))
+    Bd.tune_load(table(tb))
     Be = polymat.evaluate(p, tB, 1)
     torch.cuda.synchronize()
-    Bd.tune_load(table({"split": 2, "maxr": 3}))
+    Bd.tune_load(table(tc))
     (C,) = polymat.mul_batched(p, [tA], [tB], A_evals=[Ae], B_evals=[Be])
     torch.cuda.synchronize()
     assert np.array_equal(C.cpu().numpy().astype(np.uint64), ref)
