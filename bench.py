@@ -626,7 +626,7 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
         if kind_of(name) and wscale:
             traffic[kind_of(name)] += v * wscale / pmc_total_steps
     wflag = "" if workload == "c2" else f" --workload {workload}"
-    cmd_st = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/st -o st -- "
+    cmd_st = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {root}/st -o st -- "
               f"python3 bench.py --steps {steps_stats} --warmup {warmup_stats} --no-cpu-baseline "
               "--no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 --settle-seconds 0"
               + wflag)
@@ -648,12 +648,12 @@ def summarize_profiles(root, steps_stats, warmup_stats, steps_pmc, workload, out
     md += ["", "## HBM traffic (rocprofv3 --pmc)", "",
            "Commands:", "", "```"]
     for sub, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
-        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
+        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d {root}/{sub} "
                   f"-o {sub} -- python3 bench.py --steps {steps_pmc - 1} --warmup 1 "
                   "--no-cpu-baseline --no-batched --no-middle --no-pmbasis --no-extra --serving-seconds 0 "
                   "--settle-seconds 0" + wflag)
     for sub, c in (("cf", "FETCH_SIZE"), ("cw", "WRITE_SIZE")):
-        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/{sub} "
+        md.append(f"timeout -s KILL 90 rocprofv3 --pmc {c} --output-format csv -d {root}/{sub} "
                   f"-o {sub} -- python3 bench.py --calibration-copy")
     md += ["```", "",
            f"Calibration: a plain copy of 3 x 1 GiB reads back FETCH_SIZE x {fscale:.3f} and "

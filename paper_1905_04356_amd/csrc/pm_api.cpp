@@ -1178,8 +1178,8 @@ int build_batch(const std::vector<Plan>& plans, const std::vector<uint64_t>& off
   size_t lds[kBatchPhases] = {};  // unused: LDS is tracked per segment
   for (int i = 0; i < count; ++i) {
     const Plan& P = plans[i];
-    // the phase kernels run column passes of 2 to 4 stages (run_batch sends
-    // products with 5 to the single-product kernels)
+    // the phase kernels run column passes of 2 to 4 stages (run_batch gives
+    // products planned with 5 a 4-stage pass or the single-product kernels)
     if (P.kn.split > 4) return PM_EUNSUPPORTED;
     int st = fill_product_launches(P, prods[i].A, prods[i].B, prods[i].C, ws + offs[i], &hp[i],
                                    true);
